@@ -1,0 +1,204 @@
+/*
+ * radsvd.h -- C ABI of the MI355X (gfx950) radial-SVD rotational image
+ * alignment library.
+ *
+ * Method: A. Rangan, "Radial-recombination for rigid rotational alignment of
+ * images and volumes" (arXiv 2202.07235).  Images A and targets B are given
+ * by their Fourier transforms sampled on a polar quadrature grid (section 2.3:
+ * radial nodes k_r with weights w_r for \int g(k) k dk, angles
+ * psi_j = 2 pi j / Q).  For every image/target pair, every translation
+ * delta_t of a small set, and every on-grid rotation gamma_m = 2 pi m / Q the
+ * library evaluates the landscape
+ *
+ *   X[a][b][t][m] = sum_{h<H} sum_j conj(Ar_h[a](psi_j)) Br_h^t[b](psi_{j-m})
+ *
+ * where Ar_h = sum_r U[r][h] eta_r Ahat(k_r, .) and
+ * Br_h^t = sum_r U[r][h] eta_r exp(-i k_r.delta_t) Bhat(k_r, .) are the
+ * principal image rings (section 3.2, eta_r = sqrt(w_r dpsi)), and U holds
+ * the leading H eigenvectors of the target-averaged kernel C (sections
+ * 3.3-3.4).  At H = K this is the polar quadrature of
+ * <Ahat, R_gamma T_delta Bhat> (section 2.2), i.e. (2 pi)^2 <A, R_gamma T_delta B>
+ * with the prefactor dropped as the paper does.  It is evaluated in two steps
+ * (section 2.4 / 3.3): a per-frequency contraction over h of the angular
+ * Fourier coefficients, then a length-Q FFT over the frequency q.
+ *
+ * Conventions
+ *   - Complex arrays are interleaved (re, im): complex128 when prec ==
+ *     RADSVD_FP64, else complex64 (the memory layout of torch.complex128/64).
+ *   - Polar samples are [n][K][Q], psi fastest.
+ *   - All device buffers are owned by the caller (the library never calls
+ *     hipMalloc).  Host arrays are read during the call only.
+ *   - Work is enqueued on the caller's stream (a hipStream_t passed as void*;
+ *     NULL = the default stream).  Calls do not synchronise the host.
+ *   - Every call validates all arguments before its first launch and returns
+ *     a status; it never aborts.  radsvd_last_error() describes the last
+ *     failure of the calling thread.  Asynchronous device faults surface as
+ *     RADSVD_ERR_DEVICE from the launch check or from a later call.
+ */
+#ifndef RADSVD_H
+#define RADSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RADSVD_OK = 0,
+    RADSVD_ERR_INVALID_ARG = 1,   /* a size, pointer or flag is out of range       */
+    RADSVD_ERR_UNSUPPORTED = 2,   /* valid, but not implemented for this shape/mode */
+    RADSVD_ERR_WORKSPACE = 3,     /* workspace missing, misaligned or too small     */
+    RADSVD_ERR_DEVICE = 4         /* a HIP call or kernel launch failed             */
+} radsvd_status;
+
+/* Arithmetic of the per-frequency contraction (the rest of the path is FP32,
+ * or FP64 for RADSVD_FP64; translation phases and the eigensolver are always
+ * FP64). */
+typedef enum {
+    RADSVD_FP64 = 0,    /* complex128 in, FP64 everywhere                         */
+    RADSVD_FP32 = 1,    /* FP32 products, FP32 accumulation                        */
+    RADSVD_BF16 = 2,    /* operands rounded to bf16, FP32 accumulation             */
+    RADSVD_BF16X3 = 3   /* operands split x = hi + mid + lo (bf16 each); 3 or 6    */
+                        /* bf16 cross products summed in FP32                      */
+} radsvd_precision;
+
+/* align_pairs output selection (bit flags). */
+enum {
+    RADSVD_OUT_BEST = 1,   /* best score and its (m, t) per pair                       */
+    RADSVD_OUT_LSE = 2,    /* log-sum-exp over (t, m) per pair, and over b per image   */
+    RADSVD_OUT_FULL = 4    /* the whole landscape X[a][b][t][m]                        */
+};
+
+typedef struct {
+    int K;                  /* radial rings, 2 <= K <= 128                              */
+    int Q;                  /* angles: even, Q = 2^a 3^b, 8 <= Q <= 512                 */
+    int H;                  /* rank (principal rings kept), 1 <= H <= min(K, 32)        */
+    int T;                  /* translations, 1 <= T <= 64                               */
+    const double *k;        /* host [K]: ring radii k_r (> 0)                           */
+    const double *w;        /* host [K]: radial weights w_r (> 0), sum g(k_r) w_r ~ \int g k dk */
+    const double *delta;    /* host [T][2]: translations (dx, dy), same length unit as 1/k */
+    int prec;               /* radsvd_precision                                         */
+    int hermitian;          /* 1: caller asserts Ahat(k, psi + pi) = conj(Ahat(k, psi)) */
+                            /*    for images and targets (real-space images); the library */
+                            /*    then uses only the frequencies q in [0, Q/2]          */
+    int products;           /* RADSVD_BF16X3 only: 3 (hi*hi + hi*mid + mid*hi) or 6     */
+                            /* (+ mid*mid + hi*lo + lo*hi); ignored otherwise            */
+} radsvd_problem;
+
+typedef struct radsvd_plan radsvd_plan;   /* opaque host-side metadata */
+
+/* Bytes of device workspace align_prepare needs for this problem and these
+ * counts (0 if the arguments are invalid; see radsvd_last_error). */
+size_t align_prepare_workspace(const radsvd_problem *prob, int n_img, int n_tgt);
+
+/*
+ * Precompute (paper section 3.5, operation-count items 1-3): the kernel C
+ * of the targets at delta = 0 (section 3.4, q = 0 excluded, ring weights
+ * sqrt(w_r w_r')), its FP64 eigendecomposition (descending eigenvalues, each
+ * eigenvector's largest-magnitude entry positive), and the principal rings of
+ * every image and of every target at every translation, transformed to
+ * angular frequency.
+ *
+ *   A_polar  device [n_img][K][Q] images  (complex128 for FP64, else complex64)
+ *   B_polar  device [n_tgt][K][Q] targets
+ *   U_in     device [K][H] FP64 row-major, or NULL.  When given, it replaces
+ *            the eigenvectors of C (columns should be orthonormal) and C is
+ *            not formed; the eigenvalues reported by align_get_U are then NaN.
+ *   ws       device workspace of ws_bytes >= align_prepare_workspace(),
+ *            256-byte aligned; it holds everything the plan refers to.
+ *   out      receives a new plan on RADSVD_OK (free with align_plan_destroy).
+ *
+ * Lifetime: ws, A_polar and B_polar must stay valid and unchanged until the
+ * last call enqueued with the plan has completed (the backward pass reads the
+ * polar samples).  Plans are immutable; calls on different streams may share
+ * one plan.  n_img, n_tgt in [1, 2^20].
+ */
+radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A_polar,
+                            int n_tgt, const void *B_polar, const double *U_in,
+                            void *ws, size_t ws_bytes, void *stream, radsvd_plan **out);
+
+/*
+ * Per-pair computation (section 3.5, items 4-5): for every pair (a, b) and
+ * translation t, the contraction over the principal rings at each angular
+ * frequency q followed by the FFT over q (section 3.3, steps 1 and 2), and an
+ * epilogue on chip:
+ *
+ *   RADSVD_OUT_BEST : best_score[a][b] = max_{t,m} Re X[a][b][t][m]  (f32),
+ *                     best_m[a][b], best_t[a][b] (int32) its location; the
+ *                     maximum-likelihood rotation of section 2.6 is
+ *                     gamma = 2 pi m / Q.  Ties go to the smallest t*Q + m; a
+ *                     pair whose landscape has a NaN gets NaN and -1, -1.
+ *   RADSVD_OUT_LSE  : lse_pair[a][b] = log sum_{t,m} exp(inv_sigma2 Re X)  (f32);
+ *                     if lse_img != NULL, lse_img[a] = log sum_b exp(lse_pair[a][b]).
+ *   RADSVD_OUT_FULL : X_full [n_img][n_tgt][T][Q] complex (plan's I/O type).
+ *
+ * Pointers of the modes not selected are ignored.  All outputs are device
+ * arrays, row-major.
+ */
+radsvd_status align_pairs(const radsvd_plan *plan, int out_flags, float inv_sigma2,
+                          float *best_score, int32_t *best_m, int32_t *best_t,
+                          float *lse_pair, float *lse_img, void *X_full, void *stream);
+
+/* Bytes of device scratch align_pairs_backward needs for this plan. */
+size_t align_backward_workspace(const radsvd_plan *plan);
+
+/*
+ * Backward pass of the soft-alignment loss L = sum_a grad_lse_img[a] lse_img[a]
+ * (lse_img as produced by align_pairs with the same inv_sigma2): writes
+ *   grad_B_polar device [n_tgt][K][Q] complex (plan's I/O type):
+ *                dL/dRe Bhat + i dL/dIm Bhat, every entry treated as free;
+ *   grad_U       device [K][H] FP64: dL/dU with U a free matrix (the
+ *                eigendecomposition is not differentiated).
+ * Either output may be NULL.  lse_img and grad_lse_img are device [n_img] f32.
+ * The contraction runs in FP32 for every precision except RADSVD_FP64.
+ * bwd_ws: device scratch of bwd_bytes >= align_backward_workspace(plan).
+ */
+radsvd_status align_pairs_backward(const radsvd_plan *plan, float inv_sigma2,
+                                   const float *lse_img, const float *grad_lse_img,
+                                   void *grad_B_polar, double *grad_U,
+                                   void *bwd_ws, size_t bwd_bytes, void *stream);
+
+/* Outputs of one job of a batched launch (RADSVD_OUT_BEST). */
+typedef struct {
+    float *best_score;      /* device [n_img][n_tgt] */
+    int32_t *best_m;        /* device [n_img][n_tgt] */
+    int32_t *best_t;        /* device [n_img][n_tgt] */
+} radsvd_job_out;
+
+/* Bytes of device scratch align_pairs_batched needs (job table and queue). */
+size_t align_batched_workspace(int n_jobs);
+
+/*
+ * Many independent alignment jobs (each prepared with its own plan: its own
+ * grid, rank, translations and counts) in one persistent launch with
+ * RADSVD_OUT_BEST outputs.  Every plan must use the same precision and be
+ * Hermitian.  Results are bitwise equal to one align_pairs call per job with
+ * the same tile choice.  The launch contains no hipMemsetAsync and can be
+ * captured in a HIP graph.
+ */
+radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs,
+                                  const radsvd_job_out *outs, void *batch_ws, size_t batch_bytes,
+                                  void *stream);
+
+/* Copy U (device [K][K] FP64, column h = eigenvector h) and the eigenvalues
+ * (device [K] FP64, descending) of C into caller buffers (either may be NULL).
+ * With a caller-supplied U_in only its H columns are defined. */
+radsvd_status align_get_U(const radsvd_plan *plan, double *U_dev, double *lambda_dev,
+                          void *stream);
+
+/* Kernel-tile selection for align_pairs / align_pairs_batched (autotuner hook).
+ * tile_b: targets per workgroup tile of the fast Hermitian path, 16 or 32
+ * (0 = library default).  Applies to later calls with this plan. */
+radsvd_status align_set_tile(radsvd_plan *plan, int tile_b);
+
+void align_plan_destroy(radsvd_plan *plan);
+
+/* Description of the last error of the calling thread ("" if none). */
+const char *radsvd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RADSVD_H */

@@ -1,0 +1,348 @@
+// C ABI of the radsvd library: argument validation (always before the first
+// launch), workspace carving, plan lifetime and error reporting.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.h"
+#include "internal.h"
+
+using namespace radsvd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+radsvd_status fail(radsvd_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+radsvd_status dev_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) return fail(RADSVD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return RADSVD_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+radsvd_status validate_problem(const radsvd_problem *pr) {
+    if (!pr) return fail(RADSVD_ERR_INVALID_ARG, "problem is NULL");
+    if (pr->K < 2 || pr->K > kMaxK) return fail(RADSVD_ERR_INVALID_ARG, "K=%d outside [2, %d]", pr->K, kMaxK);
+    if (pr->Q < 8 || pr->Q > kMaxQ || (pr->Q & 1) || !fft_size_ok(pr->Q))
+        return fail(RADSVD_ERR_INVALID_ARG, "Q=%d must be even, 2^a 3^b, in [8, %d]", pr->Q, kMaxQ);
+    const int hmax = pr->K < kMaxH ? pr->K : kMaxH;
+    if (pr->H < 1 || pr->H > hmax) return fail(RADSVD_ERR_INVALID_ARG, "H=%d outside [1, %d]", pr->H, hmax);
+    if (pr->T < 1 || pr->T > kMaxT) return fail(RADSVD_ERR_INVALID_ARG, "T=%d outside [1, %d]", pr->T, kMaxT);
+    if (!pr->k || !pr->w) return fail(RADSVD_ERR_INVALID_ARG, "k or w is NULL");
+    if (!pr->delta && pr->T != 1) return fail(RADSVD_ERR_INVALID_ARG, "delta is NULL with T=%d", pr->T);
+    for (int r = 0; r < pr->K; ++r) {
+        if (!(pr->k[r] > 0.0) || !isfinite(pr->k[r]))
+            return fail(RADSVD_ERR_INVALID_ARG, "k[%d] must be finite and > 0", r);
+        if (!(pr->w[r] > 0.0) || !isfinite(pr->w[r]))
+            return fail(RADSVD_ERR_INVALID_ARG, "w[%d] must be finite and > 0", r);
+    }
+    if (pr->delta)
+        for (int t = 0; t < 2 * pr->T; ++t)
+            if (!isfinite(pr->delta[t])) return fail(RADSVD_ERR_INVALID_ARG, "delta[%d] not finite", t);
+    if (pr->prec < RADSVD_FP64 || pr->prec > RADSVD_BF16X3)
+        return fail(RADSVD_ERR_INVALID_ARG, "prec=%d unknown", pr->prec);
+    if (pr->hermitian != 0 && pr->hermitian != 1)
+        return fail(RADSVD_ERR_INVALID_ARG, "hermitian must be 0 or 1");
+    if (pr->prec == RADSVD_BF16X3 && pr->products != 3 && pr->products != 6)
+        return fail(RADSVD_ERR_INVALID_ARG, "products=%d must be 3 or 6 for BF16X3", pr->products);
+    return RADSVD_OK;
+}
+
+struct Layout {
+    size_t off_k, off_eta, off_delta, off_phase, off_C, off_U, off_lam, off_ueta, off_rsum, off_gram,
+        off_Ag, off_Bg, off_Af, off_Bf, total;
+    size_t Af_bytes, Bf_bytes;
+    int nsplit, H8, nplanes, na_pad, nb_pad, Qc;
+    bool fast;
+};
+
+Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
+    Layout L{};
+    const int K = pr->K, Q = pr->Q, H = pr->H, T = pr->T;
+    const size_t R = (pr->prec == RADSVD_FP64) ? 8 : 4;
+    const size_t CX = 2 * R;
+    L.Qc = pr->hermitian ? Q / 2 + 1 : Q;
+    L.fast = pr->hermitian && pr->prec != RADSVD_FP64;
+    L.H8 = (H + 7) / 8 * 8;
+    L.nplanes = (pr->prec == RADSVD_BF16X3) ? (pr->products == 3 ? 2 : 3) : 1;
+    L.na_pad = (n_img + kFastTA - 1) / kFastTA * kFastTA;
+    L.nb_pad = (n_tgt + kFastTB - 1) / kFastTB * kFastTB;
+    const int tiles = (K + 63) / 64;
+    int ns = 1024 / (tiles * tiles);
+    if (ns > n_tgt) ns = n_tgt;
+    if (ns < 1) ns = 1;
+    L.nsplit = ns;
+    const int KP = (K + 1) & ~1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    L.off_k = take(K * 8);
+    L.off_eta = take(K * 8);
+    L.off_delta = take((size_t)T * 2 * 8);
+    L.off_phase = take((size_t)T * K * Q * CX);
+    L.off_C = take((size_t)K * K * 8);
+    L.off_U = take((size_t)K * K * 8);
+    L.off_lam = take((size_t)K * 8);
+    L.off_ueta = take((size_t)K * H * R);
+    L.off_rsum = take((size_t)n_tgt * K * 16);
+    size_t gram = (size_t)ns * K * K;
+    if (gram < (size_t)KP * KP) gram = (size_t)KP * KP;
+    L.off_gram = take(gram * 8);
+    L.off_Ag = take((size_t)n_img * L.Qc * H * CX);
+    L.off_Bg = take((size_t)n_tgt * T * L.Qc * H * CX);
+    if (L.fast) {
+        const size_t elem = (pr->prec == RADSVD_FP32) ? 4 : 2;
+        const size_t row = (size_t)L.nplanes * 2 * L.H8 * elem;
+        L.Af_bytes = (size_t)L.na_pad * L.Qc * row;
+        L.Bf_bytes = (size_t)T * L.nb_pad * L.Qc * row;
+        L.off_Af = take(L.Af_bytes);
+        L.off_Bf = take(L.Bf_bytes);
+    }
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *radsvd_last_error(void) { return g_err; }
+
+size_t align_prepare_workspace(const radsvd_problem *prob, int n_img, int n_tgt) {
+    g_err[0] = 0;
+    if (validate_problem(prob) != RADSVD_OK) return 0;
+    if (n_img < 1 || n_img > (1 << 20) || n_tgt < 1 || n_tgt > (1 << 20)) {
+        fail(RADSVD_ERR_INVALID_ARG, "n_img=%d / n_tgt=%d outside [1, 2^20]", n_img, n_tgt);
+        return 0;
+    }
+    return make_layout(prob, n_img, n_tgt).total;
+}
+
+radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A_polar, int n_tgt,
+                            const void *B_polar, const double *U_in, void *ws, size_t ws_bytes,
+                            void *stream, radsvd_plan **out) {
+    g_err[0] = 0;
+    radsvd_status st = validate_problem(prob);
+    if (st != RADSVD_OK) return st;
+    if (!out) return fail(RADSVD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_img < 1 || n_img > (1 << 20) || n_tgt < 1 || n_tgt > (1 << 20))
+        return fail(RADSVD_ERR_INVALID_ARG, "n_img=%d / n_tgt=%d outside [1, 2^20]", n_img, n_tgt);
+    if (!A_polar || !B_polar) return fail(RADSVD_ERR_INVALID_ARG, "A_polar or B_polar is NULL");
+    if (!aligned(A_polar, 16) || !aligned(B_polar, 16))
+        return fail(RADSVD_ERR_INVALID_ARG, "A_polar / B_polar must be 16-byte aligned");
+    if (U_in && !aligned(U_in, 8)) return fail(RADSVD_ERR_INVALID_ARG, "U_in must be 8-byte aligned");
+    const Layout L = make_layout(prob, n_img, n_tgt);
+    if (!ws) return fail(RADSVD_ERR_WORKSPACE, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(RADSVD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total)
+        return fail(RADSVD_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+
+    radsvd_plan *p = new (std::nothrow) radsvd_plan();
+    if (!p) return fail(RADSVD_ERR_DEVICE, "host allocation failed");
+    p->K = prob->K;
+    p->Q = prob->Q;
+    p->H = prob->H;
+    p->T = prob->T;
+    p->prec = prob->prec;
+    p->herm = prob->hermitian;
+    p->products = prob->prec == RADSVD_BF16X3 ? prob->products : 0;
+    p->n_img = n_img;
+    p->n_tgt = n_tgt;
+    p->M = prob->Q / 2;
+    p->Qc = L.Qc;
+    p->H8 = L.H8;
+    p->nplanes = L.nplanes;
+    p->na_pad = L.na_pad;
+    p->nb_pad = L.nb_pad;
+    p->user_U = U_in != nullptr;
+    p->tile_b = 0;
+    p->ws = reinterpret_cast<char *>(ws);
+    p->ws_bytes = ws_bytes;
+    p->A_polar = A_polar;
+    p->B_polar = B_polar;
+    char *w = p->ws;
+    p->d_k = reinterpret_cast<double *>(w + L.off_k);
+    p->d_eta = reinterpret_cast<double *>(w + L.off_eta);
+    p->d_delta = reinterpret_cast<double *>(w + L.off_delta);
+    p->phase = w + L.off_phase;
+    p->C = reinterpret_cast<double *>(w + L.off_C);
+    p->U = reinterpret_cast<double *>(w + L.off_U);
+    p->lam = reinterpret_cast<double *>(w + L.off_lam);
+    p->Ueta = w + L.off_ueta;
+    p->ringsum = reinterpret_cast<double *>(w + L.off_rsum);
+    p->gram_part = reinterpret_cast<double *>(w + L.off_gram);
+    p->gram_nsplit = L.nsplit;
+    p->Ag = w + L.off_Ag;
+    p->Bg = w + L.off_Bg;
+    p->Af = L.fast ? w + L.off_Af : nullptr;
+    p->Bf = L.fast ? w + L.off_Bf : nullptr;
+    p->Af_bytes = L.Af_bytes;
+    p->Bf_bytes = L.Bf_bytes;
+
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    GridArgs g;
+    memset(&g, 0, sizeof(g));
+    g.K = prob->K;
+    g.Q = prob->Q;
+    g.T = prob->T;
+    for (int r = 0; r < prob->K; ++r) {
+        g.k[r] = prob->k[r];
+        g.w[r] = prob->w[r];
+    }
+    for (int t = 0; t < prob->T; ++t) {
+        g.delta[t][0] = prob->delta ? prob->delta[2 * t] : 0.0;
+        g.delta[t][1] = prob->delta ? prob->delta[2 * t + 1] : 0.0;
+    }
+    hipError_t e = launch_setup(p, g, s);
+    if (e == hipSuccess) {
+        if (U_in) {
+            e = launch_user_U(p, U_in, s);
+            if (e == hipSuccess) e = launch_ueta(p, U_in, p->H, s);
+        } else {
+            e = launch_kernel_C(p, s);
+            if (e == hipSuccess) e = launch_eig(p, s);
+            if (e == hipSuccess) e = launch_ueta(p, p->U, p->K, s);
+        }
+    }
+    if (e == hipSuccess) e = launch_principal_rings(p, s);
+    if (e != hipSuccess) {
+        delete p;
+        return dev_check(e, "align_prepare launch");
+    }
+    *out = p;
+    return RADSVD_OK;
+}
+
+radsvd_status align_pairs(const radsvd_plan *p, int flags, float inv_sigma2, float *best_score,
+                          int32_t *best_m, int32_t *best_t, float *lse_pair, float *lse_img,
+                          void *X_full, void *stream) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    if (flags <= 0 || (flags & ~7)) return fail(RADSVD_ERR_INVALID_ARG, "out_flags=%d invalid", flags);
+    if ((flags & RADSVD_OUT_BEST) && (!best_score || !best_m || !best_t))
+        return fail(RADSVD_ERR_INVALID_ARG, "BEST output pointers must be non-NULL");
+    if ((flags & RADSVD_OUT_LSE) && !lse_pair)
+        return fail(RADSVD_ERR_INVALID_ARG, "LSE output lse_pair must be non-NULL");
+    if ((flags & RADSVD_OUT_LSE) && !isfinite(inv_sigma2))
+        return fail(RADSVD_ERR_INVALID_ARG, "inv_sigma2 must be finite");
+    if ((flags & RADSVD_OUT_FULL) && !X_full)
+        return fail(RADSVD_ERR_INVALID_ARG, "FULL output X_full must be non-NULL");
+    if ((flags & RADSVD_OUT_BEST) && (!aligned(best_score, 4) || !aligned(best_m, 4) || !aligned(best_t, 4)))
+        return fail(RADSVD_ERR_INVALID_ARG, "BEST outputs must be 4-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    const int fast_flags = flags & (RADSVD_OUT_BEST | RADSVD_OUT_LSE);
+    if (fast_flags && fast_path_supported(p, fast_flags)) {
+        e = launch_pairs_fast(p, fast_flags, inv_sigma2, best_score, best_m, best_t, lse_pair, s);
+        if (e == hipSuccess && (flags & RADSVD_OUT_FULL))
+            e = launch_pairs_generic(p, RADSVD_OUT_FULL, inv_sigma2, nullptr, nullptr, nullptr, nullptr,
+                                     X_full, s);
+    } else {
+        e = launch_pairs_generic(p, flags, inv_sigma2, best_score, best_m, best_t, lse_pair, X_full, s);
+    }
+    if (e == hipSuccess && (flags & RADSVD_OUT_LSE) && lse_img)
+        e = launch_lse_img(p->n_img, p->n_tgt, lse_pair, lse_img, s);
+    return dev_check(e, "align_pairs launch");
+}
+
+size_t align_backward_workspace(const radsvd_plan *p) {
+    g_err[0] = 0;
+    if (!p) {
+        fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+        return 0;
+    }
+    return backward_bytes(p);
+}
+
+radsvd_status align_pairs_backward(const radsvd_plan *p, float inv_sigma2, const float *lse_img,
+                                   const float *grad_lse_img, void *grad_B_polar, double *grad_U,
+                                   void *bwd_ws, size_t bwd_bytes, void *stream) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    if (!lse_img || !grad_lse_img) return fail(RADSVD_ERR_INVALID_ARG, "lse_img / grad_lse_img NULL");
+    if (!isfinite(inv_sigma2)) return fail(RADSVD_ERR_INVALID_ARG, "inv_sigma2 must be finite");
+    if (grad_B_polar && !aligned(grad_B_polar, 16))
+        return fail(RADSVD_ERR_INVALID_ARG, "grad_B_polar must be 16-byte aligned");
+    if (grad_U && !aligned(grad_U, 8)) return fail(RADSVD_ERR_INVALID_ARG, "grad_U must be 8-byte aligned");
+    const size_t need = backward_bytes(p);
+    if (need == 0) return fail(RADSVD_ERR_UNSUPPORTED, "backward not available for this plan");
+    if (!bwd_ws) return fail(RADSVD_ERR_WORKSPACE, "backward workspace is NULL");
+    if (!aligned(bwd_ws, 256)) return fail(RADSVD_ERR_WORKSPACE, "backward workspace must be 256-byte aligned");
+    if (bwd_bytes < need)
+        return fail(RADSVD_ERR_WORKSPACE, "backward workspace too small: %zu < %zu", bwd_bytes, need);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return dev_check(launch_backward(p, inv_sigma2, lse_img, grad_lse_img, grad_B_polar, grad_U, bwd_ws, s),
+                     "align_pairs_backward launch");
+}
+
+size_t align_batched_workspace(int n_jobs) {
+    g_err[0] = 0;
+    if (n_jobs < 1 || n_jobs > 4096) {
+        fail(RADSVD_ERR_INVALID_ARG, "n_jobs=%d outside [1, 4096]", n_jobs);
+        return 0;
+    }
+    return batched_bytes(n_jobs);
+}
+
+radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs, const radsvd_job_out *outs,
+                                  void *batch_ws, size_t batch_bytes, void *stream) {
+    g_err[0] = 0;
+    if (!plans || !outs) return fail(RADSVD_ERR_INVALID_ARG, "plans / outs is NULL");
+    if (n_jobs < 1 || n_jobs > 4096) return fail(RADSVD_ERR_INVALID_ARG, "n_jobs=%d outside [1, 4096]", n_jobs);
+    int prec = -1;
+    for (int i = 0; i < n_jobs; ++i) {
+        const radsvd_plan *p = plans[i];
+        if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plans[%d] is NULL", i);
+        if (!outs[i].best_score || !outs[i].best_m || !outs[i].best_t)
+            return fail(RADSVD_ERR_INVALID_ARG, "outs[%d] has a NULL pointer", i);
+        if (prec < 0) prec = p->prec;
+        if (p->prec != prec) return fail(RADSVD_ERR_INVALID_ARG, "plans differ in precision");
+        if (!fast_path_supported(p, RADSVD_OUT_BEST))
+            return fail(RADSVD_ERR_UNSUPPORTED, "plans[%d] is not on the fast Hermitian path", i);
+    }
+    const size_t need = batched_bytes(n_jobs);
+    if (!batch_ws) return fail(RADSVD_ERR_WORKSPACE, "batch workspace is NULL");
+    if (!aligned(batch_ws, 256)) return fail(RADSVD_ERR_WORKSPACE, "batch workspace must be 256-byte aligned");
+    if (batch_bytes < need) return fail(RADSVD_ERR_WORKSPACE, "batch workspace too small: %zu < %zu", batch_bytes, need);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return dev_check(launch_pairs_batched(plans, n_jobs, outs, batch_ws, s), "align_pairs_batched launch");
+}
+
+radsvd_status align_get_U(const radsvd_plan *p, double *U_dev, double *lambda_dev, void *stream) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (U_dev) e = hipMemcpyAsync(U_dev, p->U, (size_t)p->K * p->K * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && lambda_dev)
+        e = hipMemcpyAsync(lambda_dev, p->lam, (size_t)p->K * 8, hipMemcpyDeviceToDevice, s);
+    return dev_check(e, "align_get_U copy");
+}
+
+radsvd_status align_set_tile(radsvd_plan *p, int tile_b) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    if (!fast_tile_ok(tile_b)) return fail(RADSVD_ERR_INVALID_ARG, "tile_b=%d not available", tile_b);
+    p->tile_b = tile_b;
+    return RADSVD_OK;
+}
+
+void align_plan_destroy(radsvd_plan *p) { delete p; }
+
+}  // extern "C"

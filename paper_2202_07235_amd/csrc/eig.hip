@@ -1,0 +1,156 @@
+// FP64 symmetric eigendecomposition of the kernel C (K <= 128) in one
+// workgroup: parallel cyclic Jacobi with the round-robin ("circle") pair
+// schedule, so that each round applies K/2 disjoint plane rotations at once.
+// Paper section 3.3: the principal vectors are the eigenvectors of C, ordered
+// by eigenvalue (the Rayleigh-quotient maximisers).  Output convention:
+// eigenvalues descending; each eigenvector's entry of largest magnitude is
+// positive (first such entry on ties).
+#include <math.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace radsvd {
+
+__device__ inline double block_sum_1024(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    return t;
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, int K, int KP,
+                                                 double *__restrict__ V, double *__restrict__ U,
+                                                 double *__restrict__ lam, int max_sweeps) {
+    extern __shared__ double A[];   // [KP][KP + 1]
+    __shared__ int sp[kMaxK / 2], sq[kMaxK / 2];
+    __shared__ double sc[kMaxK / 2], ss[kMaxK / 2];
+    __shared__ double red[16];
+    __shared__ int srank[kMaxK];
+    const int ld = KP + 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < KP * KP; i += nt) {
+        const int r = i / KP, c = i - r * KP;
+        A[r * ld + c] = (r < K && c < K) ? C[r * K + c] : 0.0;
+        V[i] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    double part = 0.0;
+    for (int i = tid; i < KP * KP; i += nt) {
+        const int r = i / KP, c = i - r * KP;
+        part += A[r * ld + c] * A[r * ld + c];
+    }
+    const double fro = block_sum_1024(part, red);
+    const int npair = KP / 2;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        part = 0.0;
+        for (int i = tid; i < KP * KP; i += nt) {
+            const int r = i / KP, c = i - r * KP;
+            if (r != c) part += A[r * ld + c] * A[r * ld + c];
+        }
+        const double off = block_sum_1024(part, red);
+        if (!(off > 1e-32 * fro)) break;
+        for (int round = 0; round < KP - 1; ++round) {
+            if (tid < npair) {
+                int p, q;
+                if (tid == 0) {
+                    p = KP - 1;
+                    q = round;
+                } else {
+                    p = (round + tid) % (KP - 1);
+                    q = (round - tid + (KP - 1)) % (KP - 1);
+                }
+                const double apq = A[p * ld + q];
+                double c = 1.0, s = 0.0;
+                if (apq != 0.0) {
+                    const double theta = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+                    double t;
+                    if (fabs(theta) > 1e150) t = 0.5 / theta;
+                    else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                    c = 1.0 / sqrt(t * t + 1.0);
+                    s = t * c;
+                }
+                sp[tid] = p;
+                sq[tid] = q;
+                sc[tid] = c;
+                ss[tid] = s;
+            }
+            __syncthreads();
+            for (int i = tid; i < npair * KP; i += nt) {
+                const int k = i / KP, j = i - k * KP;
+                const double c = sc[k], s = ss[k];
+                if (s == 0.0) continue;
+                const int p = sp[k], q = sq[k];
+                const double a = A[p * ld + j], b = A[q * ld + j];
+                A[p * ld + j] = c * a - s * b;
+                A[q * ld + j] = s * a + c * b;
+            }
+            __syncthreads();
+            for (int i = tid; i < npair * KP; i += nt) {
+                const int k = i / KP, r = i - k * KP;
+                const double c = sc[k], s = ss[k];
+                if (s == 0.0) continue;
+                const int p = sp[k], q = sq[k];
+                const double a = A[r * ld + p], b = A[r * ld + q];
+                A[r * ld + p] = c * a - s * b;
+                A[r * ld + q] = s * a + c * b;
+                const double va = V[r * KP + p], vb = V[r * KP + q];
+                V[r * KP + p] = c * va - s * vb;
+                V[r * KP + q] = s * va + c * vb;
+            }
+            __syncthreads();
+        }
+    }
+    // rank by descending eigenvalue (ties: lower index first)
+    for (int i = tid; i < K; i += nt) {
+        const double di = A[i * ld + i];
+        int rank = 0;
+        for (int j = 0; j < K; ++j) {
+            const double dj = A[j * ld + j];
+            if (dj > di || (dj == di && j < i)) ++rank;
+        }
+        srank[i] = rank;
+        lam[rank] = di;
+    }
+    __syncthreads();
+    for (int i = tid; i < K * K; i += nt) {
+        const int r = i / K, src = i - r * K;
+        U[r * K + srank[src]] = V[r * KP + src];
+    }
+    __threadfence_block();
+    __syncthreads();
+    // sign: largest-magnitude entry of each column positive
+    for (int h = tid; h < K; h += nt) {
+        int piv = 0;
+        double best = -1.0;
+        for (int r = 0; r < K; ++r) {
+            const double v = fabs(U[r * K + h]);
+            if (v > best) {
+                best = v;
+                piv = r;
+            }
+        }
+        if (U[piv * K + h] < 0.0)
+            for (int r = 0; r < K; ++r) U[r * K + h] = -U[r * K + h];
+    }
+}
+
+hipError_t launch_eig(radsvd_plan *p, hipStream_t s) {
+    const int K = p->K;
+    const int KP = (K + 1) & ~1;
+    const size_t shmem = (size_t)KP * (KP + 1) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)k_jacobi,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    // gram_part doubles as the Jacobi rotation accumulator (KP*KP <= its size)
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), shmem, s, p->C, K, KP, p->gram_part, p->U,
+                       p->lam, 40);
+    return hipGetLastError();
+}
+
+}  // namespace radsvd

@@ -1,0 +1,288 @@
+// Precompute kernels: grid factors, translation phases, U*eta, and the
+// principal rings of every image and translated target, transformed to
+// angular frequency (paper section 3.2, principal image rings; section 2.3,
+// angular Fourier coefficients; section 3.5, precompute items).
+//
+// The recombination K -> H is applied in psi-space before the angular FFT:
+// both maps are linear and commute, and transforming H principal rings
+// instead of K rings cuts the FFT work by K/H.
+#include <math.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace radsvd {
+
+// ---------------------------------------------------------------------------
+// grid factors and translation phases, computed in FP64
+//   eta_r = sqrt(w_r dpsi)                      (section 2.5, ring rescaling)
+//   phi_t[r][j] = exp(-i k_r (dx cos psi_j + dy sin psi_j))
+//                 (transform of B(x - delta), section 2.1)
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_setup(GridArgs g, double *d_k, double *d_eta, double *d_delta, cx<R> *phase) {
+    const int K = g.K, Q = g.Q, T = g.T;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < K) {
+        d_k[gid] = g.k[gid];
+        d_eta[gid] = sqrt(g.w[gid] * (2.0 * M_PI / (double)Q));
+    }
+    if (gid < 2 * T) d_delta[gid] = (&g.delta[0][0])[gid];
+    const int total = T * K * Q;
+    for (int i = gid; i < total; i += gridDim.x * blockDim.x) {
+        const int j = i % Q;
+        const int r = (i / Q) % K;
+        const int t = i / (Q * K);
+        double s, c;
+        sincospi(2.0 * (double)j / (double)Q, &s, &c);
+        const double arg = g.k[r] * (g.delta[t][0] * c + g.delta[t][1] * s);
+        double ps, pc;
+        sincos(arg, &ps, &pc);
+        phase[i] = cx<R>{(R)pc, (R)(-ps)};
+    }
+}
+
+template <typename R>
+__global__ void k_ueta(const double *U, int ld, const double *eta, int K, int H, R *Ueta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < K * H) {
+        const int r = i / H, h = i - r * H;
+        Ueta[i] = (R)(U[(size_t)r * ld + h] * eta[r]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// principal rings + angular FFT
+//
+// One workgroup per (item n, translation t).  Phase 1 accumulates
+//   Y[h][j] = sum_r Ueta[r][h] * phi_t[r][j] * X[n][r][j]
+// in registers (each thread owns NI (h, j) outputs).  Phase 2 transforms
+// rows of Y in LDS:  y[h][q] = Q^{-1/2} sum_j Y[h][j] exp(-2 pi i q j / Q)
+// and writes q in [0, Qc) to
+//   generic layout  G[n][t][q][h]                      (cx<R>)
+//   fast layout     F[t][tile][q][n_in][plane][c][h8]  (FP32 or bf16 planes)
+// Items n >= n_real (tile padding) only write zeros to the fast layout.
+// ---------------------------------------------------------------------------
+template <typename R, int NI>
+__global__ __launch_bounds__(256) void k_rings(
+    const cx<R> *__restrict__ X, int n_real, int T, const cx<R> *__restrict__ phase,
+    const R *__restrict__ Ueta, int K, int Q, int H, int Qc, int HC, int FC,
+    cx<R> *__restrict__ G,                                       // may be null
+    void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes) {
+    extern __shared__ unsigned char smem_raw[];
+    const int n = blockIdx.x / T;
+    const int t = blockIdx.x - n * T;
+    const int tid = threadIdx.x;
+    const int nthreads = blockDim.x;
+    cx<R> *tw = reinterpret_cast<cx<R> *>(smem_raw);             // [Q]
+    cx<R> *work = tw + Q;                                         // phase 1: zbuf[Q] | Ueta[K*H]
+    cx<R> *zbuf = work;
+    R *ue = reinterpret_cast<R *>(work + Q);
+    const size_t planeElems = (size_t)2 * H8;
+    const size_t rowElems = planeElems * nplanes;
+    const int Mp1 = Q / 2 + 1;
+    const int f_q = (Qc == Q) ? Q : Mp1;
+    const int tile = n / f_tile, n_in = n - tile * f_tile;
+    auto fidx = [&](int q) -> size_t {
+        return ((((size_t)t * f_ntiles + tile) * f_q + q) * f_tile + n_in) * rowElems;
+    };
+
+    if (n >= n_real) {
+        if (F) {
+            const size_t cnt = (size_t)f_q * rowElems;
+            for (size_t i = tid; i < cnt; i += nthreads) {
+                const int q = (int)(i / rowElems);
+                const size_t e = i - (size_t)q * rowElems;
+                if (f_kind == 0) reinterpret_cast<float *>(F)[fidx(q) + e] = 0.f;
+                else reinterpret_cast<uint16_t *>(F)[fidx(q) + e] = 0;
+            }
+        }
+        return;
+    }
+
+    for (int i = tid; i < Q; i += nthreads) {
+        double s, c;
+        sincospi(-2.0 * (double)i / (double)Q, &s, &c);
+        tw[i] = cx<R>{(R)c, (R)s};
+    }
+    const FftPlan pl = fft_make_plan(Q);
+    const R scale = (R)(1.0 / sqrt((double)Q));
+    const cx<R> *Xn = X + (size_t)n * K * Q;
+    const cx<R> *ph = phase ? phase + (size_t)t * K * Q : nullptr;
+
+    for (int h0 = 0; h0 < H; h0 += HC) {
+        const int hc = min(HC, H - h0);
+        const int nout = hc * Q;
+        cx<R> acc[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc[i] = cx<R>{(R)0, (R)0};
+        __syncthreads();
+        for (int i = tid; i < K * hc; i += nthreads) {
+            const int r = i / hc, hh = i - r * hc;
+            ue[i] = Ueta[(size_t)r * H + h0 + hh];
+        }
+        for (int r = 0; r < K; ++r) {
+            __syncthreads();
+            for (int j = tid; j < Q; j += nthreads) {
+                cx<R> x = Xn[(size_t)r * Q + j];
+                zbuf[j] = ph ? cmul(x, ph[(size_t)r * Q + j]) : x;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int o = tid + i * nthreads;
+                if (o < nout) {
+                    const int hh = o / Q, j = o - hh * Q;
+                    const R u = ue[r * hc + hh];
+                    const cx<R> z = zbuf[j];
+                    acc[i].re += u * z.re;
+                    acc[i].im += u * z.im;
+                }
+            }
+        }
+        // phase 2: FFT rows in chunks of FC rows
+        for (int f0 = 0; f0 < hc; f0 += FC) {
+            const int fc = min(FC, hc - f0);
+            __syncthreads();
+            cx<R> *ybuf = work;
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int o = tid + i * nthreads;
+                if (o < nout) {
+                    const int hh = o / Q;
+                    if (hh >= f0 && hh < f0 + fc) ybuf[o - f0 * Q] = acc[i];
+                }
+            }
+            __syncthreads();
+            lds_fft_dif(ybuf, fc, Q, pl, tw);
+            // write q < Qc
+            for (int i = tid; i < Qc * fc; i += nthreads) {
+                const int q = i / fc, hh = i - q * fc;
+                const int h = h0 + f0 + hh;
+                cx<R> v = ybuf[hh * Q + fft_pos(q, pl)];
+                v.re *= scale;
+                v.im *= scale;
+                if (G) G[(((size_t)n * T + t) * Qc + q) * H + h] = v;
+                if (F) {
+                    const size_t base = fidx(q);
+                    if (f_kind == 0) {
+                        float *Fp = reinterpret_cast<float *>(F);
+                        Fp[base + h] = (float)v.re;
+                        Fp[base + H8 + h] = (float)v.im;
+                    } else {
+                        uint16_t *Fp = reinterpret_cast<uint16_t *>(F);
+                        uint16_t hr[3], hi_[3];
+                        split3_bf16((float)v.re, hr[0], hr[1], hr[2]);
+                        split3_bf16((float)v.im, hi_[0], hi_[1], hi_[2]);
+                        for (int pl_i = 0; pl_i < nplanes; ++pl_i) {
+                            Fp[base + pl_i * planeElems + h] = hr[pl_i];
+                            Fp[base + pl_i * planeElems + H8 + h] = hi_[pl_i];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // zero the padding columns h in [H, H8) of the fast layout
+    if (F && H8 > H) {
+        const int padw = H8 - H;
+        for (int i = tid; i < Qc * padw * 2 * nplanes; i += nthreads) {
+            int rem = i;
+            const int q = rem / (padw * 2 * nplanes);
+            rem -= q * (padw * 2 * nplanes);
+            const int pl_i = rem / (padw * 2);
+            rem -= pl_i * padw * 2;
+            const int c = rem / padw;
+            const int h = H + rem - c * padw;
+            const size_t off = fidx(q) + pl_i * planeElems + c * H8 + h;
+            if (f_kind == 0) reinterpret_cast<float *>(F)[off] = 0.f;
+            else reinterpret_cast<uint16_t *>(F)[off] = 0;
+        }
+    }
+}
+
+// caller-supplied U [K][H]: copied into columns 0..H-1 of the plan's U,
+// other columns zero, eigenvalues NaN (C is not formed).
+__global__ void k_user_U(const double *U_in, int K, int H, double *U, double *lam) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < K * K) {
+        const int r = i / K, h = i - r * K;
+        U[i] = h < H ? U_in[(size_t)r * H + h] : 0.0;
+    }
+    if (i < K) lam[i] = __builtin_nan("");
+}
+
+hipError_t launch_user_U(radsvd_plan *p, const double *U_in, hipStream_t s) {
+    const int n = p->K * p->K;
+    hipLaunchKernelGGL(k_user_U, dim3((n + 255) / 256), dim3(256), 0, s, U_in, p->K, p->H, p->U, p->lam);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(radsvd_plan *p, const GridArgs &g, hipStream_t s) {
+    const int total = p->T * p->K * p->Q;
+    int blocks = (total + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 4096) blocks = 4096;
+    if (p->prec == RADSVD_FP64)
+        hipLaunchKernelGGL(k_setup<double>, dim3(blocks), dim3(256), 0, s, g, p->d_k, p->d_eta,
+                           p->d_delta, reinterpret_cast<cx<double> *>(p->phase));
+    else
+        hipLaunchKernelGGL(k_setup<float>, dim3(blocks), dim3(256), 0, s, g, p->d_k, p->d_eta,
+                           p->d_delta, reinterpret_cast<cx<float> *>(p->phase));
+    return hipGetLastError();
+}
+
+hipError_t launch_ueta(radsvd_plan *p, const double *U_src, int ld, hipStream_t s) {
+    const int n = p->K * p->H;
+    const int blocks = (n + 255) / 256;
+    if (p->prec == RADSVD_FP64)
+        hipLaunchKernelGGL(k_ueta<double>, dim3(blocks), dim3(256), 0, s, U_src, ld, p->d_eta, p->K,
+                           p->H, reinterpret_cast<double *>(p->Ueta));
+    else
+        hipLaunchKernelGGL(k_ueta<float>, dim3(blocks), dim3(256), 0, s, U_src, ld, p->d_eta, p->K,
+                           p->H, reinterpret_cast<float *>(p->Ueta));
+    return hipGetLastError();
+}
+
+template <typename R, int NI>
+static hipError_t rings_side(radsvd_plan *p, const void *X, int n_real, int n_pad, int T,
+                             bool use_phase, void *G, void *F, int f_tile, hipStream_t s) {
+    const int Q = p->Q, K = p->K, H = p->H;
+    const int nthreads = 256;
+    int HC = (nthreads * NI) / Q;
+    if (HC > H) HC = H;
+    if (HC < 1) return hipErrorInvalidValue;
+    const size_t cxb = sizeof(cx<R>);
+    const size_t work1 = (size_t)Q * cxb + (size_t)K * HC * sizeof(R);
+    int FC = (int)(32768 / ((size_t)Q * cxb));
+    if (FC < 1) FC = 1;
+    if (FC > HC) FC = HC;
+    const size_t work2 = (size_t)FC * Q * cxb;
+    const size_t shmem = (size_t)Q * cxb + (work1 > work2 ? work1 : work2);
+    const int f_kind = (p->prec == RADSVD_FP32 || p->prec == RADSVD_FP64) ? 0 : 1;
+    const int f_ntiles = n_pad / f_tile;
+    const int items = (F ? n_pad : n_real) * T;
+    hipLaunchKernelGGL((k_rings<R, NI>), dim3(items), dim3(nthreads), shmem, s,
+                       reinterpret_cast<const cx<R> *>(X), n_real, T,
+                       use_phase ? reinterpret_cast<const cx<R> *>(p->phase) : nullptr,
+                       reinterpret_cast<const R *>(p->Ueta), K, Q, H, p->Qc, HC, FC,
+                       reinterpret_cast<cx<R> *>(G), F, f_kind, f_tile, f_ntiles, p->H8, p->nplanes);
+    return hipGetLastError();
+}
+
+hipError_t launch_principal_rings(radsvd_plan *p, hipStream_t s) {
+    hipError_t e;
+    if (p->prec == RADSVD_FP64) {
+        e = rings_side<double, 32>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, nullptr,
+                                   kFastTA, s);
+        if (e != hipSuccess) return e;
+        return rings_side<double, 32>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, nullptr,
+                                      kFastTB, s);
+    }
+    e = rings_side<float, 64>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, s);
+    if (e != hipSuccess) return e;
+    return rings_side<float, 64>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, p->Bf,
+                                 kFastTB, s);
+}
+
+}  // namespace radsvd

@@ -1,0 +1,159 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances.  FP64 path: 1e-12 relative (A11 metric).  FP32 path: every step
+rounds in FP32 (eps = 6e-8); the deepest chains are the K-term ring sum
+(K <= 128), two length-Q FFTs (log2 Q <= 9 stages each) and the 2H-term
+contraction, so the error relative to max|X| is a random-sign sum of
+O(K + 2H + 2 log2 Q) roundings of terms of size <= max|X|: sqrt(300) * 6e-8
+~ 1e-6; the bound used is 1e-5 (the spec bar for the split-precision
+path).  BF16 (one product): unit roundoff 2^-9 per operand -> 2^-8 relative
+per product, averaged over sums: 1e-2.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2202_07235_amd as rs
+import synth
+from tests._parity import argmax_agrees, host_inputs, oracle_landscape_for, rel_err, to_device
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-5, "bf16": 2e-2}
+
+
+def _run(cfg, seed, precision, out="best+lse+full", products=3, U=None, inv_s2=None):
+    P = synth.make_problem(cfg, seed)
+    A, B = to_device(P, precision)
+    plan = rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision=precision, hermitian=P.hermitian,
+                   products=products, U=U)
+    A_h, B_h = host_inputs(A, B)
+    Xor, Uh, lam = oracle_landscape_for(plan, A_h, B_h, P)
+    if inv_s2 is None:
+        inv_s2 = 4.0 / np.abs(Xor).max()
+    o = plan.pairs(out, inv_sigma2=inv_s2)
+    torch.cuda.synchronize()
+    return P, plan, A_h, B_h, Xor, Uh, lam, o, inv_s2
+
+
+def test_tiny_fp64_full_landscape_and_U():
+    cfg = synth.config("tiny")
+    P, plan, A_h, B_h, Xor, Uh, lam, o, s2 = _run(cfg, 1001, "fp64")
+    X = o["X"].cpu().numpy()
+    assert rel_err(X, Xor) <= TOL["fp64"]
+    sc, m, t = oracle.best(Xor)
+    assert np.array_equal(o["best_m"].cpu().numpy(), m)
+    assert np.array_equal(o["best_t"].cpu().numpy(), t)
+    assert np.allclose(o["best_score"].cpu().numpy(), sc, rtol=1e-6, atol=1e-6 * np.abs(sc).max())
+    lp, li = oracle.lse(Xor, s2)
+    assert np.allclose(o["lse_pair"].cpu().numpy(), lp, rtol=1e-6, atol=1e-6)
+    assert np.allclose(o["lse_img"].cpu().numpy(), li, rtol=1e-6, atol=1e-6)
+    # kernel C and its eigenvectors against the oracle's
+    Cor = oracle.kernel_C(B_h, P.w, cfg.Q)
+    Uor, lam_or = oracle.principal_vectors(Cor)
+    assert np.allclose(lam, lam_or, rtol=0, atol=1e-12 * lam_or[0])
+    gaps = np.abs(np.diff(lam_or)) > 1e-8 * lam_or[0]
+    for h in range(cfg.K):
+        if (h == 0 or gaps[h - 1]) and (h == cfg.K - 1 or gaps[h]):
+            assert np.allclose(Uh[:, h], Uor[:, h], atol=1e-9), h
+    # the grid-rotated copies are recovered (targets are rotated copies + 10% noise)
+    src, shift = P.truth["src"], P.truth["shift"]
+    for b in range(cfg.n_tgt):
+        assert m[src[b], b] == (-shift[b]) % cfg.Q
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16"])
+def test_generic_hermitian_paths(precision):
+    # ragged counts (not multiples of the tiles), 9 translations, radix-3 Q
+    cfg = synth.config("fp32", N=48, K=24, Q=96, n_img=5, n_tgt=7, T=9, H=10)
+    P, plan, A_h, B_h, Xor, Uh, lam, o, s2 = _run(cfg, 1002, precision)
+    X = o["X"].cpu().numpy()
+    e = rel_err(X, Xor)
+    print(f"{precision}: rel err {e:.3e}")
+    assert e <= TOL[precision]
+    m, t = o["best_m"].cpu().numpy(), o["best_t"].cpu().numpy()
+    assert argmax_agrees(Xor, m, t, e).all()
+    sc = o["best_score"].cpu().numpy()
+    ref = np.take_along_axis(Xor.real.reshape(5, 7, -1), (t * cfg.Q + m)[..., None], axis=-1)[..., 0]
+    assert np.all(np.abs(sc - ref) <= 2 * e * np.abs(Xor).max())
+    lp, li = oracle.lse(Xor, s2)
+    assert np.allclose(o["lse_pair"].cpu().numpy(), lp, rtol=0, atol=max(1e-4, 8 * e * 4))
+
+
+def test_non_hermitian_fp32_full():
+    P = synth.make_problem(synth.config("tiny", n_img=3, n_tgt=4, H=9), 1003)
+    delta = np.array([[0, 0], [0.01, 0], [0, -0.02], [0.03, 0.01]])
+    A, B = to_device(P, "fp32")
+    plan = rs.Plan(A, B, P.k, P.w, delta, 9, precision="fp32", hermitian=False)
+    A_h, B_h = host_inputs(A, B)
+    U, _ = plan.U_lambda()
+    Xor = oracle.landscape(A_h, B_h, U.cpu().numpy(), 9, P.k, P.w, delta)
+    o = plan.pairs("full+best")
+    assert rel_err(o["X"].cpu().numpy(), Xor) <= TOL["fp32"]
+
+
+def test_user_supplied_U():
+    cfg = synth.config("fp32", N=32, K=16, Q=64, n_img=4, n_tgt=5, T=1, H=5)
+    P = synth.make_problem(cfg, 1004)
+    rng = np.random.default_rng(0)
+    Uq, _ = np.linalg.qr(rng.standard_normal((16, 16)))
+    Uin = torch.tensor(np.ascontiguousarray(Uq[:, :5]))
+    A, B = to_device(P, "fp64")
+    plan = rs.Plan(A, B, P.k, P.w, P.delta, 5, precision="fp64", hermitian=True, U=Uin)
+    A_h, B_h = host_inputs(A, B)
+    Xor = oracle.landscape(A_h, B_h, Uq, 5, P.k, P.w, P.delta)
+    o = plan.pairs("full")
+    assert rel_err(o["X"].cpu().numpy(), Xor) <= TOL["fp64"]
+    U, lam = plan.U_lambda()
+    assert torch.isnan(lam).all()
+
+
+def test_nan_input_gives_nan_score_and_minus_one():
+    cfg = synth.config("fp32", N=32, K=16, Q=64, n_img=2, n_tgt=3, T=1, H=4)
+    P = synth.make_problem(cfg, 1005)
+    A, B = to_device(P, "fp32")
+    U = torch.eye(16, dtype=torch.float64)[:, :4].contiguous()
+    A[1, 3, 7] = complex(float("nan"), 0.0)
+    plan = rs.Plan(A, B, P.k, P.w, P.delta, 4, precision="fp32", U=U)
+    o = plan.pairs("best")
+    sc, m, t = (o[k].cpu().numpy() for k in ("best_score", "best_m", "best_t"))
+    assert np.isnan(sc[1]).all() and (m[1] == -1).all() and (t[1] == -1).all()
+    assert np.isfinite(sc[0]).all() and (m[0] >= 0).all()
+
+
+def test_single_pair_and_degenerate_sizes():
+    cfg = synth.config("fp32", N=32, K=2, Q=8, n_img=1, n_tgt=1, T=1, H=1)
+    P, plan, A_h, B_h, Xor, Uh, lam, o, s2 = _run(cfg, 1006, "fp32")
+    assert rel_err(o["X"].cpu().numpy(), Xor) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_all_negative_landscape(precision):
+    """B = -A with A dominated by a centred (rotation-invariant) blob: every
+    X[m] is negative; the best must still be a valid in-range index."""
+    N, K, Q = 32, 16, 64
+    rng = np.random.default_rng(5)
+    mu, s, c = synth.blob_params(rng, 3, 4)
+    mu[:, 0] = 0.0
+    s[:, 0] = 0.05
+    c[:, 0] = 10.0
+    k, w = synth.gl_grid(N, K)
+    A0 = synth.polar_ft(mu, s, c, k, Q)
+    delta = synth.translation_grid(1, N)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    A = A0.to("cuda", dt).contiguous()
+    B = (-A0).to("cuda", dt).contiguous()
+    plan = rs.Plan(A, B, k, w, delta, 6, precision=precision, hermitian=True)
+    A_h, B_h = host_inputs(A, B)
+    U, _ = plan.U_lambda()
+    Xor = oracle.landscape(A_h, B_h, U.cpu().numpy(), 6, k, w, delta)
+    assert (Xor.real < 0).all()
+    o = plan.pairs("best")
+    m, t, sc = o["best_m"].cpu().numpy(), o["best_t"].cpu().numpy(), o["best_score"].cpu().numpy()
+    assert ((m >= 0) & (m < Q) & (t == 0)).all()
+    ref = Xor.real.max(axis=(2, 3))
+    assert np.all(np.abs(sc - ref) <= 1e-5 * np.abs(Xor).max())

@@ -130,7 +130,7 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
  *                     maximum-likelihood rotation of section 2.6 is
  *                     gamma = 2 pi m / Q.  Ties go to the smallest t*Q + m; a
  *                     pair whose landscape has a NaN gets NaN and -1, -1.
- *   RADSVD_OUT_LSE  : lse_pair[a][b] = log sum_{t,m} exp(inv_sigma2 Re X)  (f32);
+ *   RADSVD_OUT_LSE  : lse_pair[a][b] = log sum_{t,m} exp(inv_sigma2 Re X)  (f32, inv_sigma2 > 0);
  *                     if lse_img != NULL, lse_img[a] = log sum_b exp(lse_pair[a][b]).
  *   RADSVD_OUT_FULL : X_full [n_img][n_tgt][T][Q] complex (plan's I/O type).
  *

@@ -239,8 +239,8 @@ radsvd_status align_pairs(const radsvd_plan *p, int flags, float inv_sigma2, flo
         return fail(RADSVD_ERR_INVALID_ARG, "BEST output pointers must be non-NULL");
     if ((flags & RADSVD_OUT_LSE) && !lse_pair)
         return fail(RADSVD_ERR_INVALID_ARG, "LSE output lse_pair must be non-NULL");
-    if ((flags & RADSVD_OUT_LSE) && !isfinite(inv_sigma2))
-        return fail(RADSVD_ERR_INVALID_ARG, "inv_sigma2 must be finite");
+    if ((flags & RADSVD_OUT_LSE) && !(inv_sigma2 > 0.f && isfinite(inv_sigma2)))
+        return fail(RADSVD_ERR_INVALID_ARG, "inv_sigma2 must be finite and > 0");
     if ((flags & RADSVD_OUT_FULL) && !X_full)
         return fail(RADSVD_ERR_INVALID_ARG, "FULL output X_full must be non-NULL");
     if ((flags & RADSVD_OUT_BEST) && (!aligned(best_score, 4) || !aligned(best_m, 4) || !aligned(best_t, 4)))
@@ -276,7 +276,8 @@ radsvd_status align_pairs_backward(const radsvd_plan *p, float inv_sigma2, const
     g_err[0] = 0;
     if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
     if (!lse_img || !grad_lse_img) return fail(RADSVD_ERR_INVALID_ARG, "lse_img / grad_lse_img NULL");
-    if (!isfinite(inv_sigma2)) return fail(RADSVD_ERR_INVALID_ARG, "inv_sigma2 must be finite");
+    if (!(inv_sigma2 > 0.f && isfinite(inv_sigma2)))
+        return fail(RADSVD_ERR_INVALID_ARG, "inv_sigma2 must be finite and > 0");
     if (grad_B_polar && !aligned(grad_B_polar, 16))
         return fail(RADSVD_ERR_INVALID_ARG, "grad_B_polar must be 16-byte aligned");
     if (grad_U && !aligned(grad_U, 8)) return fail(RADSVD_ERR_INVALID_ARG, "grad_U must be 8-byte aligned");

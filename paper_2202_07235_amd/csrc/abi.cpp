@@ -62,7 +62,7 @@ radsvd_status validate_problem(const radsvd_problem *pr) {
 
 struct Layout {
     size_t off_k, off_eta, off_delta, off_phase, off_C, off_U, off_lam, off_ueta, off_rsum, off_gram,
-        off_Ag, off_Bg, off_Af, off_Bf, total;
+        off_Ag, off_Bg, off_Af, off_Bf, off_log, total;
     size_t Af_bytes, Bf_bytes;
     int nsplit, H8, nplanes, na_pad, nb_pad, Qc;
     bool fast;
@@ -100,16 +100,18 @@ Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
     L.off_lam = take((size_t)K * 8);
     L.off_ueta = take((size_t)K * H * R);
     L.off_rsum = take((size_t)n_tgt * K * 16);
-    size_t gram = (size_t)ns * K * K;
-    if (gram < (size_t)KP * KP) gram = (size_t)KP * KP;
-    L.off_gram = take(gram * 8);
+    (void)KP;
+    L.off_gram = take((size_t)ns * K * K * 8);
+    L.off_log = take(eig_log_bytes(K));
     L.off_Ag = take((size_t)n_img * L.Qc * H * CX);
     L.off_Bg = take((size_t)n_tgt * T * L.Qc * H * CX);
     if (L.fast) {
         const size_t elem = (pr->prec == RADSVD_FP32) ? 4 : 2;
-        const size_t row = (size_t)L.nplanes * 2 * L.H8 * elem;
-        L.Af_bytes = (size_t)L.na_pad * L.Qc * row;
-        L.Bf_bytes = (size_t)T * L.nb_pad * L.Qc * row;
+        // image rows carry [re | im | -im] per plane, target rows [re | im]
+        const size_t rowA = (size_t)L.nplanes * 3 * L.H8 * elem;
+        const size_t rowB = (size_t)L.nplanes * 2 * L.H8 * elem;
+        L.Af_bytes = (size_t)L.na_pad * L.Qc * rowA;
+        L.Bf_bytes = (size_t)T * L.nb_pad * L.Qc * rowB;
         L.off_Af = take(L.Af_bytes);
         L.off_Bf = take(L.Bf_bytes);
     }
@@ -188,6 +190,7 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
     p->ringsum = reinterpret_cast<double *>(w + L.off_rsum);
     p->gram_part = reinterpret_cast<double *>(w + L.off_gram);
     p->gram_nsplit = L.nsplit;
+    p->eig_log = w + L.off_log;
     p->Ag = w + L.off_Ag;
     p->Bg = w + L.off_Bg;
     p->Af = L.fast ? w + L.off_Af : nullptr;

@@ -5,12 +5,21 @@
 // by eigenvalue (the Rayleigh-quotient maximisers).  Output convention:
 // eigenvalues descending; each eigenvector's entry of largest magnitude is
 // positive (first such entry on ties).
+//
+// Phase 1 rotates C (in LDS) to diagonal form and records every round's
+// rotations in a global log; phase 2 replays the log on V = I (in LDS, one
+// row per thread group), so neither phase waits on global-memory round trips.
 #include <math.h>
 
 #include "common.h"
 #include "internal.h"
 
 namespace radsvd {
+
+struct Rot {
+    int p, q;
+    double c, s;
+};
 
 __device__ inline double block_sum_1024(double v, double *red) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -25,19 +34,23 @@ __device__ inline double block_sum_1024(double v, double *red) {
 }
 
 __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, int K, int KP,
-                                                 double *__restrict__ V, double *__restrict__ U,
-                                                 double *__restrict__ lam, int max_sweeps) {
-    extern __shared__ double A[];   // [KP][KP + 1]
+                                                 Rot *__restrict__ log, int max_sweeps,
+                                                 double *__restrict__ U, double *__restrict__ lam) {
+    extern __shared__ double sm[];   // phase 1: A [KP][KP+1]; phase 2: V [KP][KP+1]
     __shared__ int sp[kMaxK / 2], sq[kMaxK / 2];
     __shared__ double sc[kMaxK / 2], ss[kMaxK / 2];
     __shared__ double red[16];
+    __shared__ double sdiag[kMaxK];
     __shared__ int srank[kMaxK];
+    __shared__ int nrounds_s;
+    __shared__ int any_rot;
     const int ld = KP + 1;
     const int tid = threadIdx.x, nt = blockDim.x;
+    const int npair = KP / 2;
+    double *A = sm;
     for (int i = tid; i < KP * KP; i += nt) {
         const int r = i / KP, c = i - r * KP;
         A[r * ld + c] = (r < K && c < K) ? C[r * K + c] : 0.0;
-        V[i] = (r == c) ? 1.0 : 0.0;
     }
     __syncthreads();
     double part = 0.0;
@@ -46,7 +59,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
         part += A[r * ld + c] * A[r * ld + c];
     }
     const double fro = block_sum_1024(part, red);
-    const int npair = KP / 2;
+    int nrounds = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         part = 0.0;
         for (int i = tid; i < KP * KP; i += nt) {
@@ -54,7 +67,9 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
             if (r != c) part += A[r * ld + c] * A[r * ld + c];
         }
         const double off = block_sum_1024(part, red);
-        if (!(off > 1e-32 * fro)) break;
+        // off-diagonal mass at the rounding floor: converged
+        if (!(off > 1e-28 * fro)) break;
+        if (tid == 0) any_rot = 0;
         for (int round = 0; round < KP - 1; ++round) {
             if (tid < npair) {
                 int p, q;
@@ -66,19 +81,22 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
                     q = (round - tid + (KP - 1)) % (KP - 1);
                 }
                 const double apq = A[p * ld + q];
+                const double app = A[p * ld + p], aqq = A[q * ld + q];
                 double c = 1.0, s = 0.0;
-                if (apq != 0.0) {
-                    const double theta = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+                if (apq != 0.0 && fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+                    const double theta = (aqq - app) / (2.0 * apq);
                     double t;
                     if (fabs(theta) > 1e150) t = 0.5 / theta;
                     else t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
                     c = 1.0 / sqrt(t * t + 1.0);
                     s = t * c;
+                    any_rot = 1;
                 }
                 sp[tid] = p;
                 sq[tid] = q;
                 sc[tid] = c;
                 ss[tid] = s;
+                log[(size_t)nrounds * npair + tid] = Rot{p, q, c, s};
             }
             __syncthreads();
             for (int i = tid; i < npair * KP; i += nt) {
@@ -99,45 +117,76 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
                 const double a = A[r * ld + p], b = A[r * ld + q];
                 A[r * ld + p] = c * a - s * b;
                 A[r * ld + q] = s * a + c * b;
-                const double va = V[r * KP + p], vb = V[r * KP + q];
-                V[r * KP + p] = c * va - s * vb;
-                V[r * KP + q] = s * va + c * vb;
             }
             __syncthreads();
+            ++nrounds;
         }
+        if (!any_rot) break;   // every off-diagonal entry negligible against its diagonal pair
+    }
+    for (int i = tid; i < K; i += nt) sdiag[i] = A[i * ld + i];
+    if (tid == 0) nrounds_s = nrounds;
+    __threadfence_block();
+    __syncthreads();
+    nrounds = nrounds_s;
+    // phase 2: V = product of the recorded rotations, applied to the identity
+    double *V = sm;
+    for (int i = tid; i < KP * KP; i += nt) {
+        const int r = i / KP, c = i - r * KP;
+        V[r * ld + c] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int rd = 0; rd < nrounds; ++rd) {
+        if (tid < npair) {
+            const Rot g = log[(size_t)rd * npair + tid];
+            sp[tid] = g.p;
+            sq[tid] = g.q;
+            sc[tid] = g.c;
+            ss[tid] = g.s;
+        }
+        __syncthreads();
+        for (int i = tid; i < npair * KP; i += nt) {
+            const int k = i / KP, r = i - k * KP;
+            const double c = sc[k], s = ss[k];
+            if (s == 0.0) continue;
+            const int p = sp[k], q = sq[k];
+            const double a = V[r * ld + p], b = V[r * ld + q];
+            V[r * ld + p] = c * a - s * b;
+            V[r * ld + q] = s * a + c * b;
+        }
+        __syncthreads();
     }
     // rank by descending eigenvalue (ties: lower index first)
     for (int i = tid; i < K; i += nt) {
-        const double di = A[i * ld + i];
+        const double di = sdiag[i];
         int rank = 0;
         for (int j = 0; j < K; ++j) {
-            const double dj = A[j * ld + j];
+            const double dj = sdiag[j];
             if (dj > di || (dj == di && j < i)) ++rank;
         }
         srank[i] = rank;
         lam[rank] = di;
     }
     __syncthreads();
-    for (int i = tid; i < K * K; i += nt) {
-        const int r = i / K, src = i - r * K;
-        U[r * K + srank[src]] = V[r * KP + src];
-    }
-    __threadfence_block();
-    __syncthreads();
-    // sign: largest-magnitude entry of each column positive
-    for (int h = tid; h < K; h += nt) {
+    // sign: largest-magnitude entry of each column positive; write U
+    for (int src = tid; src < K; src += nt) {
         int piv = 0;
         double best = -1.0;
         for (int r = 0; r < K; ++r) {
-            const double v = fabs(U[r * K + h]);
+            const double v = fabs(V[r * ld + src]);
             if (v > best) {
                 best = v;
                 piv = r;
             }
         }
-        if (U[piv * K + h] < 0.0)
-            for (int r = 0; r < K; ++r) U[r * K + h] = -U[r * K + h];
+        const double sgn = V[piv * ld + src] < 0.0 ? -1.0 : 1.0;
+        const int h = srank[src];
+        for (int r = 0; r < K; ++r) U[r * K + h] = sgn * V[r * ld + src];
     }
+}
+
+size_t eig_log_bytes(int K) {
+    const int KP = (K + 1) & ~1;
+    return (size_t)kEigMaxSweeps * (KP - 1) * (KP / 2) * sizeof(Rot);
 }
 
 hipError_t launch_eig(radsvd_plan *p, hipStream_t s) {
@@ -147,9 +196,8 @@ hipError_t launch_eig(radsvd_plan *p, hipStream_t s) {
     hipError_t e = hipFuncSetAttribute((const void *)k_jacobi,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    // gram_part doubles as the Jacobi rotation accumulator (KP*KP <= its size)
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), shmem, s, p->C, K, KP, p->gram_part, p->U,
-                       p->lam, 40);
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), shmem, s, p->C, K, KP,
+                       reinterpret_cast<Rot *>(p->eig_log), kEigMaxSweeps, p->U, p->lam);
     return hipGetLastError();
 }
 

@@ -4,7 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include "../../include/radsvd.h"
+#include "radsvd.h"
 
 namespace radsvd {
 
@@ -12,6 +12,7 @@ constexpr int kMaxK = 128;
 constexpr int kMaxQ = 512;
 constexpr int kMaxH = 32;
 constexpr int kMaxT = 64;
+constexpr int kEigMaxSweeps = 40;
 
 // Grid description passed by value to the setup kernel (fits the 4 KB
 // kernel-argument limit).
@@ -50,6 +51,7 @@ struct radsvd_plan {
     void *Ueta;                       // [K][H] R : U[r][h] * eta_r
     double *ringsum;                  // [n_tgt][K] complex FP64
     double *gram_part;                // [nsplit][K][K]
+    void *eig_log;                    // Jacobi rotation log
     int gram_nsplit;
     void *Ag;                         // [n_img][Qc][H] cx<R>        generic operands
     void *Bg;                         // [n_tgt][T][Qc][H] cx<R>
@@ -69,6 +71,7 @@ hipError_t launch_principal_rings(radsvd_plan *p, hipStream_t s);
 hipError_t launch_kernel_C(radsvd_plan *p, hipStream_t s);
 // eig.hip
 hipError_t launch_eig(radsvd_plan *p, hipStream_t s);
+size_t eig_log_bytes(int K);
 // pairs_generic.hip
 hipError_t launch_pairs_generic(const radsvd_plan *p, int flags, float inv_s2, float *best_score,
                                 int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full,

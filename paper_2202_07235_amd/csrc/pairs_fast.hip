@@ -216,9 +216,7 @@ struct Args {
     int n_img, n_tgt, T;
     int nTA, nTB;              // tile counts
     int H8;
-    int rowElems;              // elements per (row) = nplanes * 2 * H8
-    int nprod;                 // split products (bf16) ; unused for FP32
-    int planeA[6], planeB[6];  // plane of each product term
+    int nplanes;
     int flags;
     float inv_s2;
     float *best_score;
@@ -241,228 +239,306 @@ __device__ __forceinline__ void tile_of(int wg, int nwg, int nTA, int nTB, int &
     tb = in_band / rows;
 }
 
-template <int Q, bool BF16, int MODE>
+// Contraction precision of the fused kernel.
+//   KIND 0: FP32 operands, v_mfma_f32_16x16x4_f32; NB = H8/8 chunks of 4 h per lane
+//   KIND 1: bf16 (one product)                        NB = ceil(H8/16) chunks of 8 h
+//   KIND 2: split bf16, products hi*hi, hi*mid, mid*hi
+//   KIND 3: split bf16, + mid*mid, hi*lo, lo*hi
+template <int KIND>
+struct Prec {
+    static constexpr int NPL = KIND == 0 ? 1 : (KIND == 3 ? 3 : (KIND == 2 ? 2 : 1));   // planes loaded
+    static constexpr int NPROD = KIND == 3 ? 6 : (KIND == 2 ? 3 : 1);
+    static constexpr int pa(int p) { return p == 2 ? 1 : (p == 3 ? 1 : (p == 5 ? 2 : 0)); }   // A plane
+    static constexpr int pb(int p) { return p == 1 ? 1 : (p == 3 ? 1 : (p == 4 ? 2 : 0)); }   // B plane
+};
+
+template <int KIND, int NB>
+struct Frag {
+    u32x4 a[Prec<KIND>::NPL][NB];
+    u32x4 b[Prec<KIND>::NPL][NB];
+};
+
+template <int Q, int KIND, int NB>
 __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
     constexpr int M = Q / 2;
-    constexpr int L = M / 2;        // per-lane FFT length (complex)
-    constexpr int NRF = M / 8;      // full rounds of 8 frequencies; q = M handled last
-    static_assert(M % 8 == 0, "Q must be a multiple of 16");
+    constexpr int L = M / 2;          // Z values per lane
+    constexpr int LH = L / 2;         // in registers; the other LH in LDS
+    constexpr int NRP = M / 16;       // paired rounds: q in [8R, 8R+8) with M - q
+    constexpr bool BF = KIND != 0;
+    using PR = Prec<KIND>;
+    static_assert(M % 16 == 0, "Q must be a multiple of 32");
 
-    __shared__ cx<float> stage[2][8][128];
+    extern __shared__ unsigned char smem_raw[];
+    cx<float> *stage = reinterpret_cast<cx<float> *>(smem_raw);   // [16][128]
+    cx<float> *upper = stage + 16 * 128;                          // [LH][256]
 
     const int tid = threadIdx.x;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wavefront (uniform)
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int l = tid & 63;
-    const int e = l >> 5;           // 0: even-k lane, 1: odd-k lane
-    const int P = 32 * w + (l & 31);// pair within the tile
+    const int e = l >> 5;               // 0: even-k lane, 1: odd-k lane
+    const int P = 32 * w + (l & 31);    // pair within the tile
     const int pa = P >> 4, pb = P & 15;
+    const bool do_best = args.flags & RADSVD_OUT_BEST;
+    const bool do_lse = args.flags & RADSVD_OUT_LSE;
 
     int ta, tb;
     tile_of(blockIdx.x, gridDim.x, args.nTA, args.nTB, ta, tb);
 
     // ---- MFMA operand roles of this lane ----
-    const int g = l >> 4;           // k-group of the MFMA operand
-    const int i16 = l & 15;         // row (A) / column (B) of the MFMA operand
+    // image rows: per plane [re | im | -im] (H8 each); target rows: per plane [re | im]
+    const int g = l >> 4, i16 = l & 15;
     const int H8 = args.H8;
-    const int rowE = args.rowElems;
-    const int esz = BF16 ? 2 : 4;
+    constexpr int esz = BF ? 2 : 4;
     const int ai = i16 >> 1, rt = i16 & 1;
-    // BF16: lane covers 8 h-values: part c = g >> 1, h block (g & 1) (+ 2 * hb_hi)
-    // FP32: lane covers H8/2 h-values: part c = g >> 1, half (g & 1)
     const int c = g >> 1, hsub = g & 1;
-    const int cc = rt ? 1 - c : c;
-    const unsigned negm = (rt == 1 && c == 0) ? (BF16 ? 0x80008000u : 0x80000000u) : 0u;
-    const int hoff = BF16 ? 8 * hsub : (H8 / 2) * hsub;
-    const int voffA = (ai * rowE + cc * H8 + hoff) * esz;
-    const int voffB = (i16 * rowE + c * H8 + hoff) * esz;
-    const int nhb = (H8 + 15) >> 4;               // BF16: h blocks of 16 per lane pair
-    const bool padlast = BF16 && ((H8 >> 3) & 1) && hsub == 1;
-    const unsigned padm = padlast ? 0u : 0xffffffffu;
-
-    const size_t rowBytes = (size_t)rowE * esz;
-    const size_t qBytesA = (size_t)8 * rowBytes;   // one q of an image tile
-    const size_t qBytesB = (size_t)16 * rowBytes;  // one q of a target tile
+    // Re row [ar | ai], Im row [-ai | ar] against the column [br | bi]
+    const int blkA = rt ? (c == 0 ? 2 : 0) : c;
+    const int planeA = 3 * H8 * esz, planeB = 2 * H8 * esz;
+    const int rowA = args.nplanes * planeA, rowB = args.nplanes * planeB;
+    const int qBytesA = 8 * rowA, qBytesB = 16 * rowB;
+    constexpr int OOB = 0x40000000;   // beyond every operand buffer: the load returns zeros
+    int voA[PR::NPL][NB], voB[PR::NPL][NB];
+#pragma unroll
+    for (int pl = 0; pl < PR::NPL; ++pl)
+#pragma unroll
+        for (int hb = 0; hb < NB; ++hb) {
+            int h0, pad;
+            if constexpr (BF) {
+                h0 = 8 * (2 * hb + hsub);
+                pad = (2 * hb + hsub) >= (H8 >> 3);
+            } else {
+                h0 = (H8 / 2) * hsub + 4 * hb;
+                pad = 0;
+            }
+            voA[pl][hb] = pad ? OOB : ai * rowA + pl * planeA + (blkA * H8 + h0) * esz;
+            voB[pl][hb] = pad ? OOB : i16 * rowB + pl * planeB + (c * H8 + h0) * esz;
+        }
     const char *Abase = reinterpret_cast<const char *>(args.Af) + (size_t)ta * (M + 1) * qBytesA;
     const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)Abase, (short)0, (int)((M + 1) * qBytesA), 0x00020000);
+        (void *)Abase, (short)0, (M + 1) * qBytesA, 0x00020000);
 
-    // running results over t
+    // per-lane twiddle factor W_Q^e
+    const float fe_c = e ? (float)trig2pi(1, Q, false) : 1.f;
+    const float fe_s = e ? (float)(-trig2pi(1, Q, true)) : 0.f;
+
     float run_best = -INFINITY;
     int run_idx = 0x7fffffff;
     bool run_nan = false;
     float run_m = -INFINITY, run_s = 0.f;
 
-    for (int t = 0; t < args.T; ++t) {
-        const char *Bbase = reinterpret_cast<const char *>(args.Bf) +
-                            ((size_t)t * args.nTB + tb) * (M + 1) * qBytesB;
-        const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)Bbase, (short)0, (int)((M + 1) * qBytesB), 0x00020000);
+    // frequency of job J = 4R + j of wave w (per round: lower 2w, 2w+1, upper 2w, 2w+1)
+    auto jobq = [&](int J) -> int {
+        const int R = J >> 2, j = J & 3;
+        const int qq = 2 * w + (j & 1);
+        return (j < 2) ? 8 * R + qq : M - 8 * R - qq;
+    };
+    auto rsrcB = [&](int t) {
+        const char *Bbase = reinterpret_cast<const char *>(args.Bf) + ((size_t)t * args.nTB + tb) * (M + 1) * qBytesB;
+        return __builtin_amdgcn_make_buffer_rsrc((void *)Bbase, (short)0, (M + 1) * qBytesB, 0x00020000);
+    };
+    auto load = [&](const __amdgpu_buffer_rsrc_t &rB, int q, Frag<KIND, NB> &f) {
+        const int sA = __builtin_amdgcn_readfirstlane(q * qBytesA);
+        const int sB = __builtin_amdgcn_readfirstlane(q * qBytesB);
+#pragma unroll
+        for (int pl = 0; pl < PR::NPL; ++pl)
+#pragma unroll
+            for (int hb = 0; hb < NB; ++hb) {
+                f.a[pl][hb] = __builtin_amdgcn_raw_buffer_load_b128(rA, voA[pl][hb], sA, 0);
+                f.b[pl][hb] = __builtin_amdgcn_raw_buffer_load_b128(rB, voB[pl][hb], sB, 0);
+            }
+    };
+    auto mma = [&](const Frag<KIND, NB> &f) -> f32x4 {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (BF) {
+#pragma unroll
+            for (int p = 0; p < PR::NPROD; ++p)
+#pragma unroll
+                for (int hb = 0; hb < NB; ++hb)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, f.a[PR::pa(p)][hb]),
+                                                                 __builtin_bit_cast(bf16x8, f.b[PR::pb(p)][hb]),
+                                                                 acc, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int hb = 0; hb < NB; ++hb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(f.a[0][hb][j]),
+                                                              __uint_as_float(f.b[0][hb][j]), acc, 0, 0, 0);
+        }
+        return acc;
+    };
+    // staging slot layout: pair P at element P ^ (16 * bit 5 of P) (halves LDS bank conflicts
+    // of the MFMA-layout writes; a wave's reads stay within one 32-pair block)
+    auto sidx = [](int P) { return P ^ (((P >> 5) & 1) << 4); };
+    // rows 4g..4g+3 of the 16x16 block: images 2g, 2g+1 (Re, Im) at target column i16
+    auto put = [&](int slot, f32x4 v) {
+        stage[slot * 128 + sidx((2 * g) * 16 + i16)] = cx<float>{v[0], v[1]};
+        stage[slot * 128 + sidx((2 * g + 1) * 16 + i16)] = cx<float>{v[2], v[3]};
+    };
+    const int Ps = sidx(P);
 
-        // one frequency q: 16x16 block of [Re S; Im S](image, target)
-        auto contract = [&](int q) -> f32x4 {
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-            const int sA = q * (int)qBytesA, sB = q * (int)qBytesB;
-            if constexpr (BF16) {
-                for (int p = 0; p < args.nprod; ++p) {
-                    const int pA = args.planeA[p] * 2 * H8 * 2, pB = args.planeB[p] * 2 * H8 * 2;
-                    for (int hb = 0; hb < nhb; ++hb) {
-                        u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rA, voffA, sA + pA + 32 * hb, 0);
-                        u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rB, voffB, sB + pB + 32 * hb, 0);
-                        a ^= negm;
-                        if (hb == nhb - 1) {
-                            a &= padm;
-                            b &= padm;
-                        }
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            __builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    constexpr int FRAG_REGS = 2 * PR::NPL * NB * 4;
+    constexpr int D = FRAG_REGS <= 32 ? 4 : (FRAG_REGS <= 48 ? 3 : 2);   // prefetch depth (jobs)
+    constexpr int NJ = 4 * NRP;
+    Frag<KIND, NB> fr[D + 1];
+
+    for (int t = 0; t < args.T; ++t) {
+        const __amdgpu_buffer_rsrc_t rB = rsrcB(t);
+        cx<float> x[LH];
+        sfor<0, D>([&](auto II) { load(rB, jobq(decltype(II)::value), fr[decltype(II)::value]); });
+        // ---------------- step 1: contraction, paired rounds ----------------
+        sfor<0, NRP>([&](auto RR) {
+            constexpr int R = decltype(RR)::value;
+            sfor<0, 4>([&](auto JJ) {
+                constexpr int J = 4 * R + decltype(JJ)::value;
+                if constexpr (J + D < NJ) {
+                    load(rB, jobq(J + D), fr[(J + D) % (D + 1)]);
+                } else if constexpr (J + D == NJ) {
+                    if (w == 0) load(rB, M / 2, fr[(J + D) % (D + 1)]);   // middle frequency
+                }
+                const f32x4 acc = mma(fr[J % (D + 1)]);
+                put((decltype(JJ)::value < 2 ? 0 : 8) + 2 * w + (decltype(JJ)::value & 1), acc);
+            });
+            __syncthreads();
+            // Z fold: lane e owns k = 8R + 2jj + e (k and M - k have equal parity)
+            sfor<0, 4>([&](auto JJ) {
+                constexpr int jj = decltype(JJ)::value;
+                cx<float> lo = stage[(2 * jj + e) * 128 + Ps];        // S[k]
+                cx<float> hi = stage[(8 + 2 * jj + e) * 128 + Ps];    // S[M - k]
+                if constexpr (R == 0 && jj == 0) {
+                    if (e == 0) {   // S[0], S[M] are real
+                        lo.im = 0.f;
+                        hi.im = 0.f;
                     }
                 }
-            } else {
-                for (int hc = 0; hc < (H8 >> 3); ++hc) {
-                    u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rA, voffA, sA + 16 * hc, 0);
-                    u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rB, voffB, sB + 16 * hc, 0);
-                    a ^= negm;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[j]), __uint_as_float(b[j]),
-                                                                  acc, 0, 0, 0);
+                const cx<float> u = {lo.re + hi.re, lo.im - hi.im};
+                cx<float> v = {lo.re - hi.re, lo.im + hi.im};
+                v = cx<float>{v.re * fe_c - v.im * fe_s, v.re * fe_s + v.im * fe_c};   // * W_Q^e
+                const cx<float> p = twmul<8 * R + 2 * jj, Q>(v);                      // * W_Q^{k-e}
+                x[4 * R + jj] = cx<float>{u.re - p.im, u.im + p.re};                  // Z[k]
+                const cx<float> zc = {u.re + p.im, p.re - u.im};                      // Z[M - k]
+                constexpr int ubase = LH - 4 * R - jj;                                 // upper slot + e
+                if constexpr (R == 0 && jj == 0) {
+                    if (e == 1) upper[(ubase - 1) * 256 + tid] = zc;
+                } else {
+                    upper[(ubase - e) * 256 + tid] = zc;
                 }
-            }
-            return acc;
-        };
-        // rows 4g..4g+3 of the block: images 2g, 2g+1 (Re, Im) at target column i16
-        auto put = [&](int buf, int qq, f32x4 v) {
-            stage[buf][qq][(2 * g) * 16 + i16] = cx<float>{v[0], v[1]};
-            stage[buf][qq][(2 * g + 1) * 16 + i16] = cx<float>{v[2], v[3]};
-        };
-
-        cx<float> st[L];
-        sfor<0, NRF>([&](auto RR) {
-            constexpr int R = decltype(RR)::value;
-            constexpr int buf = R & 1;
-            const int q0 = 8 * R + 2 * w;
-            f32x4 a0 = contract(q0);
-            f32x4 a1 = contract(q0 + 1);
-            put(buf, 2 * w, a0);
-            put(buf, 2 * w + 1, a1);
-            __syncthreads();
-            sfor<0, 4>([&](auto JJ) {
-                constexpr int j = decltype(JJ)::value;
-                st[4 * R + j] = stage[buf][2 * j + e][P];
             });
+            __syncthreads();
         });
-        {   // q = M (Nyquist): real, kept in the imaginary slot of lane e = 0's S[0]
-            constexpr int buf = NRF & 1;
+        {   // middle frequency q = M/2 (even): Z[M/2] = 2 S[M/2], upper slot 0 of lane e = 0
             if (w == 0) {
-                f32x4 a0 = contract(M);
-                put(buf, 0, a0);
+                const f32x4 acc = mma(fr[NJ % (D + 1)]);
+                put(0, acc);
             }
             __syncthreads();
-            const float sM = stage[buf][0][P].re;
-            if (e == 0) st[0].im = sM;
+            const cx<float> sm = stage[Ps];
+            if (e == 0) upper[tid] = cx<float>{2.f * sm.re, 2.f * sm.im};
+            __syncthreads();
         }
 
-        // ---- Z sequence (in place): lane 0 even k, lane 1 odd k ----
-        auto zpair = [&](cx<float> &x, cx<float> &y, auto kk) {
-            constexpr int k = decltype(kk)::value;
-            const cx<float> u = {x.re + y.re, x.im - y.im};      // S[k] + conj S[M-k]
-            const cx<float> v = {x.re - y.re, x.im + y.im};      // S[k] - conj S[M-k]
-            const cx<float> p = twmul<k, Q>(v);
-            x = cx<float>{u.re - p.im, u.im + p.re};              // Z[k]
-            y = cx<float>{u.re + p.im, p.re - u.im};              // Z[M-k]
-        };
-        if (e == 0) {
-            const float s0 = st[0].re, sM = st[0].im;
-            st[0] = cx<float>{s0 + sM, s0 - sM};
-            sfor<1, L / 2>([&](auto II) {
-                constexpr int ii = decltype(II)::value;
-                zpair(st[ii], st[L - ii], IC<2 * ii>{});
-            });
-            st[L / 2] = cx<float>{2.f * st[L / 2].re, 2.f * st[L / 2].im};
-        } else {
-            sfor<0, L / 2>([&](auto II) {
-                constexpr int ii = decltype(II)::value;
-                zpair(st[ii], st[L - 1 - ii], IC<2 * ii + 1>{});
-            });
-        }
-
-        reg_fft<L>(st);   // lane 0: E[f] = DFT_L(Z[2k']), lane 1: O[f] = DFT_L(Z[2k'+1])
-
-        // ---- cross-lane radix-2 and epilogue ----
-        float bl = -INFINITY, bh = -INFINITY;
-        int il = 0x7fffffff, ih = 0x7fffffff;
-        float mx = -INFINITY;
-        float firstX = 0.f;
-        sfor<0, L / 2>([&](auto JJ) {
-            constexpr int j = decltype(JJ)::value;
-            constexpr int ra = ct_pos(L, j), rb = ct_pos(L, L / 2 + j);
-            // lane 0 sends E[L/2 + j], lane 1 sends O[j]
-            float nre, nim;
-            st[ra].re = perm_swap_lo(st[ra].re, st[rb].re, nre);
-            st[rb].re = nre;
-            st[ra].im = perm_swap_lo(st[ra].im, st[rb].im, nim);
-            st[rb].im = nim;
-            const cx<float> a = st[ra];          // E[n]
-            cx<float> b = st[rb];                // O[n], n = j + e L/2
-            if (e) b = cx<float>{b.im, -b.re};   // W_M^{L/2} = -i
-            const cx<float> tw = twmul<j, M>(b);
-            st[ra] = cadd(a, tw);                // z[n]     -> X[2n], X[2n+1]
-            st[rb] = csub(a, tw);                // z[n + L] -> X[2n + M], X[2n + M + 1]
-            if constexpr (j == 0) firstX = st[ra].re;
+        // ---------------- step 2: FFT over q, on chip ----------------
+        // DIF split of the length-L sequence: u[k] = x[k] + x[k+LH] (even outputs),
+        // v[k] = (x[k] - x[k+LH]) W_L^k (odd outputs, parked in LDS)
+        sfor<0, LH>([&](auto KK) {
+            constexpr int k = decltype(KK)::value;
+            const cx<float> b = upper[k * 256 + tid];
+            const cx<float> a = x[k];
+            x[k] = cadd(a, b);
+            upper[k * 256 + tid] = twmul<k, L>(csub(a, b));
         });
-        if constexpr (MODE & 1) {
-            sfor<0, L / 2>([&](auto JJ) {
-                constexpr int j = decltype(JJ)::value;
-                const cx<float> zl = st[ct_pos(L, j)], zh = st[ct_pos(L, L / 2 + j)];
-                if (zl.re > bl) { bl = zl.re; il = 2 * j; }
-                if (zl.im > bl) { bl = zl.im; il = 2 * j + 1; }
-                if (zh.re > bh) { bh = zh.re; ih = 2 * j + M; }
-                if (zh.im > bh) { bh = zh.im; ih = 2 * j + M + 1; }
+        float bv[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};   // even-lo, even-hi, odd-lo, odd-hi
+        int bi[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+        float lse_mx = -INFINITY, lse_sum = 0.f;
+        bool nanX = false;
+        auto half_pass = [&](auto PARITY) {
+            constexpr int par = decltype(PARITY)::value;   // 0: even n, 1: odd n
+            reg_fft<LH>(x);   // x[pos(f)] = E[2f + par] (lane 0) / O[2f + par] (lane 1)
+            sfor<0, LH / 2>([&](auto FF) {
+                constexpr int f = decltype(FF)::value;
+                constexpr int ra = ct_pos(LH, f), rb = ct_pos(LH, f + LH / 2);
+                float nre, nim;
+                x[ra].re = perm_swap_lo(x[ra].re, x[rb].re, nre);
+                x[rb].re = nre;
+                x[ra].im = perm_swap_lo(x[ra].im, x[rb].im, nim);
+                x[rb].im = nim;
+                const cx<float> a = x[ra];          // E[n]
+                cx<float> b = x[rb];                // O[n], n = 2f + par + e L/2
+                if (e) b = cx<float>{b.im, -b.re}; // W_M^{L/2} = -i
+                const cx<float> tw = twmul<2 * f + par, M>(b);
+                x[ra] = cadd(a, tw);                // z[n]     -> X[2n], X[2n+1]
+                x[rb] = csub(a, tw);                // z[n + L] -> X[2n + M], X[2n + M + 1]
             });
-        }
-        if constexpr (MODE & 2) {
-            sfor<0, L / 2>([&](auto JJ) {
-                constexpr int j = decltype(JJ)::value;
-                const cx<float> zl = st[ct_pos(L, j)], zh = st[ct_pos(L, L / 2 + j)];
-                mx = fmaxf(mx, fmaxf(fmaxf(zl.re, zl.im), fmaxf(zh.re, zh.im)));
-            });
-        }
-        const bool isnanX = __builtin_isnan(firstX) || __builtin_isnan(__shfl_xor(firstX, 32, 64));
-        if constexpr (MODE & 1) {
-            // lane-local winner (low half wins ties), then across the lane pair
-            if (bh > bl) { bl = bh; il = ih; }
-            il += e * L;
-            const float ob = __shfl_xor(bl, 32, 64);
-            const int oi = __shfl_xor(il, 32, 64);
-            if (ob > bl || (ob == bl && oi < il)) { bl = ob; il = oi; }
+            if constexpr (par == 0) nanX = __builtin_isnan(x[ct_pos(LH, 0)].re);
+            if (do_best) {
+                sfor<0, LH / 2>([&](auto FF) {
+                    constexpr int f = decltype(FF)::value;
+                    constexpr int m0 = 4 * f + 2 * par;
+                    const cx<float> zl = x[ct_pos(LH, f)], zh = x[ct_pos(LH, f + LH / 2)];
+                    if (zl.re > bv[2 * par]) { bv[2 * par] = zl.re; bi[2 * par] = m0; }
+                    if (zl.im > bv[2 * par]) { bv[2 * par] = zl.im; bi[2 * par] = m0 + 1; }
+                    if (zh.re > bv[2 * par + 1]) { bv[2 * par + 1] = zh.re; bi[2 * par + 1] = m0 + M; }
+                    if (zh.im > bv[2 * par + 1]) { bv[2 * par + 1] = zh.im; bi[2 * par + 1] = m0 + M + 1; }
+                });
+            }
+            if (do_lse) {
+                float mx = -INFINITY;
+                sfor<0, LH / 2>([&](auto FF) {
+                    constexpr int f = decltype(FF)::value;
+                    const cx<float> zl = x[ct_pos(LH, f)], zh = x[ct_pos(LH, f + LH / 2)];
+                    mx = fmaxf(mx, fmaxf(fmaxf(zl.re, zl.im), fmaxf(zh.re, zh.im)));
+                });
+                const float s = args.inv_s2, sm = s * mx;
+                float acc = 0.f;
+                sfor<0, LH / 2>([&](auto FF) {
+                    constexpr int f = decltype(FF)::value;
+                    const cx<float> zl = x[ct_pos(LH, f)], zh = x[ct_pos(LH, f + LH / 2)];
+                    acc += __expf(fmaf(s, zl.re, -sm)) + __expf(fmaf(s, zl.im, -sm)) +
+                           __expf(fmaf(s, zh.re, -sm)) + __expf(fmaf(s, zh.im, -sm));
+                });
+                const float nm = fmaxf(lse_mx, sm);
+                lse_sum = lse_sum * __expf(lse_mx - nm) + acc * __expf(sm - nm);
+                lse_mx = nm;
+            }
+        };
+        half_pass(IC<0>{});
+        sfor<0, LH>([&](auto KK) { x[decltype(KK)::value] = upper[decltype(KK)::value * 256 + tid]; });
+        half_pass(IC<1>{});
+
+        const bool isnanX = nanX || __builtin_isnan(__shfl_xor(nanX ? __builtin_nanf("") : 0.f, 32, 64));
+        if (do_best) {
+            // lane-local winner: ties go to the smaller m (even/odd interleave)
+            float b0 = bv[0];
+            int i0 = bi[0];
+            auto take = [&](float v, int i) {
+                if (v > b0 || (v == b0 && i < i0)) { b0 = v; i0 = i; }
+            };
+            take(bv[2], bi[2]);
+            take(bv[1], bi[1]);
+            take(bv[3], bi[3]);
+            i0 += e * L;
+            const float ob = __shfl_xor(b0, 32, 64);
+            const int oi = __shfl_xor(i0, 32, 64);
+            if (ob > b0 || (ob == b0 && oi < i0)) { b0 = ob; i0 = oi; }
             if (isnanX) run_nan = true;
-            const int gidx = t * Q + il;
-            if (bl > run_best) { run_best = bl; run_idx = gidx; }
+            if (b0 > run_best) { run_best = b0; run_idx = t * Q + i0; }
         }
-        if constexpr (MODE & 2) {
-            const float s = args.inv_s2;
-            mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-            const float sm = s * mx;
-            float acc = 0.f;
-            sfor<0, L / 2>([&](auto JJ) {
-                constexpr int j = decltype(JJ)::value;
-                const cx<float> zl = st[ct_pos(L, j)], zh = st[ct_pos(L, L / 2 + j)];
-                acc += __expf(fmaf(s, zl.re, -sm)) + __expf(fmaf(s, zl.im, -sm)) +
-                       __expf(fmaf(s, zh.re, -sm)) + __expf(fmaf(s, zh.im, -sm));
-            });
-            acc += __shfl_xor(acc, 32, 64);
+        if (do_lse) {
+            const float om = __shfl_xor(lse_mx, 32, 64), os = __shfl_xor(lse_sum, 32, 64);
+            const float nm = fmaxf(lse_mx, om);
+            const float tot = lse_sum * __expf(lse_mx - nm) + os * __expf(om - nm);
             if (isnanX) run_nan = true;
-            const float nm = fmaxf(run_m, sm);
-            run_s = run_s * __expf(run_m - nm) + acc * __expf(sm - nm);
-            run_m = nm;
+            const float rm = fmaxf(run_m, nm);
+            run_s = run_s * __expf(run_m - rm) + tot * __expf(nm - rm);
+            run_m = rm;
         }
-        __syncthreads();
+        __syncthreads();   // upper[] and stage[] are reused by the next translation
     }
 
     const int a = ta * 8 + pa, b = tb * 16 + pb;
     if (e == 0 && a < args.n_img && b < args.n_tgt) {
         const size_t o = (size_t)a * args.n_tgt + b;
-        if constexpr (MODE & 1) {
+        if (do_best) {
             if (run_nan) {
                 args.best_score[o] = __builtin_nanf("");
                 args.best_m[o] = -1;
@@ -473,30 +549,59 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
                 args.best_t[o] = run_idx / Q;
             }
         }
-        if constexpr (MODE & 2) args.lse_pair[o] = run_nan ? __builtin_nanf("") : run_m + __logf(run_s);
+        if (do_lse) args.lse_pair[o] = run_nan ? __builtin_nanf("") : run_m + __logf(run_s);
     }
 }
 
-template <int Q, bool BF16>
-static hipError_t launch_q(const Args &a, int nwg, int mode, hipStream_t s) {
-    switch (mode) {
-    case 1: hipLaunchKernelGGL((k_pairs_fast<Q, BF16, 1>), dim3(nwg), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pairs_fast<Q, BF16, 2>), dim3(nwg), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pairs_fast<Q, BF16, 3>), dim3(nwg), dim3(256), 0, s, a); break;
+template <int Q, int KIND, int NB>
+static hipError_t launch_v(const Args &a, int nwg, hipStream_t s) {
+    constexpr int LH = Q / 8;
+    const size_t shmem = (size_t)(16 * 128 + LH * 256) * sizeof(cx<float>);
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_pairs_fast<Q, KIND, NB>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+        attr_done = true;
     }
+    hipLaunchKernelGGL((k_pairs_fast<Q, KIND, NB>), dim3(nwg), dim3(256), shmem, s, a);
     return hipGetLastError();
 }
 
-template <bool BF16>
-static hipError_t launch_prec(const Args &a, int Q, int nwg, int mode, hipStream_t s) {
+template <int Q, int KIND>
+static hipError_t launch_k(const Args &a, int nwg, int H8, hipStream_t s) {
+    if constexpr (KIND == 0) {
+        switch (H8) {
+        case 8: return launch_v<Q, 0, 1>(a, nwg, s);
+        case 16: return launch_v<Q, 0, 2>(a, nwg, s);
+        case 24: return launch_v<Q, 0, 3>(a, nwg, s);
+        default: return launch_v<Q, 0, 4>(a, nwg, s);
+        }
+    } else {
+        if (H8 <= 16) return launch_v<Q, KIND, 1>(a, nwg, s);
+        return launch_v<Q, KIND, 2>(a, nwg, s);
+    }
+}
+
+template <int Q>
+static hipError_t launch_q(const Args &a, int kind, int nwg, int H8, hipStream_t s) {
+    switch (kind) {
+    case 0: return launch_k<Q, 0>(a, nwg, H8, s);
+    case 1: return launch_k<Q, 1>(a, nwg, H8, s);
+    case 2: return launch_k<Q, 2>(a, nwg, H8, s);
+    default: return launch_k<Q, 3>(a, nwg, H8, s);
+    }
+}
+
+static hipError_t launch_any(const Args &a, int Q, int kind, int nwg, int H8, hipStream_t s) {
     switch (Q) {
-    case 64: return launch_q<64, BF16>(a, nwg, mode, s);
-    case 96: return launch_q<96, BF16>(a, nwg, mode, s);
-    case 128: return launch_q<128, BF16>(a, nwg, mode, s);
-    case 192: return launch_q<192, BF16>(a, nwg, mode, s);
-    case 256: return launch_q<256, BF16>(a, nwg, mode, s);
-    case 384: return launch_q<384, BF16>(a, nwg, mode, s);
-    case 512: return launch_q<512, BF16>(a, nwg, mode, s);
+    case 64: return launch_q<64>(a, kind, nwg, H8, s);
+    case 96: return launch_q<96>(a, kind, nwg, H8, s);
+    case 128: return launch_q<128>(a, kind, nwg, H8, s);
+    case 192: return launch_q<192>(a, kind, nwg, H8, s);
+    case 256: return launch_q<256>(a, kind, nwg, H8, s);
+    case 384: return launch_q<384>(a, kind, nwg, H8, s);
+    case 512: return launch_q<512>(a, kind, nwg, H8, s);
     default: return hipErrorNotSupported;
     }
 }
@@ -527,27 +632,15 @@ hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, floa
     a.nTA = p->na_pad / kFastTA;
     a.nTB = p->nb_pad / kFastTB;
     a.H8 = p->H8;
-    a.rowElems = p->nplanes * 2 * p->H8;
-    const bool bf = p->prec != RADSVD_FP32;
-    if (bf) {
-        static const int pa3[6] = {0, 0, 1, 1, 0, 2};
-        static const int pb3[6] = {0, 1, 0, 1, 2, 0};
-        a.nprod = p->prec == RADSVD_BF16 ? 1 : p->products;
-        for (int i = 0; i < 6; ++i) {
-            a.planeA[i] = pa3[i];
-            a.planeB[i] = pb3[i];
-        }
-    }
+    a.nplanes = p->nplanes;
     a.flags = flags;
     a.inv_s2 = inv_s2;
     a.best_score = best_score;
     a.best_m = best_m;
     a.best_t = best_t;
     a.lse_pair = lse_pair;
-    const int nwg = a.nTA * a.nTB;
-    const int mode = flags & 3;
-    return bf ? fastk::launch_prec<true>(a, p->Q, nwg, mode, s)
-              : fastk::launch_prec<false>(a, p->Q, nwg, mode, s);
+    const int kind = p->prec == RADSVD_FP32 ? 0 : p->prec == RADSVD_BF16 ? 1 : (p->products == 3 ? 2 : 3);
+    return fastk::launch_any(a, p->Q, kind, a.nTA * a.nTB, p->H8, s);
 }
 
 }  // namespace radsvd

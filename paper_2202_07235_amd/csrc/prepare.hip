@@ -54,34 +54,33 @@ __global__ void k_ueta(const double *U, int ld, const double *eta, int K, int H,
 // ---------------------------------------------------------------------------
 // principal rings + angular FFT
 //
-// One workgroup per (item n, translation t).  Phase 1 accumulates
+// One workgroup per (item n, translation t).  Phase 1: thread j owns the
+// angles psi_j, psi_{j+256} and accumulates, for every h of the current pass,
 //   Y[h][j] = sum_r Ueta[r][h] * phi_t[r][j] * X[n][r][j]
-// in registers (each thread owns NI (h, j) outputs).  Phase 2 transforms
-// rows of Y in LDS:  y[h][q] = Q^{-1/2} sum_j Y[h][j] exp(-2 pi i q j / Q)
-// and writes q in [0, Qc) to
+// (Ueta[r][h] is uniform across the workgroup and is read as a scalar
+// operand; no barrier inside the ring loop).  Phase 2 transforms rows of Y
+// in LDS:  y[h][q] = Q^{-1/2} sum_j Y[h][j] exp(-2 pi i q j / Q)  and writes
+// q in [0, Qc) to
 //   generic layout  G[n][t][q][h]                      (cx<R>)
 //   fast layout     F[t][tile][q][n_in][plane][c][h8]  (FP32 or bf16 planes)
 // Items n >= n_real (tile padding) only write zeros to the fast layout.
 // ---------------------------------------------------------------------------
-template <typename R, int NI>
+template <typename R, int HP>
 __global__ __launch_bounds__(256) void k_rings(
     const cx<R> *__restrict__ X, int n_real, int T, const cx<R> *__restrict__ phase,
-    const R *__restrict__ Ueta, int K, int Q, int H, int Qc, int HC, int FC,
+    const R *__restrict__ Ueta, int K, int Q, int H, int Qc, int FC,
     cx<R> *__restrict__ G,                                       // may be null
-    void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes) {
+    void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int ncomp) {
     extern __shared__ unsigned char smem_raw[];
     const int n = blockIdx.x / T;
     const int t = blockIdx.x - n * T;
     const int tid = threadIdx.x;
     const int nthreads = blockDim.x;
     cx<R> *tw = reinterpret_cast<cx<R> *>(smem_raw);             // [Q]
-    cx<R> *work = tw + Q;                                         // phase 1: zbuf[Q] | Ueta[K*H]
-    cx<R> *zbuf = work;
-    R *ue = reinterpret_cast<R *>(work + Q);
-    const size_t planeElems = (size_t)2 * H8;
+    cx<R> *ybuf = tw + Q;                                         // [FC][Q]
+    const size_t planeElems = (size_t)ncomp * H8;   // [re | im] or [re | im | -im]
     const size_t rowElems = planeElems * nplanes;
-    const int Mp1 = Q / 2 + 1;
-    const int f_q = (Qc == Q) ? Q : Mp1;
+    const int f_q = (Qc == Q) ? Q : Q / 2 + 1;
     const int tile = n / f_tile, n_in = n - tile * f_tile;
     auto fidx = [&](int q) -> size_t {
         return ((((size_t)t * f_ntiles + tile) * f_q + q) * f_tile + n_in) * rowElems;
@@ -109,34 +108,33 @@ __global__ __launch_bounds__(256) void k_rings(
     const R scale = (R)(1.0 / sqrt((double)Q));
     const cx<R> *Xn = X + (size_t)n * K * Q;
     const cx<R> *ph = phase ? phase + (size_t)t * K * Q : nullptr;
+    const int j0 = tid, j1 = tid + nthreads;
+    const bool v0 = j0 < Q, v1 = j1 < Q;
 
-    for (int h0 = 0; h0 < H; h0 += HC) {
-        const int hc = min(HC, H - h0);
-        const int nout = hc * Q;
-        cx<R> acc[NI];
+    for (int h0 = 0; h0 < H; h0 += HP) {
+        const int hc = min(HP, H - h0);
+        cx<R> acc0[HP], acc1[HP];
 #pragma unroll
-        for (int i = 0; i < NI; ++i) acc[i] = cx<R>{(R)0, (R)0};
-        __syncthreads();
-        for (int i = tid; i < K * hc; i += nthreads) {
-            const int r = i / hc, hh = i - r * hc;
-            ue[i] = Ueta[(size_t)r * H + h0 + hh];
-        }
+        for (int h = 0; h < HP; ++h) acc0[h] = acc1[h] = cx<R>{(R)0, (R)0};
         for (int r = 0; r < K; ++r) {
-            __syncthreads();
-            for (int j = tid; j < Q; j += nthreads) {
-                cx<R> x = Xn[(size_t)r * Q + j];
-                zbuf[j] = ph ? cmul(x, ph[(size_t)r * Q + j]) : x;
+            cx<R> z0 = {(R)0, (R)0}, z1 = {(R)0, (R)0};
+            if (v0) {
+                z0 = Xn[(size_t)r * Q + j0];
+                if (ph) z0 = cmul(z0, ph[(size_t)r * Q + j0]);
             }
-            __syncthreads();
+            if (v1) {
+                z1 = Xn[(size_t)r * Q + j1];
+                if (ph) z1 = cmul(z1, ph[(size_t)r * Q + j1]);
+            }
+            const R *ur = Ueta + (size_t)r * H + h0;
 #pragma unroll
-            for (int i = 0; i < NI; ++i) {
-                const int o = tid + i * nthreads;
-                if (o < nout) {
-                    const int hh = o / Q, j = o - hh * Q;
-                    const R u = ue[r * hc + hh];
-                    const cx<R> z = zbuf[j];
-                    acc[i].re += u * z.re;
-                    acc[i].im += u * z.im;
+            for (int h = 0; h < HP; ++h) {
+                if (h < hc) {
+                    const R u = ur[h];
+                    acc0[h].re += u * z0.re;
+                    acc0[h].im += u * z0.im;
+                    acc1[h].re += u * z1.re;
+                    acc1[h].im += u * z1.im;
                 }
             }
         }
@@ -144,18 +142,15 @@ __global__ __launch_bounds__(256) void k_rings(
         for (int f0 = 0; f0 < hc; f0 += FC) {
             const int fc = min(FC, hc - f0);
             __syncthreads();
-            cx<R> *ybuf = work;
 #pragma unroll
-            for (int i = 0; i < NI; ++i) {
-                const int o = tid + i * nthreads;
-                if (o < nout) {
-                    const int hh = o / Q;
-                    if (hh >= f0 && hh < f0 + fc) ybuf[o - f0 * Q] = acc[i];
+            for (int h = 0; h < HP; ++h) {
+                if (h >= f0 && h < f0 + fc) {
+                    if (v0) ybuf[(h - f0) * Q + j0] = acc0[h];
+                    if (v1) ybuf[(h - f0) * Q + j1] = acc1[h];
                 }
             }
             __syncthreads();
             lds_fft_dif(ybuf, fc, Q, pl, tw);
-            // write q < Qc
             for (int i = tid; i < Qc * fc; i += nthreads) {
                 const int q = i / fc, hh = i - q * fc;
                 const int h = h0 + f0 + hh;
@@ -169,6 +164,7 @@ __global__ __launch_bounds__(256) void k_rings(
                         float *Fp = reinterpret_cast<float *>(F);
                         Fp[base + h] = (float)v.re;
                         Fp[base + H8 + h] = (float)v.im;
+                        if (ncomp == 3) Fp[base + 2 * H8 + h] = -(float)v.im;
                     } else {
                         uint16_t *Fp = reinterpret_cast<uint16_t *>(F);
                         uint16_t hr[3], hi_[3];
@@ -177,6 +173,7 @@ __global__ __launch_bounds__(256) void k_rings(
                         for (int pl_i = 0; pl_i < nplanes; ++pl_i) {
                             Fp[base + pl_i * planeElems + h] = hr[pl_i];
                             Fp[base + pl_i * planeElems + H8 + h] = hi_[pl_i];
+                            if (ncomp == 3) Fp[base + pl_i * planeElems + 2 * H8 + h] = hi_[pl_i] ^ 0x8000u;
                         }
                     }
                 }
@@ -186,12 +183,12 @@ __global__ __launch_bounds__(256) void k_rings(
     // zero the padding columns h in [H, H8) of the fast layout
     if (F && H8 > H) {
         const int padw = H8 - H;
-        for (int i = tid; i < Qc * padw * 2 * nplanes; i += nthreads) {
+        for (int i = tid; i < Qc * padw * ncomp * nplanes; i += nthreads) {
             int rem = i;
-            const int q = rem / (padw * 2 * nplanes);
-            rem -= q * (padw * 2 * nplanes);
-            const int pl_i = rem / (padw * 2);
-            rem -= pl_i * padw * 2;
+            const int q = rem / (padw * ncomp * nplanes);
+            rem -= q * (padw * ncomp * nplanes);
+            const int pl_i = rem / (padw * ncomp);
+            rem -= pl_i * padw * ncomp;
             const int c = rem / padw;
             const int h = H + rem - c * padw;
             const size_t off = fidx(q) + pl_i * planeElems + c * H8 + h;
@@ -244,45 +241,39 @@ hipError_t launch_ueta(radsvd_plan *p, const double *U_src, int ld, hipStream_t 
     return hipGetLastError();
 }
 
-template <typename R, int NI>
+template <typename R, int HP>
 static hipError_t rings_side(radsvd_plan *p, const void *X, int n_real, int n_pad, int T,
-                             bool use_phase, void *G, void *F, int f_tile, hipStream_t s) {
+                             bool use_phase, void *G, void *F, int f_tile, int ncomp, hipStream_t s) {
     const int Q = p->Q, K = p->K, H = p->H;
-    const int nthreads = 256;
-    int HC = (nthreads * NI) / Q;
-    if (HC > H) HC = H;
-    if (HC < 1) return hipErrorInvalidValue;
     const size_t cxb = sizeof(cx<R>);
-    const size_t work1 = (size_t)Q * cxb + (size_t)K * HC * sizeof(R);
     int FC = (int)(32768 / ((size_t)Q * cxb));
     if (FC < 1) FC = 1;
-    if (FC > HC) FC = HC;
-    const size_t work2 = (size_t)FC * Q * cxb;
-    const size_t shmem = (size_t)Q * cxb + (work1 > work2 ? work1 : work2);
+    if (FC > HP) FC = HP;
+    const size_t shmem = (size_t)Q * cxb + (size_t)FC * Q * cxb;
     const int f_kind = (p->prec == RADSVD_FP32 || p->prec == RADSVD_FP64) ? 0 : 1;
     const int f_ntiles = n_pad / f_tile;
     const int items = (F ? n_pad : n_real) * T;
-    hipLaunchKernelGGL((k_rings<R, NI>), dim3(items), dim3(nthreads), shmem, s,
+    hipLaunchKernelGGL((k_rings<R, HP>), dim3(items), dim3(256), shmem, s,
                        reinterpret_cast<const cx<R> *>(X), n_real, T,
                        use_phase ? reinterpret_cast<const cx<R> *>(p->phase) : nullptr,
-                       reinterpret_cast<const R *>(p->Ueta), K, Q, H, p->Qc, HC, FC,
-                       reinterpret_cast<cx<R> *>(G), F, f_kind, f_tile, f_ntiles, p->H8, p->nplanes);
+                       reinterpret_cast<const R *>(p->Ueta), K, Q, H, p->Qc, FC,
+                       reinterpret_cast<cx<R> *>(G), F, f_kind, f_tile, f_ntiles, p->H8, p->nplanes, ncomp);
     return hipGetLastError();
 }
 
 hipError_t launch_principal_rings(radsvd_plan *p, hipStream_t s) {
     hipError_t e;
     if (p->prec == RADSVD_FP64) {
-        e = rings_side<double, 32>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, nullptr,
-                                   kFastTA, s);
+        e = rings_side<double, 16>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, nullptr,
+                                   kFastTA, 3, s);
         if (e != hipSuccess) return e;
-        return rings_side<double, 32>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, nullptr,
-                                      kFastTB, s);
+        return rings_side<double, 16>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, nullptr,
+                                      kFastTB, 2, s);
     }
-    e = rings_side<float, 64>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, s);
+    e = rings_side<float, 32>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, 3, s);
     if (e != hipSuccess) return e;
-    return rings_side<float, 64>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, p->Bf,
-                                 kFastTB, s);
+    return rings_side<float, 32>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, p->Bf,
+                                 kFastTB, 2, s);
 }
 
 }  // namespace radsvd

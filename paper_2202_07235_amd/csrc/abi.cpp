@@ -106,12 +106,10 @@ Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
     L.off_Ag = take((size_t)n_img * L.Qc * H * CX);
     L.off_Bg = take((size_t)n_tgt * T * L.Qc * H * CX);
     if (L.fast) {
-        const size_t elem = (pr->prec == RADSVD_FP32) ? 4 : 2;
-        // image rows carry [re | im | -im] per plane, target rows [re | im]
-        const size_t rowA = (size_t)L.nplanes * 3 * L.H8 * elem;
-        const size_t rowB = (size_t)L.nplanes * 2 * L.H8 * elem;
-        L.Af_bytes = (size_t)L.na_pad * L.Qc * rowA;
-        L.Bf_bytes = (size_t)T * L.nb_pad * L.Qc * rowB;
+        // one fragment-ordered operand block per (tile, q): 8 images or 16 targets
+        const size_t blk = (size_t)L.nplanes * frag_plane_bytes(pr->prec != RADSVD_FP32, L.H8);
+        L.Af_bytes = (size_t)(L.na_pad / kFastTA) * L.Qc * blk;
+        L.Bf_bytes = (size_t)T * (L.nb_pad / kFastTB) * L.Qc * blk;
         L.off_Af = take(L.Af_bytes);
         L.off_Bf = take(L.Bf_bytes);
     }

@@ -27,6 +27,41 @@ struct GridArgs {
 constexpr int kFastTA = 8;     // images per tile   (16 MFMA rows: re and im rows)
 constexpr int kFastTB = 16;    // targets per tile  (16 MFMA columns)
 
+// Fragment-ordered operands of the fast path.  For one (tile, q) an operand
+// block holds, plane after plane, the 64-lane register fragments of the
+// 16-row (images: Re and Im row per image) or 16-column (targets) matrix
+// operand, in the order the wavefront loads them: lane l's 16 (or 8) bytes at
+// l * 16 (or l * 8), so that one load instruction reads one contiguous 1 KB
+// (512 B) block.  The depth index of the real embedding of conj(a) b is
+// k = c * H8 + h with c = 0 / 1 the first / second block:
+//   image Re row [ar | ai], image Im row [-ai | ar], target column [br | bi].
+// BF16 planes: chunks of 16 h (v_mfma_f32_16x16x32_bf16; lane l: row l % 16,
+//   c = (l / 16) / 2, h = 16 chunk + 8 ((l / 16) % 2) + 0..7) and, when H8 is
+//   an odd multiple of 8, one half chunk of 8 h (v_mfma_f32_16x16x16_bf16;
+//   lane l: c = (l / 16) / 2, h = 4 ((l / 16) % 2) + 0..3, 8 bytes per lane).
+// FP32 plane: chunks of 16 consecutive k (v_mfma_f32_16x16x4_f32; lane l's
+//   element j feeds the chunk's MFMA j with k = 16 chunk + 4 j + l / 16).
+__host__ __device__ inline int frag_plane_bytes(bool bf16, int H8) {
+    return bf16 ? (H8 / 16) * 1024 + ((H8 % 16) ? 512 : 0) : (H8 / 8) * 1024;
+}
+// byte offset of element (row, c, h) within one plane of an operand block
+__host__ __device__ inline int frag_elem_offset(bool bf16, int H8, int row, int c, int h) {
+    if (bf16) {
+        const int nfull = H8 / 16;
+        if (h < 16 * nfull) {
+            const int hb = h >> 4, hh = h & 15;
+            const int g = 2 * c + (hh >> 3);
+            return hb * 1024 + (16 * g + row) * 16 + (hh & 7) * 2;
+        }
+        const int hh = h - 16 * nfull;
+        const int g = 2 * c + (hh >> 2);
+        return nfull * 1024 + (16 * g + row) * 8 + (hh & 3) * 2;
+    }
+    const int k = c * H8 + h;
+    const int chunk = k >> 4, kk = k & 15;
+    return chunk * 1024 + (16 * (kk & 3) + row) * 16 + (kk >> 2) * 4;
+}
+
 }  // namespace radsvd
 
 struct radsvd_plan {

@@ -1,0 +1,636 @@
+#pragma once
+// Fused Hermitian pair kernel on the gfx950 matrix cores.
+//
+// Paper section 3.3 (two-step evaluation with principal rings, steps 1-2) for
+// Hermitian inputs (real images, section 2.5 conjugacy):
+//   step 1  S[q] = sum_h conj(At[a][h][q]) Bt[b][t][h][q],   q in [0, M], M = Q/2
+//   step 2  X[m] = sum_{q<Q} S[q] exp(-2 pi i q m / Q)        (S[Q-q] = conj S[q])
+// then the maximum over (t, m) (section 2.6) and/or the log-sum-exp, without
+// the landscape ever leaving the chip.
+//
+// Workgroup = 4 wavefronts = one tile of 8 images x 16 targets (128 pairs);
+// the translations t are looped inside the workgroup.
+//
+// Step 1 runs on MFMA.  For one q the contraction is a real GEMM with
+//   rows  = (image, re/im)           16 = 8 images x {Re S, Im S}
+//   cols  = target                   16
+//   depth = (product, re/im part, h) the real embedding of conj(a) * b:
+//           Re-row [ar | ai], Im-row [-ai | ar], column [br | bi]
+// FP32:   v_mfma_f32_16x16x4_f32, depth 2*H8.
+// BF16x3: v_mfma_f32_16x16x32_bf16 over the split products (hi*hi, hi*mid,
+//         mid*hi [, mid*mid, hi*lo, lo*hi]); FP32 accumulation.  A half chunk
+//         (ranks an odd multiple of 8) runs on v_mfma_f32_16x16x16_bf16 in an
+//         accumulation chain of its own.
+// The prepare kernel writes the operands of each (tile, q) as one block in
+// register-fragment order (frag_elem_offset), so every load instruction of a
+// wavefront reads one contiguous 1 KB (or 512 B) span.
+//
+// Step 2: every pair is owned by two lanes (l and l + 32 of one wavefront).
+// The half-spectrum S[0..M] becomes the length-M complex sequence
+//   Z[k] = (S[k] + conj S[M-k]) + i W_Q^k (S[k] - conj S[M-k]),
+// whose length-M DFT z gives X[2n] = Re z[n], X[2n+1] = Im z[n].  Lane
+// e = 0 holds Z at even k, lane e = 1 at odd k; each runs an in-register
+// FFT of length L = M/2, and one radix-2 stage across the two lanes
+// (v_permlane32_swap) completes z.  Everything in step 2 is FP32 VALU.
+#include <type_traits>
+
+#include "common.h"
+#include "internal.h"
+
+namespace radsvd {
+namespace fastk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+using IC = std::integral_constant<int, N>;
+
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F &&f) {
+    if constexpr (B < E) {
+        f(IC<B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// compile-time twiddles: cos / sin of 2 pi num / den with exact octant
+// reduction and Taylor series on [0, pi/4]
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double sin_poly(double x) {
+    double x2 = x * x, t = x, s = x;
+    for (int n = 1; n < 14; ++n) {
+        t *= -x2 / ((2.0 * n) * (2.0 * n + 1.0));
+        s += t;
+    }
+    return s;
+}
+constexpr double cos_poly(double x) {
+    double x2 = x * x, t = 1.0, s = 1.0;
+    for (int n = 1; n < 14; ++n) {
+        t *= -x2 / ((2.0 * n - 1.0) * (2.0 * n));
+        s += t;
+    }
+    return s;
+}
+// returns cos (want_sin = false) or sin of 2 pi num / den
+constexpr double trig2pi(long num, long den, bool want_sin) {
+    long n = num % den;
+    if (n < 0) n += den;
+    const long a = 8 * n;
+    const long o = a / den;
+    const long r = a - o * den;
+    const double th = (kPi / 4.0) * ((double)r / (double)den);
+    const double thc = (kPi / 4.0) * ((double)(den - r) / (double)den);
+    double c = 0, s = 0;
+    switch (o) {
+    case 0: c = cos_poly(th); s = sin_poly(th); break;
+    case 1: c = sin_poly(thc); s = cos_poly(thc); break;
+    case 2: c = -sin_poly(th); s = cos_poly(th); break;
+    case 3: c = -cos_poly(thc); s = sin_poly(thc); break;
+    case 4: c = -cos_poly(th); s = -sin_poly(th); break;
+    case 5: c = -sin_poly(thc); s = -cos_poly(thc); break;
+    case 6: c = sin_poly(th); s = -cos_poly(th); break;
+    default: c = cos_poly(thc); s = -sin_poly(thc); break;
+    }
+    return want_sin ? s : c;
+}
+
+// v * W_N^E, W_N = exp(-2 pi i / N)
+template <long E, long N>
+__device__ __forceinline__ cx<float> twmul(cx<float> v) {
+    constexpr long e = ((E % N) + N) % N;
+    if constexpr (e == 0) {
+        return v;
+    } else if constexpr (4 * e == N) {
+        return {v.im, -v.re};
+    } else if constexpr (2 * e == N) {
+        return {-v.re, -v.im};
+    } else if constexpr (4 * e == 3 * N) {
+        return {-v.im, v.re};
+    } else {
+        constexpr float c = (float)trig2pi(e, N, false);
+        constexpr float s = (float)(-trig2pi(e, N, true));
+        return {v.re * c - v.im * s, v.re * s + v.im * c};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// in-register mixed-radix DIF FFT (radices 4, then 2, then 3)
+// ---------------------------------------------------------------------------
+constexpr int ct_nst(int n) {
+    int s = 0;
+    while (n % 4 == 0) { n /= 4; ++s; }
+    while (n % 2 == 0) { n /= 2; ++s; }
+    while (n % 3 == 0) { n /= 3; ++s; }
+    return s;
+}
+constexpr int ct_radix(int n, int st) {
+    int s = 0;
+    while (n % 4 == 0) { if (s == st) return 4; n /= 4; ++s; }
+    while (n % 2 == 0) { if (s == st) return 2; n /= 2; ++s; }
+    while (n % 3 == 0) { if (s == st) return 3; n /= 3; ++s; }
+    return 1;
+}
+constexpr int ct_len(int n, int st) {
+    int L = n;
+    for (int s = 0; s < st; ++s) L /= ct_radix(n, s);
+    return L;
+}
+// register position of output frequency f
+constexpr int ct_pos(int n, int f) {
+    int pos = 0, L = n;
+    const int ns = ct_nst(n);
+    for (int s = 0; s < ns; ++s) {
+        const int R = ct_radix(n, s);
+        L /= R;
+        pos += (f % R) * L;
+        f /= R;
+    }
+    return pos;
+}
+
+template <int R>
+__device__ __forceinline__ void dft_r(cx<float> *v) {
+    if constexpr (R == 2) {
+        cx<float> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        cx<float> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        cx<float> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+        cx<float> u = cmul_mi(t3);
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, u);
+        v[3] = csub(t1, u);
+    } else {
+        const float h = 0.86602540378443864676f;
+        cx<float> a = v[0];
+        cx<float> t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+        cx<float> m = {a.re - 0.5f * t1.re, a.im - 0.5f * t1.im};
+        cx<float> u = {h * t2.im, -h * t2.re};
+        v[0] = cadd(a, t1);
+        v[1] = cadd(m, u);
+        v[2] = csub(m, u);
+    }
+}
+
+template <int N, int S>
+__device__ __forceinline__ void fft_stage(cx<float> (&x)[N]) {
+    constexpr int R = ct_radix(N, S);
+    constexpr int L = ct_len(N, S);
+    constexpr int span = L / R;
+    sfor<0, N / L>([&](auto blk) {
+        sfor<0, span>([&](auto kk) {
+            constexpr int k = decltype(kk)::value;
+            constexpr int base = decltype(blk)::value * L + k;
+            cx<float> v[R];
+            sfor<0, R>([&](auto r) { v[decltype(r)::value] = x[base + decltype(r)::value * span]; });
+            dft_r<R>(v);
+            x[base] = v[0];
+            sfor<1, R>([&](auto pp) {
+                constexpr int p = decltype(pp)::value;
+                x[base + p * span] = twmul<(long)k * p, L>(v[p]);
+            });
+        });
+    });
+}
+
+template <int N>
+__device__ __forceinline__ void reg_fft(cx<float> (&x)[N]) {
+    sfor<0, ct_nst(N)>([&](auto S) { fft_stage<N, decltype(S)::value>(x); });
+}
+
+__device__ __forceinline__ float perm_swap_lo(float vdst, float vsrc, float &vsrc_out) {
+    // lanes 32..63 of vdst <-> lanes 0..31 of vsrc
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(vdst), __float_as_uint(vsrc), false, false);
+    vsrc_out = __uint_as_float(r[1]);
+    return __uint_as_float(r[0]);
+}
+
+struct Args {
+    const void *Af;            // fast operands, images
+    const void *Bf;            // fast operands, targets
+    int n_img, n_tgt, T;
+    int nTA, nTB;              // tile counts
+    int H8;
+    int nplanes;
+    int flags;
+    float inv_s2;
+    float *best_score;
+    int32_t *best_m, *best_t;
+    float *lse_pair;
+};
+
+// tile index of workgroup `wg`: workgroups are dealt round-robin to the 8
+// XCDs; consecutive workgroups of one XCD walk an 8-row band of image tiles
+// with the target tile advancing every 8, so the XCD's concurrently resident
+// workgroups share image and target operand rows in its L2.
+__device__ __forceinline__ void tile_of(int wg, int nwg, int nTA, int nTB, int &ta, int &tb) {
+    const int xcd = wg & 7;
+    const int full = nwg >> 3, rem = nwg & 7;
+    const int lin = xcd * full + min(xcd, rem) + (wg >> 3);
+    const int band = lin / (8 * nTB);
+    const int rows = min(8, nTA - band * 8);
+    const int in_band = lin - band * 8 * nTB;
+    ta = band * 8 + in_band % rows;
+    tb = in_band / rows;
+}
+
+// Contraction precision of the fused kernel.
+//   KIND 0: FP32 operands, v_mfma_f32_16x16x4_f32
+//   KIND 1: bf16 (one product), v_mfma_f32_16x16x32_bf16 (+ 16x16x16 for a half chunk)
+//   KIND 2: split bf16, products hi*hi, hi*mid, mid*hi
+//   KIND 3: split bf16, + mid*mid, hi*lo, lo*hi
+template <int KIND>
+struct Prec {
+    static constexpr int NPL = KIND == 0 ? 1 : (KIND == 3 ? 3 : (KIND == 2 ? 2 : 1));   // planes loaded
+    static constexpr int NPROD = KIND == 3 ? 6 : (KIND == 2 ? 3 : 1);
+    static constexpr int pa(int p) { return p == 2 ? 1 : (p == 3 ? 1 : (p == 5 ? 2 : 0)); }   // A plane
+    static constexpr int pb(int p) { return p == 1 ? 1 : (p == 3 ? 1 : (p == 4 ? 2 : 0)); }   // B plane
+};
+
+// One job's operand registers: NF full chunks (16 bytes per lane) and, for
+// BF16 ranks that are odd multiples of 8, one half chunk (8 bytes per lane),
+// per loaded plane, for the image rows (a) and the target columns (b).
+template <int KIND, int NF, int HF>
+struct Frag {
+    u32x4 a[Prec<KIND>::NPL][NF > 0 ? NF : 1];
+    u32x4 b[Prec<KIND>::NPL][NF > 0 ? NF : 1];
+    u32x2 ah[Prec<KIND>::NPL];
+    u32x2 bh[Prec<KIND>::NPL];
+};
+
+// Q angles; KIND contraction precision; NF, HF operand chunks per plane
+// (FP32: NF = H8 / 8 chunks of 16 depth values, HF = 0; BF16: NF = H8 / 16,
+// HF = 1 when H8 is an odd multiple of 8).
+template <int Q, int KIND, int NF, int HF>
+__global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
+    constexpr int M = Q / 2;
+    constexpr int L = M / 2;          // Z values per lane
+    constexpr int LH = L / 2;         // in registers; the other LH in LDS
+    constexpr int NRP = M / 16;       // paired rounds: q in [8R, 8R+8) with M - q
+    constexpr bool BF = KIND != 0;
+    using PR = Prec<KIND>;
+    static_assert(M % 16 == 0, "Q must be a multiple of 32");
+
+    extern __shared__ unsigned char smem_raw[];
+    cx<float> *stage = reinterpret_cast<cx<float> *>(smem_raw);   // [16][128]
+    cx<float> *upper = stage + 16 * 128;                          // [LH][256]
+
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l = tid & 63;
+    const int e = l >> 5;               // 0: even-k lane, 1: odd-k lane
+    const int P = 32 * w + (l & 31);    // pair within the tile
+    const int pa = P >> 4, pb = P & 15;
+    const bool do_best = args.flags & RADSVD_OUT_BEST;
+    const bool do_lse = args.flags & RADSVD_OUT_LSE;
+
+    int ta, tb;
+    tile_of(blockIdx.x, gridDim.x, args.nTA, args.nTB, ta, tb);
+
+    // ---- MFMA operands: fragment-ordered blocks, one per (tile, q) ----
+    // Lane l reads bytes [16 l, 16 l + 16) of each full chunk and [8 l, 8 l + 8)
+    // of the half chunk; the block of frequency q starts at q * BB.  Job J of
+    // this wave reads frequency q = 8R + 2w + j (lower, j = 0, 1) or
+    // M - 8R - 2w - (j - 2) (upper, j = 2, 3); the wave part of q lives in the
+    // per-lane offsets, the round part is a compile-time scalar offset.
+    const int g = l >> 4, i16 = l & 15;        // MFMA output: rows 4g..4g+3, column i16
+    constexpr int PB = NF * 1024 + HF * 512;   // bytes per plane
+    constexpr int BB = PR::NPL * PB;           // bytes per (tile, q) block
+    const int vlo = 2 * w * BB;
+    const int vhi = (M / 2 + 7 - 2 * w) * BB;
+    const int vF_lo = 16 * l + vlo, vF_hi = 16 * l + vhi;
+    const int vH_lo = 8 * l + NF * 1024 + vlo, vH_hi = 8 * l + NF * 1024 + vhi;
+    const char *Abase = reinterpret_cast<const char *>(args.Af) + (size_t)ta * (M + 1) * BB;
+    const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)Abase, (short)0, (M + 1) * BB, 0x00020000);
+
+    // per-lane twiddle factor W_Q^e
+    const float fe_c = e ? (float)trig2pi(1, Q, false) : 1.f;
+    const float fe_s = e ? (float)(-trig2pi(1, Q, true)) : 0.f;
+
+    float run_best = -INFINITY;
+    int run_idx = 0x7fffffff;
+    bool run_nan = false;
+    float run_m = -INFINITY, run_s = 0.f;
+
+    auto rsrcB = [&](int t) {
+        const char *Bbase = reinterpret_cast<const char *>(args.Bf) + ((size_t)t * args.nTB + tb) * (M + 1) * BB;
+        return __builtin_amdgcn_make_buffer_rsrc((void *)Bbase, (short)0, (M + 1) * BB, 0x00020000);
+    };
+    // job J = 4R + j: upper (j >= 2) or lower, and its compile-time block offset
+    auto job_upper = [](int J) { return (J & 3) >= 2; };
+    auto job_soff = [](int J) {
+        const int R = J >> 2, j = J & 3;
+        return (j < 2) ? (8 * R + (j & 1)) * BB : (8 * (NRP - 1 - R) + 1 - (j & 1)) * BB;
+    };
+    using FragT = Frag<KIND, NF, HF>;
+    auto load_at = [&](const __amdgpu_buffer_rsrc_t &rB, bool upper, int soff, FragT &f) {
+        const int vF = upper ? vF_hi : vF_lo;
+        const int vH = upper ? vH_hi : vH_lo;
+#pragma unroll
+        for (int pl = 0; pl < PR::NPL; ++pl) {
+#pragma unroll
+            for (int hb = 0; hb < NF; ++hb) {
+                f.a[pl][hb] = __builtin_amdgcn_raw_buffer_load_b128(rA, vF + pl * PB + hb * 1024, soff, 0);
+                f.b[pl][hb] = __builtin_amdgcn_raw_buffer_load_b128(rB, vF + pl * PB + hb * 1024, soff, 0);
+            }
+            if constexpr (HF) {
+                f.ah[pl] = __builtin_amdgcn_raw_buffer_load_b64(rA, vH + pl * PB, soff, 0);
+                f.bh[pl] = __builtin_amdgcn_raw_buffer_load_b64(rB, vH + pl * PB, soff, 0);
+            }
+        }
+    };
+    auto mma = [&](const FragT &f) -> f32x4 {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (BF) {
+            // the half chunk (v_mfma_f32_16x16x16_bf16) accumulates in a chain of its own:
+            // every accumulation chain then has a single MFMA opcode
+            f32x4 acch = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int p = 0; p < PR::NPROD; ++p) {
+#pragma unroll
+                for (int hb = 0; hb < NF; ++hb)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, f.a[PR::pa(p)][hb]),
+                                                                 __builtin_bit_cast(bf16x8, f.b[PR::pb(p)][hb]),
+                                                                 acc, 0, 0, 0);
+                if constexpr (HF)
+                    acch = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, f.ah[PR::pa(p)]),
+                                                                    __builtin_bit_cast(s16x4, f.bh[PR::pb(p)]),
+                                                                    acch, 0, 0, 0);
+            }
+            if constexpr (HF) {
+                if constexpr (NF > 0) acc += acch;
+                else acc = acch;
+            }
+        } else {
+#pragma unroll
+            for (int hb = 0; hb < NF; ++hb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(f.a[0][hb][j]),
+                                                              __uint_as_float(f.b[0][hb][j]), acc, 0, 0, 0);
+        }
+        return acc;
+    };
+    // staging slot layout: pair P at element P ^ (16 * bit 5 of P) (halves LDS bank conflicts
+    // of the MFMA-layout writes; a wave's reads stay within one 32-pair block)
+    auto sidx = [](int P) { return P ^ (((P >> 5) & 1) << 4); };
+    // rows 4g..4g+3 of the 16x16 block: images 2g, 2g+1 (Re, Im) at target column i16
+    auto put = [&](int slot, f32x4 v) {
+        stage[slot * 128 + sidx((2 * g) * 16 + i16)] = cx<float>{v[0], v[1]};
+        stage[slot * 128 + sidx((2 * g + 1) * 16 + i16)] = cx<float>{v[2], v[3]};
+    };
+    const int Ps = sidx(P);
+
+    constexpr int FRAG_REGS = 2 * PR::NPL * (4 * NF + 2 * HF);
+    // prefetch depth in jobs: as deep as the registers beside the FFT state allow
+    constexpr int D = FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 32 ? 4 : (FRAG_REGS <= 48 ? 3 : 2));
+    constexpr int NJ = 4 * NRP;
+    FragT fr[D + 1];
+
+    for (int t = 0; t < args.T; ++t) {
+        const __amdgpu_buffer_rsrc_t rB = rsrcB(t);
+        cx<float> x[LH];
+        sfor<0, D>([&](auto II) {
+            constexpr int J = decltype(II)::value;
+            load_at(rB, job_upper(J), job_soff(J), fr[J]);
+        });
+        // ---------------- step 1: contraction, paired rounds ----------------
+        sfor<0, NRP>([&](auto RR) {
+            constexpr int R = decltype(RR)::value;
+            sfor<0, 4>([&](auto JJ) {
+                constexpr int J = 4 * R + decltype(JJ)::value;
+                if constexpr (J + D < NJ) {
+                    load_at(rB, job_upper(J + D), job_soff(J + D), fr[(J + D) % (D + 1)]);
+                } else if constexpr (J + D == NJ) {
+                    // middle frequency q = M/2, wave 0 (whose lower offsets are the bare lane part)
+                    if (w == 0) load_at(rB, false, (M / 2) * BB, fr[(J + D) % (D + 1)]);
+                }
+                // keep the prefetch ahead of this job's MFMAs (the scheduler would otherwise
+                // sink the loads and shorten the prefetch distance)
+                __builtin_amdgcn_sched_barrier(0);
+                const f32x4 acc = mma(fr[J % (D + 1)]);
+                put((decltype(JJ)::value < 2 ? 0 : 8) + 2 * w + (decltype(JJ)::value & 1), acc);
+            });
+            __syncthreads();
+            // Z fold: lane e owns k = 8R + 2jj + e (k and M - k have equal parity)
+            sfor<0, 4>([&](auto JJ) {
+                constexpr int jj = decltype(JJ)::value;
+                cx<float> lo = stage[(2 * jj + e) * 128 + Ps];        // S[k]
+                cx<float> hi = stage[(8 + 2 * jj + e) * 128 + Ps];    // S[M - k]
+                if constexpr (R == 0 && jj == 0) {
+                    if (e == 0) {   // S[0], S[M] are real
+                        lo.im = 0.f;
+                        hi.im = 0.f;
+                    }
+                }
+                const cx<float> u = {lo.re + hi.re, lo.im - hi.im};
+                cx<float> v = {lo.re - hi.re, lo.im + hi.im};
+                v = cx<float>{v.re * fe_c - v.im * fe_s, v.re * fe_s + v.im * fe_c};   // * W_Q^e
+                const cx<float> p = twmul<8 * R + 2 * jj, Q>(v);                      // * W_Q^{k-e}
+                x[4 * R + jj] = cx<float>{u.re - p.im, u.im + p.re};                  // Z[k]
+                const cx<float> zc = {u.re + p.im, p.re - u.im};                      // Z[M - k]
+                constexpr int ubase = LH - 4 * R - jj;                                 // upper slot + e
+                if constexpr (R == 0 && jj == 0) {
+                    if (e == 1) upper[(ubase - 1) * 256 + tid] = zc;
+                } else {
+                    upper[(ubase - e) * 256 + tid] = zc;
+                }
+            });
+            __syncthreads();
+        });
+        {   // middle frequency q = M/2 (even): Z[M/2] = 2 S[M/2], upper slot 0 of lane e = 0
+            if (w == 0) {
+                const f32x4 acc = mma(fr[NJ % (D + 1)]);
+                put(0, acc);
+            }
+            __syncthreads();
+            const cx<float> sm = stage[Ps];
+            if (e == 0) upper[tid] = cx<float>{2.f * sm.re, 2.f * sm.im};
+            __syncthreads();
+        }
+
+        // ---------------- step 2: FFT over q, on chip ----------------
+        // DIF split of the length-L sequence: u[k] = x[k] + x[k+LH] (even outputs),
+        // v[k] = (x[k] - x[k+LH]) W_L^k (odd outputs, parked in LDS)
+        sfor<0, LH>([&](auto KK) {
+            constexpr int k = decltype(KK)::value;
+            const cx<float> b = upper[k * 256 + tid];
+            const cx<float> a = x[k];
+            x[k] = cadd(a, b);
+            upper[k * 256 + tid] = twmul<k, L>(csub(a, b));
+        });
+        float bv[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};   // even-lo, even-hi, odd-lo, odd-hi
+        int bi[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+        float lse_mx = -INFINITY, lse_sum = 0.f;
+        bool nanX = false;
+        auto half_pass = [&](auto PARITY) {
+            constexpr int par = decltype(PARITY)::value;   // 0: even n, 1: odd n
+            reg_fft<LH>(x);   // x[pos(f)] = E[2f + par] (lane 0) / O[2f + par] (lane 1)
+            sfor<0, LH / 2>([&](auto FF) {
+                constexpr int f = decltype(FF)::value;
+                constexpr int ra = ct_pos(LH, f), rb = ct_pos(LH, f + LH / 2);
+                float nre, nim;
+                x[ra].re = perm_swap_lo(x[ra].re, x[rb].re, nre);
+                x[rb].re = nre;
+                x[ra].im = perm_swap_lo(x[ra].im, x[rb].im, nim);
+                x[rb].im = nim;
+                const cx<float> a = x[ra];          // E[n]
+                cx<float> b = x[rb];                // O[n], n = 2f + par + e L/2
+                if (e) b = cx<float>{b.im, -b.re}; // W_M^{L/2} = -i
+                const cx<float> tw = twmul<2 * f + par, M>(b);
+                x[ra] = cadd(a, tw);                // z[n]     -> X[2n], X[2n+1]
+                x[rb] = csub(a, tw);                // z[n + L] -> X[2n + M], X[2n + M + 1]
+            });
+            if constexpr (par == 0) nanX = __builtin_isnan(x[ct_pos(LH, 0)].re);
+            if (do_best) {
+                sfor<0, LH / 2>([&](auto FF) {
+                    constexpr int f = decltype(FF)::value;
+                    constexpr int m0 = 4 * f + 2 * par;
+                    const cx<float> zl = x[ct_pos(LH, f)], zh = x[ct_pos(LH, f + LH / 2)];
+                    if (zl.re > bv[2 * par]) { bv[2 * par] = zl.re; bi[2 * par] = m0; }
+                    if (zl.im > bv[2 * par]) { bv[2 * par] = zl.im; bi[2 * par] = m0 + 1; }
+                    if (zh.re > bv[2 * par + 1]) { bv[2 * par + 1] = zh.re; bi[2 * par + 1] = m0 + M; }
+                    if (zh.im > bv[2 * par + 1]) { bv[2 * par + 1] = zh.im; bi[2 * par + 1] = m0 + M + 1; }
+                });
+            }
+            if (do_lse) {
+                float mx = -INFINITY;
+                sfor<0, LH / 2>([&](auto FF) {
+                    constexpr int f = decltype(FF)::value;
+                    const cx<float> zl = x[ct_pos(LH, f)], zh = x[ct_pos(LH, f + LH / 2)];
+                    mx = fmaxf(mx, fmaxf(fmaxf(zl.re, zl.im), fmaxf(zh.re, zh.im)));
+                });
+                const float s = args.inv_s2, sm = s * mx;
+                float acc = 0.f;
+                sfor<0, LH / 2>([&](auto FF) {
+                    constexpr int f = decltype(FF)::value;
+                    const cx<float> zl = x[ct_pos(LH, f)], zh = x[ct_pos(LH, f + LH / 2)];
+                    acc += __expf(fmaf(s, zl.re, -sm)) + __expf(fmaf(s, zl.im, -sm)) +
+                           __expf(fmaf(s, zh.re, -sm)) + __expf(fmaf(s, zh.im, -sm));
+                });
+                const float nm = fmaxf(lse_mx, sm);
+                lse_sum = lse_sum * __expf(lse_mx - nm) + acc * __expf(sm - nm);
+                lse_mx = nm;
+            }
+        };
+        half_pass(IC<0>{});
+        sfor<0, LH>([&](auto KK) { x[decltype(KK)::value] = upper[decltype(KK)::value * 256 + tid]; });
+        half_pass(IC<1>{});
+
+        const bool isnanX = nanX || __builtin_isnan(__shfl_xor(nanX ? __builtin_nanf("") : 0.f, 32, 64));
+        if (do_best) {
+            // lane-local winner: ties go to the smaller m (even/odd interleave)
+            float b0 = bv[0];
+            int i0 = bi[0];
+            auto take = [&](float v, int i) {
+                if (v > b0 || (v == b0 && i < i0)) { b0 = v; i0 = i; }
+            };
+            take(bv[2], bi[2]);
+            take(bv[1], bi[1]);
+            take(bv[3], bi[3]);
+            i0 += e * L;
+            const float ob = __shfl_xor(b0, 32, 64);
+            const int oi = __shfl_xor(i0, 32, 64);
+            if (ob > b0 || (ob == b0 && oi < i0)) { b0 = ob; i0 = oi; }
+            if (isnanX) run_nan = true;
+            if (b0 > run_best) { run_best = b0; run_idx = t * Q + i0; }
+        }
+        if (do_lse) {
+            const float om = __shfl_xor(lse_mx, 32, 64), os = __shfl_xor(lse_sum, 32, 64);
+            const float nm = fmaxf(lse_mx, om);
+            const float tot = lse_sum * __expf(lse_mx - nm) + os * __expf(om - nm);
+            if (isnanX) run_nan = true;
+            const float rm = fmaxf(run_m, nm);
+            run_s = run_s * __expf(run_m - rm) + tot * __expf(nm - rm);
+            run_m = rm;
+        }
+        __syncthreads();   // upper[] and stage[] are reused by the next translation
+    }
+
+    const int a = ta * 8 + pa, b = tb * 16 + pb;
+    if (e == 0 && a < args.n_img && b < args.n_tgt) {
+        const size_t o = (size_t)a * args.n_tgt + b;
+        if (do_best) {
+            if (run_nan) {
+                args.best_score[o] = __builtin_nanf("");
+                args.best_m[o] = -1;
+                args.best_t[o] = -1;
+            } else {
+                args.best_score[o] = run_best;
+                args.best_m[o] = run_idx % Q;
+                args.best_t[o] = run_idx / Q;
+            }
+        }
+        if (do_lse) args.lse_pair[o] = run_nan ? __builtin_nanf("") : run_m + __logf(run_s);
+    }
+}
+
+template <int Q, int KIND, int NF, int HF>
+static hipError_t launch_v(const Args &a, int nwg, hipStream_t s) {
+    constexpr int LH = Q / 8;
+    const size_t shmem = (size_t)(16 * 128 + LH * 256) * sizeof(cx<float>);
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_pairs_fast<Q, KIND, NF, HF>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    hipLaunchKernelGGL((k_pairs_fast<Q, KIND, NF, HF>), dim3(nwg), dim3(256), shmem, s, a);
+    return hipGetLastError();
+}
+
+// operand chunk geometry of rank H8 (8, 16, 24 or 32)
+template <int Q, int KIND>
+static hipError_t launch_h(const Args &a, int nwg, int H8, hipStream_t s) {
+    if constexpr (KIND == 0) {
+        switch (H8) {
+        case 8: return launch_v<Q, 0, 1, 0>(a, nwg, s);
+        case 16: return launch_v<Q, 0, 2, 0>(a, nwg, s);
+        case 24: return launch_v<Q, 0, 3, 0>(a, nwg, s);
+        case 32: return launch_v<Q, 0, 4, 0>(a, nwg, s);
+        default: return hipErrorNotSupported;
+        }
+    } else {
+        switch (H8) {
+        case 8: return launch_v<Q, KIND, 0, 1>(a, nwg, s);
+        case 16: return launch_v<Q, KIND, 1, 0>(a, nwg, s);
+        case 24: return launch_v<Q, KIND, 1, 1>(a, nwg, s);
+        case 32: return launch_v<Q, KIND, 2, 0>(a, nwg, s);
+        default: return hipErrorNotSupported;
+        }
+    }
+}
+
+template <int KIND>
+static hipError_t launch_kind(const Args &a, int Q, int nwg, int H8, hipStream_t s) {
+    switch (Q) {
+    case 64: return launch_h<64, KIND>(a, nwg, H8, s);
+    case 96: return launch_h<96, KIND>(a, nwg, H8, s);
+    case 128: return launch_h<128, KIND>(a, nwg, H8, s);
+    case 192: return launch_h<192, KIND>(a, nwg, H8, s);
+    case 256: return launch_h<256, KIND>(a, nwg, H8, s);
+    case 384: return launch_h<384, KIND>(a, nwg, H8, s);
+    case 512: return launch_h<512, KIND>(a, nwg, H8, s);
+    default: return hipErrorNotSupported;
+    }
+}
+
+// one translation unit per contraction precision (compiled in parallel)
+hipError_t launch_fast_fp32(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_bf16(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_bf16x3(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_bf16x3_6(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+
+}  // namespace fastk
+}  // namespace radsvd

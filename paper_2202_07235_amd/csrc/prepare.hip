@@ -13,6 +13,8 @@
 
 namespace radsvd {
 
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------------------
 // grid factors and translation phases, computed in FP64
 //   eta_r = sqrt(w_r dpsi)                      (section 2.5, ring rescaling)
@@ -62,15 +64,16 @@ __global__ void k_ueta(const double *U, int ld, const double *eta, int K, int H,
 // in LDS:  y[h][q] = Q^{-1/2} sum_j Y[h][j] exp(-2 pi i q j / Q)  and writes
 // q in [0, Qc) to
 //   generic layout  G[n][t][q][h]                      (cx<R>)
-//   fast layout     F[t][tile][q][n_in][plane][c][h8]  (FP32 or bf16 planes)
-// Items n >= n_real (tile padding) only write zeros to the fast layout.
+//   fast layout     F[t][tile][q] operand blocks in MFMA fragment order
+//                   (FP32 or bf16 planes), zero-filled beforehand, so that
+//                   padding items and ranks h in [H, H8) stay zero.
 // ---------------------------------------------------------------------------
 template <typename R, int HP>
 __global__ __launch_bounds__(256) void k_rings(
     const cx<R> *__restrict__ X, int n_real, int T, const cx<R> *__restrict__ phase,
     const R *__restrict__ Ueta, int K, int Q, int H, int Qc, int FC,
     cx<R> *__restrict__ G,                                       // may be null
-    void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int ncomp) {
+    void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
     extern __shared__ unsigned char smem_raw[];
     const int n = blockIdx.x / T;
     const int t = blockIdx.x - n * T;
@@ -78,26 +81,15 @@ __global__ __launch_bounds__(256) void k_rings(
     const int nthreads = blockDim.x;
     cx<R> *tw = reinterpret_cast<cx<R> *>(smem_raw);             // [Q]
     cx<R> *ybuf = tw + Q;                                         // [FC][Q]
-    const size_t planeElems = (size_t)ncomp * H8;   // [re | im] or [re | im | -im]
-    const size_t rowElems = planeElems * nplanes;
+    const bool fbf = f_kind != 0;
+    const int planeB = frag_plane_bytes(fbf, H8);
+    const size_t blockB = (size_t)nplanes * planeB;
     const int f_q = (Qc == Q) ? Q : Q / 2 + 1;
     const int tile = n / f_tile, n_in = n - tile * f_tile;
-    auto fidx = [&](int q) -> size_t {
-        return ((((size_t)t * f_ntiles + tile) * f_q + q) * f_tile + n_in) * rowElems;
+    auto fblk = [&](int q) -> char * {
+        return reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
     };
-
-    if (n >= n_real) {
-        if (F) {
-            const size_t cnt = (size_t)f_q * rowElems;
-            for (size_t i = tid; i < cnt; i += nthreads) {
-                const int q = (int)(i / rowElems);
-                const size_t e = i - (size_t)q * rowElems;
-                if (f_kind == 0) reinterpret_cast<float *>(F)[fidx(q) + e] = 0.f;
-                else reinterpret_cast<uint16_t *>(F)[fidx(q) + e] = 0;
-            }
-        }
-        return;
-    }
+    if (n >= n_real) return;
 
     for (int i = tid; i < Q; i += nthreads) {
         double s, c;
@@ -159,43 +151,46 @@ __global__ __launch_bounds__(256) void k_rings(
                 v.im *= scale;
                 if (G) G[(((size_t)n * T + t) * Qc + q) * H + h] = v;
                 if (F) {
-                    const size_t base = fidx(q);
-                    if (f_kind == 0) {
-                        float *Fp = reinterpret_cast<float *>(F);
-                        Fp[base + h] = (float)v.re;
-                        Fp[base + H8 + h] = (float)v.im;
-                        if (ncomp == 3) Fp[base + 2 * H8 + h] = -(float)v.im;
+                    // image n_in: Re row 2 n_in = [ar | ai], Im row 2 n_in + 1 = [-ai | ar];
+                    // target n_in: column [br | bi]
+                    char *blk = fblk(q);
+                    const int r0 = is_img ? 2 * n_in : n_in;
+                    const int o_re = frag_elem_offset(fbf, H8, r0, 0, h);
+                    const int o_im = frag_elem_offset(fbf, H8, r0, 1, h);
+                    const int o_nim = is_img ? frag_elem_offset(fbf, H8, r0 + 1, 0, h) : 0;
+                    const int o_re2 = is_img ? frag_elem_offset(fbf, H8, r0 + 1, 1, h) : 0;
+                    if (!fbf) {
+                        *reinterpret_cast<float *>(blk + o_re) = (float)v.re;
+                        *reinterpret_cast<float *>(blk + o_im) = (float)v.im;
+                        if (is_img) {
+                            *reinterpret_cast<float *>(blk + o_nim) = -(float)v.im;
+                            *reinterpret_cast<float *>(blk + o_re2) = (float)v.re;
+                        }
                     } else {
-                        uint16_t *Fp = reinterpret_cast<uint16_t *>(F);
                         uint16_t hr[3], hi_[3];
                         split3_bf16((float)v.re, hr[0], hr[1], hr[2]);
                         split3_bf16((float)v.im, hi_[0], hi_[1], hi_[2]);
                         for (int pl_i = 0; pl_i < nplanes; ++pl_i) {
-                            Fp[base + pl_i * planeElems + h] = hr[pl_i];
-                            Fp[base + pl_i * planeElems + H8 + h] = hi_[pl_i];
-                            if (ncomp == 3) Fp[base + pl_i * planeElems + 2 * H8 + h] = hi_[pl_i] ^ 0x8000u;
+                            char *pb = blk + (size_t)pl_i * planeB;
+                            *reinterpret_cast<uint16_t *>(pb + o_re) = hr[pl_i];
+                            *reinterpret_cast<uint16_t *>(pb + o_im) = hi_[pl_i];
+                            if (is_img) {
+                                *reinterpret_cast<uint16_t *>(pb + o_nim) = hi_[pl_i] ^ 0x8000u;
+                                *reinterpret_cast<uint16_t *>(pb + o_re2) = hr[pl_i];
+                            }
                         }
                     }
                 }
             }
         }
     }
-    // zero the padding columns h in [H, H8) of the fast layout
-    if (F && H8 > H) {
-        const int padw = H8 - H;
-        for (int i = tid; i < Qc * padw * ncomp * nplanes; i += nthreads) {
-            int rem = i;
-            const int q = rem / (padw * ncomp * nplanes);
-            rem -= q * (padw * ncomp * nplanes);
-            const int pl_i = rem / (padw * ncomp);
-            rem -= pl_i * padw * ncomp;
-            const int c = rem / padw;
-            const int h = H + rem - c * padw;
-            const size_t off = fidx(q) + pl_i * planeElems + c * H8 + h;
-            if (f_kind == 0) reinterpret_cast<float *>(F)[off] = 0.f;
-            else reinterpret_cast<uint16_t *>(F)[off] = 0;
-        }
-    }
+}
+
+// zero fill of the fast operand buffers (a kernel rather than a memset, so
+// that the prepare sequence stays capturable in a graph)
+__global__ void k_zero16(u32x4_t *p, size_t n16) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = u32x4_t{0u, 0u, 0u, 0u};
 }
 
 // caller-supplied U [K][H]: copied into columns 0..H-1 of the plan's U,
@@ -243,7 +238,7 @@ hipError_t launch_ueta(radsvd_plan *p, const double *U_src, int ld, hipStream_t 
 
 template <typename R, int HP>
 static hipError_t rings_side(radsvd_plan *p, const void *X, int n_real, int n_pad, int T,
-                             bool use_phase, void *G, void *F, int f_tile, int ncomp, hipStream_t s) {
+                             bool use_phase, void *G, void *F, int f_tile, int is_img, hipStream_t s) {
     const int Q = p->Q, K = p->K, H = p->H;
     const size_t cxb = sizeof(cx<R>);
     int FC = (int)(32768 / ((size_t)Q * cxb));
@@ -252,12 +247,12 @@ static hipError_t rings_side(radsvd_plan *p, const void *X, int n_real, int n_pa
     const size_t shmem = (size_t)Q * cxb + (size_t)FC * Q * cxb;
     const int f_kind = (p->prec == RADSVD_FP32 || p->prec == RADSVD_FP64) ? 0 : 1;
     const int f_ntiles = n_pad / f_tile;
-    const int items = (F ? n_pad : n_real) * T;
+    const int items = n_real * T;   // padding items of the fast layout stay zero
     hipLaunchKernelGGL((k_rings<R, HP>), dim3(items), dim3(256), shmem, s,
                        reinterpret_cast<const cx<R> *>(X), n_real, T,
                        use_phase ? reinterpret_cast<const cx<R> *>(p->phase) : nullptr,
                        reinterpret_cast<const R *>(p->Ueta), K, Q, H, p->Qc, FC,
-                       reinterpret_cast<cx<R> *>(G), F, f_kind, f_tile, f_ntiles, p->H8, p->nplanes, ncomp);
+                       reinterpret_cast<cx<R> *>(G), F, f_kind, f_tile, f_ntiles, p->H8, p->nplanes, is_img);
     return hipGetLastError();
 }
 
@@ -265,15 +260,22 @@ hipError_t launch_principal_rings(radsvd_plan *p, hipStream_t s) {
     hipError_t e;
     if (p->prec == RADSVD_FP64) {
         e = rings_side<double, 16>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, nullptr,
-                                   kFastTA, 3, s);
+                                   kFastTA, 1, s);
         if (e != hipSuccess) return e;
         return rings_side<double, 16>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, nullptr,
-                                      kFastTB, 2, s);
+                                      kFastTB, 0, s);
     }
-    e = rings_side<float, 32>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, 3, s);
+    if (p->Af) {   // both fast buffers are contiguous multiples of 256 bytes
+        hipLaunchKernelGGL(k_zero16, dim3(2048), dim3(256), 0, s, reinterpret_cast<u32x4_t *>(p->Af),
+                           p->Af_bytes / 16);
+        hipLaunchKernelGGL(k_zero16, dim3(2048), dim3(256), 0, s, reinterpret_cast<u32x4_t *>(p->Bf),
+                           p->Bf_bytes / 16);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    e = rings_side<float, 32>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, 1, s);
     if (e != hipSuccess) return e;
     return rings_side<float, 32>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, p->Bf,
-                                 kFastTB, 2, s);
+                                 kFastTB, 0, s);
 }
 
 }  // namespace radsvd

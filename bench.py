@@ -43,11 +43,97 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--precision", default="bf16x3")
-    ap.add_argument("--products", type=int, default=3)
+    ap.add_argument("--products", type=int, default=6,
+                    help="bf16x3 cross products: 6 uses all three split terms (hi, mid, lo), "
+                         "3 only the two leading terms")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of N_A and N_B (for quick local runs; 1.0 = the full workload)")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the same-GPU comparison runs (FP32, bf16x3 with 3 products)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB streaming kernel (x -> -x) whose HBM counters calibrate FETCH_SIZE / "
+                         "WRITE_SIZE of the pair kernel")
+    ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "`bench.py --copy-probe` into the traffic profile text and exit")
     return ap.parse_args()
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pairs_fast_precision_bf16x3_6_traffic.txt")
+TRAFFIC_CONFIG = "bf16x3 products=6"
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_07235_amd", "csrc", f)
+                  for f in ("pairs_fast.h", "pairs_fast.hip", "pairs_fast_bf16x3_6.hip", "common.h", "internal.h")]
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def reduce_counters(fetch_dir, write_dir):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the pair kernel, scaled by
+    what the same counters read for the 1 GiB streaming kernel (read 1 GiB,
+    write 1 GiB), as HBM bytes per launch."""
+    out = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        pair, copy = [], []
+        for r in _counter_rows(d):
+            if r.get("Counter_Name") != name:
+                continue
+            kn, v = r.get("Kernel_Name", ""), float(r["Counter_Value"])
+            if "k_pairs_fast" in kn:
+                pair.append(v)
+            elif "neg" in kn and "elementwise" in kn:
+                copy.append(v)
+        if not pair or not copy:
+            raise SystemExit(f"{d}: no {name} rows for the pair kernel ({len(pair)}) or the copy kernel ({len(copy)})")
+        cp = max(copy)   # the 1 GiB launch (smaller neg launches, if any, read less)
+        out[name] = (sum(pair) / len(pair), len(pair), cp, COPY_BYTES / (cp * 1024.0))
+    fa, na, fc, ff = out["FETCH_SIZE"]
+    wa, nw, wc, wf = out["WRITE_SIZE"]
+    traffic = fa * 1024.0 * ff + wa * 1024.0 * wf
+    lines = [
+        "# HBM traffic of k_pairs_fast, precision workload (N=256 K=128 Q=512 N_A=N_B=4096 T=9 H=24)",
+        f"config: {TRAFFIC_CONFIG}",
+        f"kernel_source_sha256_16: {kernel_source_hash()}",
+        f"pair kernel FETCH_SIZE per dispatch: {fa:.6g} KiB ({na} dispatches)",
+        f"pair kernel WRITE_SIZE per dispatch: {wa:.6g} KiB ({nw} dispatches)",
+        f"copy kernel (1 GiB read + 1 GiB write) FETCH_SIZE: {fc:.6g} KiB -> scale {ff:.4f}",
+        f"copy kernel (1 GiB read + 1 GiB write) WRITE_SIZE: {wc:.6g} KiB -> scale {wf:.4f}",
+        f"traffic_bytes_per_launch: {traffic:.6g}",
+    ]
+    return "\n".join(lines)
+
+
+def traffic_from_profile():
+    """HBM bytes per pair-kernel launch from the committed counter profile, or
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            txt = fh.read()
+    except OSError:
+        return None
+    kv = dict(l.split(": ", 1) for l in txt.splitlines() if ": " in l and not l.startswith("#"))
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash() or kv.get("config") != TRAFFIC_CONFIG:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 class Step:
@@ -157,6 +243,9 @@ def cpu_baseline(P, A, B, U, H, gpu_out, budget_s=12.0):
 
 def main():
     a = parse()
+    if a.reduce_counters:
+        print(reduce_counters(*a.reduce_counters))
+        return 0
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); nothing in this build runs across "
               f"GPUs.", file=sys.stderr)
@@ -200,14 +289,29 @@ def main():
     print(f"[bench] {a.precision}: {ms_step:.2f} ms/step, pairs kernel {pairs_avg:.2f} ms", file=sys.stderr,
           flush=True)
 
-    fp32 = None
-    if not a.no_fp32 and a.precision != "fp32":
-        s32 = Step(rs, A, B, P, H, "fp32", 3)
-        w32, p32 = timed(s32, max(2, a.steps // 2), 1)
-        s32.close()
-        fp32 = {"value": n_pairs * max(2, a.steps // 2) / w32, "ms_per_step": 1e3 * w32 / max(2, a.steps // 2),
-                "pairs_kernel_ms": float(np.mean(p32))}
-        print(f"[bench] fp32: {fp32['ms_per_step']:.2f} ms/step, pairs kernel {fp32['pairs_kernel_ms']:.2f} ms",
+    if a.copy_probe:
+        src = torch.randn(COPY_BYTES // 4, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        print("[bench] copy probe done", file=sys.stderr, flush=True)
+
+    # the same step in plain FP32 and, for bf16x3, with the two-term split (3 products), on this GPU
+    alt = {}
+    alt_runs = [] if a.no_fp32 else [("fp32", 3)]
+    if not a.no_fp32 and a.precision == "bf16x3" and a.products == 6:
+        alt_runs.append(("bf16x3", 3))
+    for prec, prod in alt_runs:
+        if prec == a.precision and prod == a.products:
+            continue
+        s2 = Step(rs, A, B, P, H, prec, prod)
+        n2 = max(2, a.steps // 2)
+        w2, p2 = timed(s2, n2, 1)
+        s2.close()
+        key = prec if prec == "fp32" else f"{prec}_{prod}products"
+        alt[key] = {"value": n_pairs * n2 / w2, "ms_per_step": 1e3 * w2 / n2, "pairs_kernel_ms": float(np.mean(p2))}
+        print(f"[bench] {key}: {alt[key]['ms_per_step']:.2f} ms/step, pairs kernel {alt[key]['pairs_kernel_ms']:.2f} ms",
               file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (the fused pair kernel)
@@ -233,7 +337,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": bytes_min / t_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = traffic_from_profile() if f"{a.precision} products={a.products}" == TRAFFIC_CONFIG else None
     roof["kernel"] = f"k_pairs_fast<Q={Q},bf16={a.precision != 'fp32'},BEST>"
     roof["kernel_ms"] = pairs_avg
     roof["per_unit"] = {"unit": "pair-translation", "units_per_launch": pair_delta,
@@ -262,7 +366,7 @@ def main():
                    "products": a.products, "step": "align_prepare + align_pairs(BEST)"},
         "pairs_only_per_s": n_pairs / (pairs_avg * 1e-3),
         "pairs_kernel_ms": pairs_avg,
-        "fp32": fp32,
+        "same_gpu_comparison": alt,
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": accuracy,

@@ -66,11 +66,17 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_source_hash():
+    """Hash of the pair kernel's sources with comments and blank lines removed
+    (a changed comment does not invalidate measured counters)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            txt = fh.read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", "", txt)
+        h.update("\n".join(l.rstrip() for l in txt.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
 
@@ -108,6 +114,7 @@ def reduce_counters(fetch_dir, write_dir):
     traffic = fa * 1024.0 * ff + wa * 1024.0 * wf
     lines = [
         "# HBM traffic of k_pairs_fast, precision workload (N=256 K=128 Q=512 N_A=N_B=4096 T=9 H=24)",
+        "# kernel_source_sha256_16: hash of the pair kernel sources with comments removed (bench.kernel_source_hash)",
         f"config: {TRAFFIC_CONFIG}",
         f"kernel_source_sha256_16: {kernel_source_hash()}",
         f"pair kernel FETCH_SIZE per dispatch: {fa:.6g} KiB ({na} dispatches)",

@@ -127,7 +127,7 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
  *
  *   RADSVD_OUT_BEST : best_score[a][b] = max_{t,m} Re X[a][b][t][m]  (f32),
  *                     best_m[a][b], best_t[a][b] (int32) its location; the
- *                     maximum-likelihood rotation of section 2.6 is
+ *                     maximum-likelihood rotation of section 2.7 is
  *                     gamma = 2 pi m / Q.  Ties go to the smallest t*Q + m; a
  *                     pair whose landscape has a NaN gets NaN and -1, -1.
  *   RADSVD_OUT_LSE  : lse_pair[a][b] = log sum_{t,m} exp(inv_sigma2 Re X)  (f32, inv_sigma2 > 0);

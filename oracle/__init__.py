@@ -26,7 +26,7 @@ alignment of images and volumes", arXiv 2202.07235):
                           is the full polar quadrature of <Ahat, R_gamma T_delta Bhat>
                           (prefactor (2 pi)^-2 dropped, as the paper does).
 * ``best`` / ``lse``   -- maximum-likelihood alignment argmax_gamma X (section
-                          2.6) and the soft-alignment log-sum-exp score.
+                          2.7) and the soft-alignment log-sum-exp score.
 * ``lse_grad``         -- gradient of sum_a g_a lse_img[a] with respect to the
                           target polar samples and U (chain rule written as
                           direct psi-space sums).
@@ -93,7 +93,7 @@ def _c128(a) -> np.ndarray:
 # grid-derived factors
 # --------------------------------------------------------------------------
 def eta(w, Q: int) -> np.ndarray:
-    """eta_r = sqrt(w_r dpsi), dpsi = 2 pi / Q (section 2.5, ring rescaling)."""
+    """eta_r = sqrt(w_r dpsi), dpsi = 2 pi / Q (section 2.6, ring rescaling)."""
     return np.sqrt(np.asarray(w, dtype=np.float64) * (2.0 * math.pi / Q))
 
 
@@ -189,7 +189,7 @@ def landscape(A, B, U, H: int, k, w, delta, pairs=None) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# decisions (section 2.6) and the soft-alignment score
+# decisions (section 2.7) and the soft-alignment score
 # --------------------------------------------------------------------------
 def best(X):
     """argmax over (t, m) of Re X per pair; ties go to the smallest t*Q + m.
@@ -217,7 +217,7 @@ def _logsumexp(x, axis):
 def lse(X, inv_sigma2: float):
     """lse_pair[a,b] = log sum_{t,m} exp(inv_sigma2 Re X); lse_img[a] =
     log sum_b exp(lse_pair[a,b]).  Soft version of the maximum-likelihood
-    alignment: the Gaussian log-likelihood of section 2.5 is, up to
+    alignment: the Gaussian log-likelihood of section 2.6 is, up to
     gamma-independent terms, X / sigma^2."""
     R = np.asarray(X).real * inv_sigma2
     na, nb, T, Q = R.shape

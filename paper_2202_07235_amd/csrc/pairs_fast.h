@@ -2,10 +2,10 @@
 // Fused Hermitian pair kernel on the gfx950 matrix cores.
 //
 // Paper section 3.3 (two-step evaluation with principal rings, steps 1-2) for
-// Hermitian inputs (real images, section 2.5 conjugacy):
+// Hermitian inputs (real images, whose transforms are conjugate-symmetric):
 //   step 1  S[q] = sum_h conj(At[a][h][q]) Bt[b][t][h][q],   q in [0, M], M = Q/2
 //   step 2  X[m] = sum_{q<Q} S[q] exp(-2 pi i q m / Q)        (S[Q-q] = conj S[q])
-// then the maximum over (t, m) (section 2.6) and/or the log-sum-exp, without
+// then the maximum over (t, m) (section 2.7) and/or the log-sum-exp, without
 // the landscape ever leaving the chip.
 //
 // Workgroup = 4 wavefronts = one tile of 8 images x 16 targets (128 pairs);

@@ -17,7 +17,7 @@ typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // grid factors and translation phases, computed in FP64
-//   eta_r = sqrt(w_r dpsi)                      (section 2.5, ring rescaling)
+//   eta_r = sqrt(w_r dpsi)                      (section 2.6, ring rescaling)
 //   phi_t[r][j] = exp(-i k_r (dx cos psi_j + dy sin psi_j))
 //                 (transform of B(x - delta), section 2.1)
 // ---------------------------------------------------------------------------

@@ -152,8 +152,15 @@ size_t align_backward_workspace(const radsvd_plan *plan);
  *   grad_U       device [K][H] FP64: dL/dU with U a free matrix (the
  *                eigendecomposition is not differentiated).
  * Either output may be NULL.  lse_img and grad_lse_img are device [n_img] f32.
- * The contraction runs in FP32 for every precision except RADSVD_FP64.
- * bwd_ws: device scratch of bwd_bytes >= align_backward_workspace(plan).
+ * Every step runs in FP64 on the plan's stored principal-ring coefficients
+ * (FP32 for every precision but RADSVD_FP64): the landscape is recomputed,
+ * and lse_img serves only as the exponent shift; the normalisation over
+ * (b, t, m) is recomputed in FP64.  Images are processed in chunks whose
+ * landscape transforms take at most 4 GiB of the scratch.
+ * bwd_ws: device scratch of bwd_bytes >= align_backward_workspace(plan),
+ * 256-byte aligned.  Errors: RADSVD_ERR_INVALID_ARG (NULL plan or lse
+ * pointers, inv_sigma2 not finite and > 0, misaligned outputs),
+ * RADSVD_ERR_WORKSPACE (scratch missing, misaligned or too small).
  */
 radsvd_status align_pairs_backward(const radsvd_plan *plan, float inv_sigma2,
                                    const float *lse_img, const float *grad_lse_img,

@@ -21,7 +21,7 @@ __all__ = [
     "align_prepare_workspace", "align_prepare", "align_pairs", "align_backward_workspace",
     "align_pairs_backward", "align_batched_workspace", "align_pairs_batched", "align_get_U",
     "align_set_tile", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
-    "PRECISIONS",
+    "PRECISIONS", "RadialAlignLSE",
 ]
 
 FP64, FP32, BF16, BF16X3 = 0, 1, 2, 3
@@ -271,3 +271,40 @@ class Plan:
         align_pairs_backward(self.handle, inv_sigma2, lse_img.contiguous(), grad_lse_img.contiguous(),
                              gB, gU, ws, stream)
         return gB, gU
+
+
+class RadialAlignLSE(torch.autograd.Function):
+    """Soft-alignment score with a hand-written backward.
+
+        lse_img = RadialAlignLSE.apply(A_polar, B_polar, U, k, w, delta, inv_sigma2, precision, hermitian)
+
+    Forward: ``align_prepare`` with the caller's U [K][H] (FP64) and
+    ``align_pairs`` with the log-sum-exp output; returns lse_img [n_img] (f32):
+    lse_img[a] = log sum_{b,t,m} exp(inv_sigma2 Re X[a][b][t][m]).
+    Backward: ``align_pairs_backward``; gradients flow to B_polar (complex,
+    dL/dRe + i dL/dIm, every entry free) and U (a free real matrix).  A_polar,
+    the grid and the scalars get none.
+    """
+
+    @staticmethod
+    def forward(ctx, A_polar, B_polar, U, k, w, delta, inv_sigma2=1.0, precision="fp32", hermitian=True):
+        plan = Plan(A_polar.detach().contiguous(), B_polar.detach().contiguous(), k, w, delta, U.shape[1],
+                    precision=precision, hermitian=hermitian, U=U.detach())
+        o = plan.pairs("lse", inv_sigma2=inv_sigma2)
+        ctx.plan = plan
+        ctx.inv_sigma2 = float(inv_sigma2)
+        ctx.U_dtype = U.dtype
+        ctx.save_for_backward(o["lse_img"])
+        return o["lse_img"].clone()
+
+    @staticmethod
+    def backward(ctx, grad_lse_img):
+        (lse_img,) = ctx.saved_tensors
+        want_B, want_U = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        gB = gU = None
+        if want_B or want_U:
+            gB, gU = ctx.plan.backward(ctx.inv_sigma2, lse_img, grad_lse_img.to(torch.float32).contiguous(),
+                                       want_B=want_B, want_U=want_U)
+        if gU is not None:
+            gU = gU.to(ctx.U_dtype)
+        return None, gB, gU, None, None, None, None, None, None

@@ -1,14 +1,454 @@
-// Backward pass of the soft-alignment loss.  Not available yet: no plan has
-// a backward workspace size.
+// Backward pass of the soft-alignment loss L = sum_a g[a] lse_img[a], with
+// lse_img[a] = log sum_b exp(lse_pair[a][b]) and lse_pair[a][b] =
+// log sum_{t,m} exp(s Re X[a][b][t][m]) (s = inv_sigma2): the Gaussian
+// log-likelihood of paper section 2.6 marginalised over the alignments.
+//
+// With P[a,b,t,m] = dL/dRe X = g[a] s exp(s Re X - lse_img[a]) and the unitary
+// angular coefficients at, bt of the principal rings (X[m] = sum_q W^{qm}
+// sum_h conj(at[h,q]) bt[h,q], W = exp(-2 pi i / Q)):
+//   Phat[q]        = sum_m P[m] exp(+2 pi i q m / Q)
+//   g_bt[b,t,h,q]  = sum_a at[a,h,q] Phat[a,b,t,q]
+//   g_at[a,h,q]    = sum_{b,t} conj(Phat[a,b,t,q]) bt[b,t,h,q]
+// back to psi-space by the adjoint (inverse) unitary transform, then through
+// the recombination Br_h^t = sum_r U[r,h] eta_r phi_t[r,.] Bhat[r,.]:
+//   dL/dBhat[b,r,j] = eta_r sum_t conj(phi_t[r,j]) sum_h U[r,h] g_Br[b,t,h,j]
+//   dL/dU[r,h]      = sum Re(conj(g_Ar[a,h,j]) eta_r Ahat[a,r,j])
+//                   + sum Re(conj(g_Br[b,t,h,j]) eta_r phi_t[r,j] Bhat[b,r,j])
+// (complex gradients: dL/dRe + i dL/dIm; U is a free real matrix).
+//
+// For Hermitian inputs only q in [0, Q/2] is stored; the other half follows
+// from Phat[Q-q] = conj Phat[q] and at, bt, g_at, g_bt[Q-q] = (-1)^q conj(.[q]).
+// Every step runs in FP64; images are processed in chunks so that the Phat
+// buffer stays within a fixed budget.  All reductions have a fixed order.
+// The forward's lse_img (FP32) only serves as the exponent shift c_a: the
+// kernel forms Pt = exp(s Re X - c_a) and the per-pair sums of Pt, and the
+// exact normalisation g[a] s exp(c_a - lse_img[a]) = g[a] s / sum_{b,t,m} Pt
+// is applied as a per-image factor kappa[a] in the contractions.
+#include <math.h>
+
 #include "common.h"
 #include "internal.h"
 
 namespace radsvd {
 
-size_t backward_bytes(const radsvd_plan *) { return 0; }
-hipError_t launch_backward(const radsvd_plan *, float, const float *, const float *, void *, double *,
-                           void *, hipStream_t) {
-    return hipErrorNotSupported;
+namespace {
+
+constexpr size_t kPhatBudget = size_t(4) << 30;   // bytes of Phat per image chunk
+
+struct BwdLayout {
+    int chunk;   // images per chunk
+    size_t off_phat, off_sum, off_kappa, off_gBt, off_gAt, off_gBpsi, off_gApsi, off_ph64, off_part, total;
+};
+
+BwdLayout bwd_layout(const radsvd_plan *p) {
+    const size_t Qs = p->Qc, T = p->T, H = p->H, K = p->K, Q = p->Q;
+    const size_t na = p->n_img, nb = p->n_tgt, NBT = nb * T;
+    BwdLayout L{};
+    const size_t per_img = Qs * NBT * sizeof(cx<double>);
+    size_t ch = kPhatBudget / per_img;
+    if (ch < 1) ch = 1;
+    if (ch > na) ch = na;
+    if (ch > 65535) ch = 65535;
+    L.chunk = (int)ch;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t o = off;
+        off = align_up(off + b, 256);
+        return o;
+    };
+    L.off_phat = take(ch * per_img);                        // [chunk][Qs][NBT]
+    L.off_sum = take(ch * nb * sizeof(double));             // [chunk][nb]
+    L.off_kappa = take(ch * sizeof(double));                // [chunk]
+    L.off_gBt = take(NBT * Qs * H * sizeof(cx<double>));    // [NBT][Qs][H]
+    L.off_gAt = take(na * Qs * H * sizeof(cx<double>));     // [na][Qs][H]
+    L.off_gBpsi = take(NBT * H * Q * sizeof(cx<double>));   // [NBT][H][Q]
+    L.off_gApsi = take(na * H * Q * sizeof(cx<double>));    // [na][H][Q]
+    L.off_ph64 = take(T * K * Q * sizeof(cx<double>));      // [T][K][Q]
+    L.off_part = take((na + nb) * K * H * sizeof(double));  // [na + nb][K][H]
+    L.total = off;
+    return L;
+}
+
+template <typename R>
+__device__ __forceinline__ cx<double> up(const cx<R> &v) {
+    return cx<double>{(double)v.re, (double)v.im};
+}
+
+__device__ __forceinline__ void fill_twiddles(cx<double> *tw, int Q) {
+    for (int i = threadIdx.x; i < Q; i += blockDim.x) {
+        double s, c;
+        sincospi(-2.0 * (double)i / (double)Q, &s, &c);
+        tw[i] = cx<double>{c, s};
+    }
+}
+
+// phi_t[r][j] = exp(-i k_r (dx cos psi_j + dy sin psi_j)) in FP64
+__global__ void k_bwd_phase(const double *d_k, const double *d_delta, int K, int Q, int T, cx<double> *ph) {
+    const int total = T * K * Q;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int j = i % Q, r = (i / Q) % K, t = i / (Q * K);
+        double s, c;
+        sincospi(2.0 * (double)j / (double)Q, &s, &c);
+        const double arg = d_k[r] * (d_delta[2 * t] * c + d_delta[2 * t + 1] * s);
+        double ps, pc;
+        sincos(arg, &ps, &pc);
+        ph[i] = cx<double>{pc, -ps};
+    }
+}
+
+// One workgroup per pair (a0 + blockIdx.y, blockIdx.x): for every t, the
+// landscape X (contraction + FFT, FP64), Pt = exp(s Re X - c_a), the
+// transform of Pt at the stored q, and the pair's sum of Pt over (t, m).
+template <typename R>
+__global__ __launch_bounds__(256) void k_bwd_phat(const cx<R> *__restrict__ Ag, const cx<R> *__restrict__ Bg,
+                                                  int a0, int n_tgt, int T, int H, int Q, int Qs, int herm,
+                                                  double s2, const float *__restrict__ lse_img,
+                                                  cx<double> *__restrict__ Phat, double *__restrict__ psum) {
+    __shared__ double red[256];
+    extern __shared__ unsigned char smem_raw[];
+    cx<double> *tw = reinterpret_cast<cx<double> *>(smem_raw);
+    cx<double> *X = tw + Q;
+    cx<double> *Pb = X + Q;
+    const int b = blockIdx.x, al = blockIdx.y, a = a0 + al;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int M = Q / 2;
+    const size_t NBT = (size_t)n_tgt * T;
+    fill_twiddles(tw, Q);
+    const FftPlan pl = fft_make_plan(Q);
+    const double ca = (double)lse_img[a];
+    double mysum = 0.0;
+    for (int t = 0; t < T; ++t) {
+        __syncthreads();
+        const cx<R> *Aq = Ag + (size_t)a * Qs * H;
+        const cx<R> *Bq = Bg + ((size_t)b * T + t) * Qs * H;
+        for (int q = tid; q < Qs; q += nt) {
+            double re = 0.0, im = 0.0;
+            for (int h = 0; h < H; ++h) {
+                const cx<double> x = up(Aq[(size_t)q * H + h]), y = up(Bq[(size_t)q * H + h]);
+                re += x.re * y.re + x.im * y.im;   // conj(x) y
+                im += x.re * y.im - x.im * y.re;
+            }
+            X[q] = cx<double>{re, im};
+            if (herm && q > 0 && q < M) X[Q - q] = cx<double>{re, -im};
+        }
+        __syncthreads();
+        lds_fft_dif(X, 1, Q, pl, tw);   // X[pos(m)] = sum_q S[q] W^{qm}
+        for (int m = tid; m < Q; m += nt) {
+            const double pt = exp(s2 * X[fft_pos(m, pl)].re - ca);
+            mysum += pt;
+            Pb[m] = cx<double>{pt, 0.0};
+        }
+        __syncthreads();
+        lds_fft_dif(Pb, 1, Q, pl, tw);   // sum_m P[m] W^{qm}; Phat = its conjugate
+        cx<double> *out = Phat + (size_t)al * Qs * NBT + (size_t)b * T + t;
+        for (int q = tid; q < Qs; q += nt) {
+            const cx<double> v = Pb[fft_pos(q, pl)];
+            out[(size_t)q * NBT] = cx<double>{v.re, -v.im};
+        }
+    }
+    red[tid] = mysum;
+    __syncthreads();
+    if (tid == 0) {
+        double sacc = 0.0;
+        for (int i = 0; i < nt; ++i) sacc += red[i];
+        psum[(size_t)al * n_tgt + b] = sacc;
+    }
+}
+
+// kappa[a] = g[a] s / sum_{b,t,m} Pt  (= g[a] s exp(c_a - lse_img[a]), exact lse)
+__global__ void k_bwd_kappa(const double *__restrict__ psum, const float *__restrict__ glse, int a0, int na_chunk,
+                            int n_tgt, double s2, double *__restrict__ kappa) {
+    const int al = blockIdx.x * blockDim.x + threadIdx.x;
+    if (al >= na_chunk) return;
+    double sacc = 0.0;
+    for (int b = 0; b < n_tgt; ++b) sacc += psum[(size_t)al * n_tgt + b];
+    kappa[al] = (double)glse[a0 + al] * s2 / sacc;
+}
+
+// g_bt[bt][q][h] (+)= sum_{a in chunk} at[a][q][h] Phat[a][q][bt]; one workgroup
+// per (64 columns bt, q); rank h <= 32 in 4 groups of 8 per thread.
+template <typename R>
+__global__ __launch_bounds__(256) void k_bwd_gBt(const cx<R> *__restrict__ Ag, const cx<double> *__restrict__ Phat,
+                                                 const double *__restrict__ kappa, int a0, int na_chunk, int NBT,
+                                                 int Qs, int H, int accumulate, cx<double> *__restrict__ gBt) {
+    __shared__ cx<double> sP[16][64];
+    __shared__ cx<double> sA[16][kMaxH];
+    const int q = blockIdx.y, bt0 = blockIdx.x * 64;
+    const int tid = threadIdx.x, bl = tid & 63, hg = tid >> 6;
+    cx<double> acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = cx<double>{0.0, 0.0};
+    for (int c0 = 0; c0 < na_chunk; c0 += 16) {
+        for (int e = tid; e < 16 * 64; e += 256) {
+            const int aa = e >> 6, bb = e & 63;
+            cx<double> v = {0.0, 0.0};
+            if (c0 + aa < na_chunk && bt0 + bb < NBT)
+                v = cscale(Phat[((size_t)(c0 + aa) * Qs + q) * NBT + bt0 + bb], kappa[c0 + aa]);
+            sP[aa][bb] = v;
+        }
+        for (int e = tid; e < 16 * H; e += 256) {
+            const int aa = e / H, h = e - aa * H;
+            cx<double> v = {0.0, 0.0};
+            if (c0 + aa < na_chunk) v = up(Ag[((size_t)(a0 + c0 + aa) * Qs + q) * H + h]);
+            sA[aa][h] = v;
+        }
+        __syncthreads();
+        for (int aa = 0; aa < 16; ++aa) {
+            const cx<double> pv = sP[aa][bl];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int h = hg + 4 * i;
+                if (h < H) acc[i] = cadd(acc[i], cmul(sA[aa][h], pv));
+            }
+        }
+        __syncthreads();
+    }
+    const int bt = bt0 + bl;
+    if (bt < NBT) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int h = hg + 4 * i;
+            if (h < H) {
+                cx<double> *o = gBt + ((size_t)bt * Qs + q) * H + h;
+                *o = accumulate ? cadd(*o, acc[i]) : acc[i];
+            }
+        }
+    }
+}
+
+// g_at[a][q][h] = sum_bt conj(Phat[a][q][bt]) bt[bt][q][h] for the chunk's
+// images; one workgroup per (64 images, q).
+template <typename R>
+__global__ __launch_bounds__(256) void k_bwd_gAt(const cx<R> *__restrict__ Bg, const cx<double> *__restrict__ Phat,
+                                                 const double *__restrict__ kappa, int a0, int na_chunk, int NBT,
+                                                 int Qs, int H, cx<double> *__restrict__ gAt) {
+    __shared__ cx<double> sP[64][17];
+    __shared__ cx<double> sB[16][kMaxH];
+    const int q = blockIdx.y, al0 = blockIdx.x * 64;
+    const int tid = threadIdx.x, al = tid & 63, hg = tid >> 6;
+    cx<double> acc[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = cx<double>{0.0, 0.0};
+    for (int c0 = 0; c0 < NBT; c0 += 16) {
+        for (int e = tid; e < 64 * 16; e += 256) {
+            const int aa = e >> 4, bb = e & 15;
+            cx<double> v = {0.0, 0.0};
+            if (al0 + aa < na_chunk && c0 + bb < NBT) v = Phat[((size_t)(al0 + aa) * Qs + q) * NBT + c0 + bb];
+            sP[aa][bb] = v;
+        }
+        for (int e = tid; e < 16 * H; e += 256) {
+            const int bb = e / H, h = e - bb * H;
+            cx<double> v = {0.0, 0.0};
+            if (c0 + bb < NBT) v = up(Bg[((size_t)(c0 + bb) * Qs + q) * H + h]);
+            sB[bb][h] = v;
+        }
+        __syncthreads();
+        for (int bb = 0; bb < 16; ++bb) {
+            const cx<double> pv = cconj(sP[al][bb]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int h = hg + 4 * i;
+                if (h < H) acc[i] = cadd(acc[i], cmul(pv, sB[bb][h]));
+            }
+        }
+        __syncthreads();
+    }
+    if (al0 + al < na_chunk) {
+        const double kp = kappa[al0 + al];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int h = hg + 4 * i;
+            if (h < H) gAt[((size_t)(a0 + al0 + al) * Qs + q) * H + h] = cscale(acc[i], kp);
+        }
+    }
+}
+
+// psi-space ring gradients: G[n][q][h] (stored q) -> Gpsi[n][h][j] =
+// Q^{-1/2} sum_q exp(+2 pi i q j / Q) G[q], the full spectrum rebuilt from the
+// Hermitian half when herm.  One workgroup per row n; HC rank rows per pass.
+__global__ __launch_bounds__(256) void k_bwd_inv_rings(const cx<double> *__restrict__ G, int H, int Q, int Qs,
+                                                       int herm, int HC, cx<double> *__restrict__ Gpsi) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<double> *tw = reinterpret_cast<cx<double> *>(smem_raw);
+    cx<double> *buf = tw + Q;
+    const int n = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int M = Q / 2;
+    fill_twiddles(tw, Q);
+    const FftPlan pl = fft_make_plan(Q);
+    const double sc = 1.0 / sqrt((double)Q);
+    const cx<double> *Gn = G + (size_t)n * Qs * H;
+    for (int h0 = 0; h0 < H; h0 += HC) {
+        const int hc = min(HC, H - h0);
+        __syncthreads();
+        for (int i = tid; i < hc * Q; i += nt) {
+            const int hh = i / Q, q = i - hh * Q;
+            cx<double> v;
+            if (!herm || q <= M) {
+                v = Gn[(size_t)q * H + h0 + hh];
+            } else {
+                const int qq = Q - q;
+                const cx<double> u = Gn[(size_t)qq * H + h0 + hh];
+                v = (qq & 1) ? cx<double>{-u.re, u.im} : cx<double>{u.re, -u.im};   // (-1)^qq conj(u)
+            }
+            buf[hh * Q + q] = cconj(v);
+        }
+        __syncthreads();
+        lds_fft_dif(buf, hc, Q, pl, tw);
+        for (int i = tid; i < hc * Q; i += nt) {
+            const int hh = i / Q, j = i - hh * Q;
+            const cx<double> v = buf[hh * Q + fft_pos(j, pl)];
+            Gpsi[((size_t)n * H + h0 + hh) * Q + j] = cx<double>{v.re * sc, -v.im * sc};
+        }
+    }
+}
+
+// dL/dBhat[b][r][j] = eta_r sum_t conj(phi_t[r][j]) sum_h U[r][h] g_Br[b][t][h][j]
+template <typename R>
+__global__ __launch_bounds__(256) void k_bwd_gBhat(const cx<double> *__restrict__ gBpsi, const double *__restrict__ U,
+                                                   const double *__restrict__ eta, const cx<double> *__restrict__ ph,
+                                                   int K, int H, int Q, int T, cx<R> *__restrict__ gB) {
+    const int b = blockIdx.x, r = blockIdx.y;
+    const double er = eta[r];
+    for (int j = threadIdx.x; j < Q; j += blockDim.x) {
+        cx<double> acc = {0.0, 0.0};
+        for (int t = 0; t < T; ++t) {
+            const cx<double> *g = gBpsi + ((size_t)b * T + t) * H * Q + j;
+            cx<double> s = {0.0, 0.0};
+            for (int h = 0; h < H; ++h) {
+                const double u = U[(size_t)r * K + h];
+                const cx<double> v = g[(size_t)h * Q];
+                s.re += u * v.re;
+                s.im += u * v.im;
+            }
+            acc = cadd(acc, cmul(cconj(ph[((size_t)t * K + r) * Q + j]), s));
+        }
+        gB[((size_t)b * K + r) * Q + j] = cx<R>{(R)(er * acc.re), (R)(er * acc.im)};
+    }
+}
+
+// part[n][r][h] = sum_t sum_j Re(conj(Gpsi[n][t][h][j]) eta_r phi_t[r][j] X[n][r][j])
+// (phi = 1 when ph is null).  One workgroup per item n; j in chunks of 16.
+template <typename R>
+__global__ __launch_bounds__(256) void k_bwd_gU_part(const cx<double> *__restrict__ Gpsi, const cx<R> *__restrict__ Xp,
+                                                     const double *__restrict__ eta, const cx<double> *__restrict__ ph,
+                                                     int K, int H, int Q, int T, double *__restrict__ part) {
+    __shared__ cx<double> sY[kMaxK][17];
+    __shared__ cx<double> sG[kMaxH][17];
+    const int n = blockIdx.x, tid = threadIdx.x;
+    const int nout = K * H;
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    for (int t = 0; t < T; ++t) {
+        for (int j0 = 0; j0 < Q; j0 += 16) {
+            __syncthreads();
+            for (int e = tid; e < K * 16; e += 256) {
+                const int r = e >> 4, jj = e & 15, j = j0 + jj;
+                cx<double> y = {0.0, 0.0};
+                if (j < Q) {
+                    y = up(Xp[((size_t)n * K + r) * Q + j]);
+                    if (ph) y = cmul(ph[((size_t)t * K + r) * Q + j], y);
+                    y = cscale(y, eta[r]);
+                }
+                sY[r][jj] = y;
+            }
+            for (int e = tid; e < H * 16; e += 256) {
+                const int h = e >> 4, jj = e & 15, j = j0 + jj;
+                sG[h][jj] = (j < Q) ? Gpsi[(((size_t)n * T + t) * H + h) * Q + j] : cx<double>{0.0, 0.0};
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int o = tid + 256 * i;
+                if (o < nout) {
+                    const int r = o / H, h = o - r * H;
+                    double s = 0.0;
+                    for (int jj = 0; jj < 16; ++jj) s += sG[h][jj].re * sY[r][jj].re + sG[h][jj].im * sY[r][jj].im;
+                    acc[i] += s;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int o = tid + 256 * i;
+        if (o < nout) part[(size_t)n * nout + o] = acc[i];
+    }
+}
+
+// gU[r][h] = sum_n part[n][r][h] in item order (column h of U's [K][H] block)
+__global__ void k_bwd_gU_reduce(const double *__restrict__ part, int n_items, int K, int H, double *__restrict__ gU) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= K * H) return;
+    double s = 0.0;
+    for (int n = 0; n < n_items; ++n) s += part[(size_t)n * K * H + o];
+    gU[o] = s;
+}
+
+template <typename R>
+hipError_t run_backward(const radsvd_plan *p, float inv_s2, const float *lse_img, const float *glse, void *gB_out,
+                        double *gU_out, void *ws, hipStream_t s) {
+    const BwdLayout L = bwd_layout(p);
+    char *w = reinterpret_cast<char *>(ws);
+    cx<double> *Phat = reinterpret_cast<cx<double> *>(w + L.off_phat);
+    double *psum = reinterpret_cast<double *>(w + L.off_sum);
+    double *kappa = reinterpret_cast<double *>(w + L.off_kappa);
+    cx<double> *gBt = reinterpret_cast<cx<double> *>(w + L.off_gBt);
+    cx<double> *gAt = reinterpret_cast<cx<double> *>(w + L.off_gAt);
+    cx<double> *gBpsi = reinterpret_cast<cx<double> *>(w + L.off_gBpsi);
+    cx<double> *gApsi = reinterpret_cast<cx<double> *>(w + L.off_gApsi);
+    cx<double> *ph = reinterpret_cast<cx<double> *>(w + L.off_ph64);
+    double *part = reinterpret_cast<double *>(w + L.off_part);
+    const cx<R> *Ag = reinterpret_cast<const cx<R> *>(p->Ag);
+    const cx<R> *Bg = reinterpret_cast<const cx<R> *>(p->Bg);
+    const int K = p->K, Q = p->Q, H = p->H, T = p->T, Qs = p->Qc, na = p->n_img, nb = p->n_tgt;
+    const int NBT = nb * T;
+    const bool want_U = gU_out != nullptr;
+
+    hipLaunchKernelGGL(k_bwd_phase, dim3((T * K * Q + 255) / 256 < 4096 ? (T * K * Q + 255) / 256 : 4096), dim3(256),
+                       0, s, p->d_k, p->d_delta, K, Q, T, ph);
+    const size_t sh_phat = (size_t)3 * Q * sizeof(cx<double>);
+    for (int a0 = 0; a0 < na; a0 += L.chunk) {
+        const int ca = min(L.chunk, na - a0);
+        hipLaunchKernelGGL(k_bwd_phat<R>, dim3(nb, ca), dim3(256), sh_phat, s, Ag, Bg, a0, nb, T, H, Q, Qs,
+                           p->herm, (double)inv_s2, lse_img, Phat, psum);
+        hipLaunchKernelGGL(k_bwd_kappa, dim3((ca + 255) / 256), dim3(256), 0, s, psum, glse, a0, ca, nb,
+                           (double)inv_s2, kappa);
+        hipLaunchKernelGGL(k_bwd_gBt<R>, dim3((NBT + 63) / 64, Qs), dim3(256), 0, s, Ag, Phat, kappa, a0, ca, NBT,
+                           Qs, H, a0 > 0 ? 1 : 0, gBt);
+        if (want_U)
+            hipLaunchKernelGGL(k_bwd_gAt<R>, dim3((ca + 63) / 64, Qs), dim3(256), 0, s, Bg, Phat, kappa, a0, ca,
+                               NBT, Qs, H, gAt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int HC = max(1, min(H, (int)((size_t)60 * 1024 / ((size_t)Q * sizeof(cx<double>))) - 1));
+    const size_t sh_inv = (size_t)(1 + HC) * Q * sizeof(cx<double>);
+    hipLaunchKernelGGL(k_bwd_inv_rings, dim3(NBT), dim3(256), sh_inv, s, gBt, H, Q, Qs, p->herm, HC, gBpsi);
+    if (gB_out)
+        hipLaunchKernelGGL(k_bwd_gBhat<R>, dim3(nb, K), dim3(256), 0, s, gBpsi, p->U, p->d_eta, ph, K, H, Q, T,
+                           reinterpret_cast<cx<R> *>(gB_out));
+    if (want_U) {
+        hipLaunchKernelGGL(k_bwd_inv_rings, dim3(na), dim3(256), sh_inv, s, gAt, H, Q, Qs, p->herm, HC, gApsi);
+        hipLaunchKernelGGL(k_bwd_gU_part<R>, dim3(na), dim3(256), 0, s, gApsi,
+                           reinterpret_cast<const cx<R> *>(p->A_polar), p->d_eta, (const cx<double> *)nullptr, K, H,
+                           Q, 1, part);
+        hipLaunchKernelGGL(k_bwd_gU_part<R>, dim3(nb), dim3(256), 0, s, gBpsi,
+                           reinterpret_cast<const cx<R> *>(p->B_polar), p->d_eta, ph, K, H, Q, T,
+                           part + (size_t)na * K * H);
+        hipLaunchKernelGGL(k_bwd_gU_reduce, dim3((K * H + 255) / 256), dim3(256), 0, s, part, na + nb, K, H, gU_out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t backward_bytes(const radsvd_plan *p) { return bwd_layout(p).total; }
+
+hipError_t launch_backward(const radsvd_plan *p, float inv_s2, const float *lse_img, const float *glse, void *gB,
+                           double *gU, void *ws, hipStream_t s) {
+    if (p->prec == RADSVD_FP64) return run_backward<double>(p, inv_s2, lse_img, glse, gB, gU, ws, s);
+    return run_backward<float>(p, inv_s2, lse_img, glse, gB, gU, ws, s);
 }
 
 }  // namespace radsvd

@@ -180,10 +180,18 @@ size_t align_batched_workspace(int n_jobs);
 /*
  * Many independent alignment jobs (each prepared with its own plan: its own
  * grid, rank, translations and counts) in one persistent launch with
- * RADSVD_OUT_BEST outputs.  Every plan must use the same precision and be
- * Hermitian.  Results are bitwise equal to one align_pairs call per job with
- * the same tile choice.  The launch contains no hipMemsetAsync and can be
- * captured in a HIP graph.
+ * RADSVD_OUT_BEST outputs: section 3.5's per-pair step for every job, the
+ * tiles of all jobs drawn from one work queue.  Every plan must be Hermitian,
+ * FP32, BF16 or bf16x3 (all the same precision and product count), with
+ * Q in {128, 192, 256, 384, 512}.  Results are bitwise equal to one
+ * align_pairs call per job.  batch_ws (device, 256-byte aligned,
+ * >= align_batched_workspace(n_jobs) bytes) receives the job table and the
+ * queue; the sequence contains no hipMemsetAsync and no host memory is read
+ * at run time, so it can be captured in a HIP graph.  The plans' workspaces
+ * and the outputs must stay valid until the launch completes; calls that
+ * share one batch_ws must not overlap.  Errors: RADSVD_ERR_INVALID_ARG (NULL
+ * pointers, n_jobs outside [1, 4096], mixed precisions), RADSVD_ERR_UNSUPPORTED
+ * (a plan off the supported set), RADSVD_ERR_WORKSPACE.
  */
 radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs,
                                   const radsvd_job_out *outs, void *batch_ws, size_t batch_bytes,
@@ -195,10 +203,14 @@ radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs,
 radsvd_status align_get_U(const radsvd_plan *plan, double *U_dev, double *lambda_dev,
                           void *stream);
 
-/* Kernel-tile selection for align_pairs / align_pairs_batched (autotuner hook).
- * tile_b: targets per workgroup tile of the fast Hermitian path, 16 or 32
- * (0 = library default).  Applies to later calls with this plan. */
-radsvd_status align_set_tile(radsvd_plan *plan, int tile_b);
+/* Tile-order selection for align_pairs / align_pairs_batched (autotuner hook).
+ * The fast Hermitian path computes tiles of 8 images x 16 targets; `band`
+ * is the number of image tiles each XCD walks before the target tile
+ * advances (1, 2, 4, 8 or 16; 0 = the default, 8).  It changes the order in
+ * which tiles run, and so the operand reuse in each XCD's L2, never the
+ * results.  Applies to later calls with this plan.  Errors:
+ * RADSVD_ERR_INVALID_ARG for a NULL plan or another value. */
+radsvd_status align_set_tile(radsvd_plan *plan, int band);
 
 void align_plan_destroy(radsvd_plan *plan);
 

@@ -21,7 +21,7 @@ __all__ = [
     "align_prepare_workspace", "align_prepare", "align_pairs", "align_backward_workspace",
     "align_pairs_backward", "align_batched_workspace", "align_pairs_batched", "align_get_U",
     "align_set_tile", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
-    "PRECISIONS", "RadialAlignLSE",
+    "PRECISIONS", "RadialAlignLSE", "pairs_batched",
 ]
 
 FP64, FP32, BF16, BF16X3 = 0, 1, 2, 3
@@ -181,8 +181,8 @@ def align_get_U(plan, U_dev=None, lambda_dev=None, stream=None):
     _check(_load().align_get_U(plan, _ptr(U_dev), _ptr(lambda_dev), _stream(stream)))
 
 
-def align_set_tile(plan, tile_b: int):
-    _check(_load().align_set_tile(plan, int(tile_b)))
+def align_set_tile(plan, band: int):
+    _check(_load().align_set_tile(plan, int(band)))
 
 
 def align_plan_destroy(plan):
@@ -220,6 +220,7 @@ class Plan:
         self.U_in = None if U is None else U.to(device=A_polar.device, dtype=torch.float64).contiguous()
         self.handle = align_prepare(self.problem, n_img, A_polar, n_tgt, B_polar, self.U_in, self.ws, stream)
         self.device = A_polar.device
+        self.band = 0
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -257,8 +258,10 @@ class Plan:
         align_get_U(self.handle, U, lam, stream)
         return U, lam
 
-    def set_tile(self, tile_b: int):
-        align_set_tile(self.handle, tile_b)
+    def set_tile(self, band: int):
+        """Tile order of the fast path: image tiles per XCD band (0 = default)."""
+        align_set_tile(self.handle, band)
+        self.band = band
 
     def backward(self, inv_sigma2: float, lse_img: torch.Tensor, grad_lse_img: torch.Tensor,
                  want_B: bool = True, want_U: bool = True, stream=None):
@@ -308,3 +311,19 @@ class RadialAlignLSE(torch.autograd.Function):
         if gU is not None:
             gU = gU.to(ctx.U_dtype)
         return None, gB, gU, None, None, None, None, None, None
+
+
+def pairs_batched(plans, outputs=None, batch_ws=None, stream=None):
+    """Best (score, m, t) of every job in one persistent launch
+    (``align_pairs_batched``).  ``plans``: list of ``Plan``; returns (or fills)
+    one dict per job with best_score / best_m / best_t."""
+    dev = plans[0].device
+    if outputs is None:
+        outputs = [{"best_score": torch.empty((p.n_img, p.n_tgt), dtype=torch.float32, device=dev),
+                    "best_m": torch.empty((p.n_img, p.n_tgt), dtype=torch.int32, device=dev),
+                    "best_t": torch.empty((p.n_img, p.n_tgt), dtype=torch.int32, device=dev)} for p in plans]
+    if batch_ws is None:
+        batch_ws = torch.empty(align_batched_workspace(len(plans)), dtype=torch.uint8, device=dev)
+    align_pairs_batched([p.handle for p in plans],
+                        [(o["best_score"], o["best_m"], o["best_t"]) for o in outputs], batch_ws, stream)
+    return outputs

@@ -171,7 +171,7 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
     p->na_pad = L.na_pad;
     p->nb_pad = L.nb_pad;
     p->user_U = U_in != nullptr;
-    p->tile_b = 0;
+    p->band = 0;
     p->ws = reinterpret_cast<char *>(ws);
     p->ws_bytes = ws_bytes;
     p->A_polar = A_polar;
@@ -315,8 +315,12 @@ radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs, c
             return fail(RADSVD_ERR_INVALID_ARG, "outs[%d] has a NULL pointer", i);
         if (prec < 0) prec = p->prec;
         if (p->prec != prec) return fail(RADSVD_ERR_INVALID_ARG, "plans differ in precision");
-        if (!fast_path_supported(p, RADSVD_OUT_BEST))
-            return fail(RADSVD_ERR_UNSUPPORTED, "plans[%d] is not on the fast Hermitian path", i);
+        if (p->prec == RADSVD_BF16X3 && p->products != plans[0]->products)
+            return fail(RADSVD_ERR_INVALID_ARG, "plans differ in the bf16x3 product count");
+        if (!batched_supported(p))
+            return fail(RADSVD_ERR_UNSUPPORTED,
+                        "plans[%d]: the batched launch needs a Hermitian FP32/BF16/bf16x3 plan with "
+                        "Q in {128, 192, 256, 384, 512} (got Q=%d)", i, p->Q);
     }
     const size_t need = batched_bytes(n_jobs);
     if (!batch_ws) return fail(RADSVD_ERR_WORKSPACE, "batch workspace is NULL");
@@ -337,11 +341,11 @@ radsvd_status align_get_U(const radsvd_plan *p, double *U_dev, double *lambda_de
     return dev_check(e, "align_get_U copy");
 }
 
-radsvd_status align_set_tile(radsvd_plan *p, int tile_b) {
+radsvd_status align_set_tile(radsvd_plan *p, int band) {
     g_err[0] = 0;
     if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
-    if (!fast_tile_ok(tile_b)) return fail(RADSVD_ERR_INVALID_ARG, "tile_b=%d not available", tile_b);
-    p->tile_b = tile_b;
+    if (!fast_band_ok(band)) return fail(RADSVD_ERR_INVALID_ARG, "band=%d not one of 0, 1, 2, 4, 8, 16", band);
+    p->band = band;
     return RADSVD_OK;
 }
 

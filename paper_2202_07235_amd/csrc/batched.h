@@ -1,0 +1,141 @@
+// Persistent multi-job launch of the fused Hermitian pair kernel.
+//
+// Many independent alignment jobs, each with its own angle count Q, rank H,
+// translations and image/target counts, run in one launch: every job's tiles
+// (8 images x 16 targets, all translations) make up its work items, one tile
+// per item, or several consecutive ones for jobs whose tiles are cheap (so
+// that the per-item queue and call overhead stays small).  Items are
+// ordered by decreasing cost per item (the long ones start first) and, within
+// a job, in the job's band order; the sequence is cut into chunks of kChunk
+// consecutive items dealt round-robin to the 8 XCDs, one queue per XCD.  A
+// fixed grid of workgroups (one per compute unit) takes items from its own
+// XCD's queue with an atomic counter, so the workgroups resident on one XCD
+// run neighbouring tiles that share operands in its L2; an XCD whose queue is
+// empty takes items from the others.  Each item runs the tile body of its
+// job's (Q, H8) specialisation.  The job table lives in the batch
+// workspace; it is written by a kernel (job data passed by value), so the
+// whole sequence needs no host memory at run time and can be captured in a
+// HIP graph.
+#pragma once
+#include "pairs_fast.h"
+
+namespace radsvd {
+namespace fastk {
+
+// angle counts and ranks of the batched kernel
+constexpr int kBatchQ[5] = {128, 192, 256, 384, 512};
+constexpr int kBatchH8[4] = {8, 16, 24, 32};
+
+struct BatchJob {
+    Args a;        // fast-path arguments of the job (BEST output)
+    int qi, hi;    // indices into kBatchQ, kBatchH8
+    int item0;     // first work item of the job
+    int group;     // tiles per work item (cheap tiles are grouped)
+};
+
+constexpr int kChunk = 128;   // consecutive items per XCD chunk
+
+struct BatchHeader {
+    int n_jobs;
+    int total;                  // work items
+    int count[8];               // items in each XCD's queue
+    unsigned int next[8];       // queue positions
+};
+
+constexpr int kTableChunk = 32;   // jobs per table-writer launch (kernel argument space)
+
+struct TableChunk {
+    int first, n, n_jobs, total;
+    int count[8];
+    BatchJob jobs[kTableChunk];
+};
+
+// Job arguments are read through the constant address space: the table is
+// not written during the launch, so the compiler may reload its fields where
+// it would otherwise keep them in (and spill) registers.
+typedef const __attribute__((address_space(4))) Args CArgs;
+typedef const __attribute__((address_space(4))) BatchJob CJob;
+
+// One (Q, H8) specialisation per function: each gets the register allocation
+// of the single-job kernel, not the union of all of them.
+// tiles lin0 .. lin0 + cnt - 1 of a job, in its band order
+template <int Q, int KIND, int H8>
+__device__ __attribute__((noinline)) void tile_h(CArgs &a, int lin0, int cnt, unsigned char *sm) {
+    const int nTA = __builtin_amdgcn_readfirstlane(a.nTA), nTB = __builtin_amdgcn_readfirstlane(a.nTB);
+    const int band = __builtin_amdgcn_readfirstlane(a.band);
+    for (int k = 0; k < cnt; ++k) {
+        int ta, tb;
+        band_tile(lin0 + k, nTA, nTB, band, ta, tb);
+        if constexpr (KIND == 0) fast_tile<Q, 0, H8 / 8, 0>(a, ta, tb, sm);
+        else fast_tile<Q, KIND, H8 / 16, (H8 % 16) ? 1 : 0>(a, ta, tb, sm);
+    }
+}
+
+template <int Q, int KIND>
+__device__ __forceinline__ void tile_q(int hi, CArgs &a, int lin0, int cnt, unsigned char *sm) {
+    switch (hi) {
+    case 0: tile_h<Q, KIND, 8>(a, lin0, cnt, sm); break;
+    case 1: tile_h<Q, KIND, 16>(a, lin0, cnt, sm); break;
+    case 2: tile_h<Q, KIND, 24>(a, lin0, cnt, sm); break;
+    default: tile_h<Q, KIND, 32>(a, lin0, cnt, sm); break;
+    }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256, 1) void k_pairs_batched(BatchHeader *hdr, const BatchJob *__restrict__ jobs_g) {
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int s_item;
+    CJob *jobs = (CJob *)jobs_g;
+    const int x0 = blockIdx.x & 7;   // workgroups are dealt to the XCDs round-robin
+    for (int qn = 0; qn < 8; ++qn) {
+      const int x = (x0 + qn) & 7;
+      for (;;) {
+        const int qcount = hdr->count[x], nj = hdr->n_jobs;
+        __syncthreads();   // s_item of the previous item has been read by every thread
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&hdr->next[x], 1u);
+        __syncthreads();
+        const int k = s_item;
+        if (k >= qcount) break;   // uniform across the workgroup: every wave leaves
+        const int item = (x + 8 * (k / kChunk)) * kChunk + k % kChunk;
+        int lo = 0, hi = nj - 1;    // last job with item0 <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].item0 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        CArgs &a = jobs[lo].a;
+        const int qi = jobs[lo].qi, hr = jobs[lo].hi, g = jobs[lo].group;
+        const int lin0 = (item - jobs[lo].item0) * g;
+        const int cnt = min(g, a.nTA * a.nTB - lin0);
+        switch (qi) {
+        case 0: tile_q<128, KIND>(hr, a, lin0, cnt, smem_raw); break;
+        case 1: tile_q<192, KIND>(hr, a, lin0, cnt, smem_raw); break;
+        case 2: tile_q<256, KIND>(hr, a, lin0, cnt, smem_raw); break;
+        case 3: tile_q<384, KIND>(hr, a, lin0, cnt, smem_raw); break;
+        default: tile_q<512, KIND>(hr, a, lin0, cnt, smem_raw); break;
+        }
+      }
+    }
+}
+
+template <int KIND>
+hipError_t launch_batched_kind(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s) {
+    static size_t attr_bytes = 0;
+    if (shmem > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_pairs_batched<KIND>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+        attr_bytes = shmem;
+    }
+    hipLaunchKernelGGL(k_pairs_batched<KIND>, dim3(grid), dim3(256), shmem, s, hdr, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_fp32(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
+hipError_t launch_batched_bf16(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
+hipError_t launch_batched_bf16x3(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
+hipError_t launch_batched_bf16x3_6(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem,
+                                   hipStream_t s);
+
+}  // namespace fastk
+}  // namespace radsvd

@@ -1,13 +1,138 @@
-// Batched persistent launch over many alignment jobs.  Not available yet.
-#include "common.h"
-#include "internal.h"
+// Host side of the persistent multi-job launch: job table, item order, launch.
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "batched.h"
 
 namespace radsvd {
 
-size_t batched_bytes(int n_jobs) { return 256 + (size_t)n_jobs * 256; }
-hipError_t launch_pairs_batched(const radsvd_plan *const *, int, const radsvd_job_out *, void *,
-                                hipStream_t) {
-    return hipErrorNotSupported;
+namespace fastk {
+
+// copies one chunk of the job table (passed by value) into the workspace;
+// the first chunk also resets the queue
+__global__ void k_batch_table(TableChunk c, BatchHeader *hdr, BatchJob *jobs) {
+    const int i = threadIdx.x;
+    if (i < c.n) jobs[c.first + i] = c.jobs[i];
+    if (c.first == 0 && i < 8) {
+        hdr->count[i] = c.count[i];
+        hdr->next[i] = 0u;
+        if (i == 0) {
+            hdr->n_jobs = c.n_jobs;
+            hdr->total = c.total;
+        }
+    }
+}
+
+}  // namespace fastk
+
+namespace {
+
+int batch_q_index(int Q) {
+    for (int i = 0; i < 5; ++i)
+        if (fastk::kBatchQ[i] == Q) return i;
+    return -1;
+}
+
+int plan_kind(const radsvd_plan *p) {
+    if (p->prec == RADSVD_FP32) return 0;
+    if (p->prec == RADSVD_BF16) return 1;
+    return p->products == 3 ? 2 : 3;
+}
+
+int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+}  // namespace
+
+size_t batched_bytes(int n_jobs) {
+    return align_up(sizeof(fastk::BatchHeader), 256) + align_up((size_t)n_jobs * sizeof(fastk::BatchJob), 256);
+}
+
+bool batched_supported(const radsvd_plan *p) {
+    return fast_path_supported(p, RADSVD_OUT_BEST) && batch_q_index(p->Q) >= 0 && p->H8 >= 8 && p->H8 <= 32;
+}
+
+hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, const radsvd_job_out *outs,
+                                void *ws, hipStream_t s) {
+    using namespace fastk;
+    const int kind = plan_kind(plans[0]);
+    // item order: decreasing cost per item (translations x angles x work per angle)
+    std::vector<int> order(n_jobs);
+    std::vector<double> cost(n_jobs);
+    int max_q = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const radsvd_plan *p = plans[i];
+        order[i] = i;
+        cost[i] = (double)p->T * p->Q * (std::log2((double)p->Q) + 0.25 * p->H8);
+        max_q = std::max(max_q, p->Q);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<BatchJob> jobs(n_jobs);
+    int total = 0;
+    for (int k = 0; k < n_jobs; ++k) {
+        const int i = order[k];
+        const radsvd_plan *p = plans[i];
+        BatchJob &J = jobs[k];
+        memset(&J, 0, sizeof(J));
+        Args &a = J.a;
+        a.Af = p->Af;
+        a.Bf = p->Bf;
+        a.n_img = p->n_img;
+        a.n_tgt = p->n_tgt;
+        a.T = p->T;
+        a.nTA = p->na_pad / kFastTA;
+        a.nTB = p->nb_pad / kFastTB;
+        a.band = p->band ? p->band : kDefaultBand;
+        a.H8 = p->H8;
+        a.nplanes = p->nplanes;
+        a.flags = RADSVD_OUT_BEST;
+        a.inv_s2 = 1.f;
+        a.best_score = outs[i].best_score;
+        a.best_m = outs[i].best_m;
+        a.best_t = outs[i].best_t;
+        a.lse_pair = nullptr;
+        J.qi = batch_q_index(p->Q);
+        J.hi = p->H8 / 8 - 1;
+        // group cheap tiles: about the work of one Q = 256, T = 9, rank-16 tile per item
+        const double ref = 9.0 * 256 * (8.0 + 4.0);
+        J.group = std::max(1, std::min(16, (int)std::lround(ref / cost[i])));
+        J.item0 = total;
+        total += (a.nTA * a.nTB + J.group - 1) / J.group;
+    }
+    // items of each XCD queue: chunks x, x + 8, x + 16, ... of kChunk items
+    int count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = 0; (long)c * kChunk < total; ++c) count[c & 7] += std::min(kChunk, total - c * kChunk);
+    char *w = reinterpret_cast<char *>(ws);
+    BatchHeader *hdr = reinterpret_cast<BatchHeader *>(w);
+    BatchJob *djobs = reinterpret_cast<BatchJob *>(w + align_up(sizeof(BatchHeader), 256));
+    for (int first = 0; first < n_jobs; first += kTableChunk) {
+        TableChunk c;
+        memset(&c, 0, sizeof(c));
+        c.first = first;
+        c.n = std::min(kTableChunk, n_jobs - first);
+        c.n_jobs = n_jobs;
+        c.total = total;
+        for (int x = 0; x < 8; ++x) c.count[x] = count[x];
+        for (int k = 0; k < c.n; ++k) c.jobs[k] = jobs[first + k];
+        hipLaunchKernelGGL(k_batch_table, dim3(1), dim3(kTableChunk), 0, s, c, hdr, djobs);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int grid = std::max(1, std::min(total, device_cus()));
+    const size_t shmem = (size_t)(16 * 128 + (max_q / 8) * 256) * sizeof(cx<float>);
+    switch (kind) {
+    case 0: return launch_batched_fp32(hdr, djobs, grid, shmem, s);
+    case 1: return launch_batched_bf16(hdr, djobs, grid, shmem, s);
+    case 2: return launch_batched_bf16x3(hdr, djobs, grid, shmem, s);
+    default: return launch_batched_bf16x3_6(hdr, djobs, grid, shmem, s);
+    }
 }
 
 }  // namespace radsvd

@@ -72,7 +72,7 @@ struct radsvd_plan {
     int nplanes; // fast operand planes (bf16: 1/2/3; fp32: 1)
     int na_pad, nb_pad;   // counts padded to the fast tile sizes
     int user_U;
-    int tile_b;
+    int band;    // image tiles per XCD band of the fast path's tile order (0 = default)
     void *stream_hint;
     char *ws;
     size_t ws_bytes;
@@ -113,7 +113,8 @@ hipError_t launch_pairs_generic(const radsvd_plan *p, int flags, float inv_s2, f
                                 hipStream_t s);
 // pairs_fast.hip
 bool fast_path_supported(const radsvd_plan *p, int flags);
-bool fast_tile_ok(int tile_b);
+bool fast_band_ok(int band);
+constexpr int kDefaultBand = 8;
 hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, float *best_score,
                              int32_t *best_m, int32_t *best_t, float *lse_pair, hipStream_t s);
 // lse.hip
@@ -125,6 +126,7 @@ hipError_t launch_backward(const radsvd_plan *p, float inv_s2, const float *lse_
 
 // batched.hip
 size_t batched_bytes(int n_jobs);
+bool batched_supported(const radsvd_plan *p);
 hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, const radsvd_job_out *outs,
                                 void *ws, hipStream_t s);
 

@@ -219,6 +219,7 @@ struct Args {
     const void *Bf;            // fast operands, targets
     int n_img, n_tgt, T;
     int nTA, nTB;              // tile counts
+    int band;                  // image tiles per XCD band (tile order only)
     int H8;
     int nplanes;
     int flags;
@@ -229,18 +230,22 @@ struct Args {
 };
 
 // tile index of workgroup `wg`: workgroups are dealt round-robin to the 8
-// XCDs; consecutive workgroups of one XCD walk an 8-row band of image tiles
-// with the target tile advancing every 8, so the XCD's concurrently resident
-// workgroups share image and target operand rows in its L2.
-__device__ __forceinline__ void tile_of(int wg, int nwg, int nTA, int nTB, int &ta, int &tb) {
+// XCDs; consecutive workgroups of one XCD walk a band of `band` image tiles
+// with the target tile advancing every `band`, so the XCD's concurrently
+// resident workgroups share image and target operand rows in its L2.
+// linear tile index -> (image tile, target tile) in bands of `band` image tiles
+__device__ __forceinline__ void band_tile(int lin, int nTA, int nTB, int band, int &ta, int &tb) {
+    const int bi = lin / (band * nTB);
+    const int rows = min(band, nTA - bi * band);
+    const int in_band = lin - bi * band * nTB;
+    ta = bi * band + in_band % rows;
+    tb = in_band / rows;
+}
+__device__ __forceinline__ void tile_of(int wg, int nwg, int nTA, int nTB, int band, int &ta, int &tb) {
     const int xcd = wg & 7;
     const int full = nwg >> 3, rem = nwg & 7;
     const int lin = xcd * full + min(xcd, rem) + (wg >> 3);
-    const int band = lin / (8 * nTB);
-    const int rows = min(8, nTA - band * 8);
-    const int in_band = lin - band * 8 * nTB;
-    ta = band * 8 + in_band % rows;
-    tb = in_band / rows;
+    band_tile(lin, nTA, nTB, band, ta, tb);
 }
 
 // Contraction precision of the fused kernel.
@@ -267,11 +272,13 @@ struct Frag {
     u32x2 bh[Prec<KIND>::NPL];
 };
 
-// Q angles; KIND contraction precision; NF, HF operand chunks per plane
-// (FP32: NF = H8 / 8 chunks of 16 depth values, HF = 0; BF16: NF = H8 / 16,
-// HF = 1 when H8 is an odd multiple of 8).
-template <int Q, int KIND, int NF, int HF>
-__global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
+// One tile (ta, tb) for all translations.  Q angles; KIND contraction
+// precision; NF, HF operand chunks per plane (FP32: NF = H8 / 8 chunks of 16
+// depth values, HF = 0; BF16: NF = H8 / 16, HF = 1 when H8 is an odd multiple
+// of 8).  Called by all 256 threads of a workgroup; smem_raw holds
+// (16 * 128 + Q / 8 * 256) complex FP32 values.  Begins and ends at a barrier.
+template <int Q, int KIND, int NF, int HF, class ArgsT>
+__device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_in, unsigned char *smem_raw) {
     constexpr int M = Q / 2;
     constexpr int L = M / 2;          // Z values per lane
     constexpr int LH = L / 2;         // in registers; the other LH in LDS
@@ -280,7 +287,6 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
     using PR = Prec<KIND>;
     static_assert(M % 16 == 0, "Q must be a multiple of 32");
 
-    extern __shared__ unsigned char smem_raw[];
     cx<float> *stage = reinterpret_cast<cx<float> *>(smem_raw);   // [16][128]
     cx<float> *upper = stage + 16 * 128;                          // [LH][256]
 
@@ -290,11 +296,22 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
     const int e = l >> 5;               // 0: even-k lane, 1: odd-k lane
     const int P = 32 * w + (l & 31);    // pair within the tile
     const int pa = P >> 4, pb = P & 15;
-    const bool do_best = args.flags & RADSVD_OUT_BEST;
-    const bool do_lse = args.flags & RADSVD_OUT_LSE;
-
-    int ta, tb;
-    tile_of(blockIdx.x, gridDim.x, args.nTA, args.nTB, ta, tb);
+    // Every scalar of the tile is workgroup-uniform.  Said explicitly, so that a
+    // caller passing them in vector registers (a function call) still gets
+    // scalar buffer descriptors and offsets instead of per-lane loops.
+    const int ta = __builtin_amdgcn_readfirstlane(ta_in), tb = __builtin_amdgcn_readfirstlane(tb_in);
+    const int flags = __builtin_amdgcn_readfirstlane(args.flags);
+    const int nT = __builtin_amdgcn_readfirstlane(args.T), nTB = __builtin_amdgcn_readfirstlane(args.nTB);
+    const float inv_s2 = __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(args.inv_s2)));
+    auto uniform_ptr = [](const void *q) {
+        const unsigned long long u = reinterpret_cast<unsigned long long>(q);
+        const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)u);
+        const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(u >> 32));
+        return reinterpret_cast<const char *>(((unsigned long long)hi << 32) | lo);
+    };
+    const char *Af = uniform_ptr(args.Af), *Bf = uniform_ptr(args.Bf);
+    const bool do_best = flags & RADSVD_OUT_BEST;
+    const bool do_lse = flags & RADSVD_OUT_LSE;
 
     // ---- MFMA operands: fragment-ordered blocks, one per (tile, q) ----
     // Lane l reads bytes [16 l, 16 l + 16) of each full chunk and [8 l, 8 l + 8)
@@ -309,7 +326,7 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
     const int vhi = (M / 2 + 7 - 2 * w) * BB;
     const int vF_lo = 16 * l + vlo, vF_hi = 16 * l + vhi;
     const int vH_lo = 8 * l + NF * 1024 + vlo, vH_hi = 8 * l + NF * 1024 + vhi;
-    const char *Abase = reinterpret_cast<const char *>(args.Af) + (size_t)ta * (M + 1) * BB;
+    const char *Abase = Af + (size_t)ta * (M + 1) * BB;
     const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
         (void *)Abase, (short)0, (M + 1) * BB, 0x00020000);
 
@@ -323,7 +340,7 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
     float run_m = -INFINITY, run_s = 0.f;
 
     auto rsrcB = [&](int t) {
-        const char *Bbase = reinterpret_cast<const char *>(args.Bf) + ((size_t)t * args.nTB + tb) * (M + 1) * BB;
+        const char *Bbase = Bf + ((size_t)t * nTB + tb) * (M + 1) * BB;
         return __builtin_amdgcn_make_buffer_rsrc((void *)Bbase, (short)0, (M + 1) * BB, 0x00020000);
     };
     // job J = 4R + j: upper (j >= 2) or lower, and its compile-time block offset
@@ -397,7 +414,7 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
     constexpr int NJ = 4 * NRP;
     FragT fr[D + 1];
 
-    for (int t = 0; t < args.T; ++t) {
+    for (int t = 0; t < nT; ++t) {
         const __amdgpu_buffer_rsrc_t rB = rsrcB(t);
         cx<float> x[LH];
         sfor<0, D>([&](auto II) {
@@ -510,7 +527,7 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
                     const cx<float> zl = x[ct_pos(LH, f)], zh = x[ct_pos(LH, f + LH / 2)];
                     mx = fmaxf(mx, fmaxf(fmaxf(zl.re, zl.im), fmaxf(zh.re, zh.im)));
                 });
-                const float s = args.inv_s2, sm = s * mx;
+                const float s = inv_s2, sm = s * mx;
                 float acc = 0.f;
                 sfor<0, LH / 2>([&](auto FF) {
                     constexpr int f = decltype(FF)::value;
@@ -573,6 +590,14 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
         }
         if (do_lse) args.lse_pair[o] = run_nan ? __builtin_nanf("") : run_m + __logf(run_s);
     }
+}
+
+template <int Q, int KIND, int NF, int HF>
+__global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
+    extern __shared__ unsigned char smem_raw[];
+    int ta, tb;
+    tile_of(blockIdx.x, gridDim.x, args.nTA, args.nTB, args.band, ta, tb);
+    fast_tile<Q, KIND, NF, HF>(args, ta, tb, smem_raw);
 }
 
 template <int Q, int KIND, int NF, int HF>

@@ -17,7 +17,7 @@ bool fast_path_supported(const radsvd_plan *p, int flags) {
     return fast_q_ok(p->Q);
 }
 
-bool fast_tile_ok(int tile_b) { return tile_b == 0 || tile_b == 16; }
+bool fast_band_ok(int band) { return band == 0 || band == 1 || band == 2 || band == 4 || band == 8 || band == 16; }
 
 hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, float *best_score,
                              int32_t *best_m, int32_t *best_t, float *lse_pair, hipStream_t s) {
@@ -30,6 +30,7 @@ hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, floa
     a.T = p->T;
     a.nTA = p->na_pad / kFastTA;
     a.nTB = p->nb_pad / kFastTB;
+    a.band = p->band ? p->band : kDefaultBand;
     a.H8 = p->H8;
     a.nplanes = p->nplanes;
     a.flags = flags;

@@ -31,7 +31,7 @@ import torch
 
 __all__ = [
     "gl_grid", "translation_grid", "blob_params", "polar_ft", "Problem",
-    "make_problem", "CONFIGS", "config",
+    "make_problem", "CONFIGS", "config", "batch_configs",
 ]
 
 
@@ -161,6 +161,24 @@ CONFIGS = {
     "diff_fd": Config("diff_fd", N=32, K=16, Q=64, n_img=16, n_tgt=8, T=9, H=8,
                       noisy_side="img"),
 }
+
+
+def batch_configs(n_jobs: int = 64, seed: int = 4000, scale: float = 1.0):
+    """Independent jobs of the batching workload: N uniform in {64, 96, 128,
+    192, 256} with K = N/2 and Q = 2N; N_A log-uniform in [128, 2048] and N_B
+    log-uniform in [64, 1024] (both multiplied by ``scale``, at least 8);
+    T uniform in {1, 9, 25}; H uniform in [8, 32]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(n_jobs):
+        N = int(rng.choice([64, 96, 128, 192, 256]))
+        na = int(round(math.exp(rng.uniform(math.log(128), math.log(2048)))))
+        nb = int(round(math.exp(rng.uniform(math.log(64), math.log(1024)))))
+        T = int(rng.choice([1, 9, 25]))
+        H = int(rng.integers(8, 33))
+        out.append(Config(f"batch{j}", N=N, K=N // 2, Q=2 * N, n_img=max(8, int(na * scale)),
+                          n_tgt=max(8, int(nb * scale)), T=T, H=H))
+    return out
 
 
 def config(name: str, **over) -> Config:

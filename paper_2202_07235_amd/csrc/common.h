@@ -134,6 +134,20 @@ __device__ __forceinline__ void dft_small(int rad, cx<R> *v) {
     }
 }
 
+template <int RAD, typename R>
+__device__ __forceinline__ void fft_butterfly(cx<R> *x, int span, int k, int tstep, int n, const cx<R> *tw) {
+    cx<R> v[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = x[r * span];
+    dft_small(RAD, v);
+    x[0] = v[0];
+#pragma unroll
+    for (int p = 1; p < RAD; ++p) {
+        const int e = (k * p * tstep) % n;
+        x[p * span] = cmul(v[p], tw[e]);
+    }
+}
+
 // In-place forward FFT (exp(-2 pi i f j / n)) of `cnt` sequences of length n
 // stored at buf + s*seq_stride; tw[i] = exp(-2 pi i i / n) for i < n.
 // All threads of the block cooperate; ends with a barrier.
@@ -154,14 +168,10 @@ __device__ void lds_fft_dif(cx<R> *buf, int cnt, int seq_stride, const FftPlan &
             const int blk = bi / span;
             const int k = bi - blk * span;
             cx<R> *x = buf + (size_t)sq * seq_stride + blk * L + k;
-            cx<R> v[4];
-            for (int r = 0; r < rad; ++r) v[r] = x[r * span];
-            dft_small(rad, v);
-            x[0] = v[0];
-            for (int p = 1; p < rad; ++p) {
-                int e = (k * p * tstep) % n;
-                x[p * span] = cmul(v[p], tw[e]);
-            }
+            // one butterfly per radix with a fixed-size register array
+            if (rad == 4) fft_butterfly<4>(x, span, k, tstep, n, tw);
+            else if (rad == 2) fft_butterfly<2>(x, span, k, tstep, n, tw);
+            else fft_butterfly<3>(x, span, k, tstep, n, tw);
         }
         __syncthreads();
         L = span;

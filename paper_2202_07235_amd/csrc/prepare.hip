@@ -8,6 +8,8 @@
 // instead of K rings cuts the FFT work by K/H.
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 
@@ -68,6 +70,65 @@ __global__ void k_ueta(const double *U, int ld, const double *eta, int K, int H,
 //                   (FP32 or bf16 planes), zero-filled beforehand, so that
 //                   padding items and ranks h in [H, H8) stay zero.
 // ---------------------------------------------------------------------------
+// Output of one item's principal rings: rows y[0..nrows) of ybuf (row
+// stride Q, psi order) are transformed in LDS, scaled by Q^{-1/2}, and
+// frequencies q < Qc of rows h0 + i are written to the generic layout and,
+// for the fast path, to the fragment-ordered operand block of (t, tile, q).
+// Called by all threads; starts with the FFT's barriers.
+template <typename R>
+__device__ void emit_rows(cx<R> *ybuf, int nrows, int h0, int n, int t, int T, int Q, int H, int Qc,
+                          const FftPlan &pl, const cx<R> *tw, cx<R> *__restrict__ G, void *__restrict__ F,
+                          int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
+    const bool fbf = f_kind != 0;
+    const int planeB = frag_plane_bytes(fbf, H8);
+    const size_t blockB = (size_t)nplanes * planeB;
+    const int f_q = (Qc == Q) ? Q : Q / 2 + 1;
+    const int tile = n / f_tile, n_in = n - tile * f_tile;
+    const R scale = (R)(1.0 / sqrt((double)Q));
+    lds_fft_dif(ybuf, nrows, Q, pl, tw);
+    for (int i = threadIdx.x; i < Qc * nrows; i += blockDim.x) {
+        const int q = i / nrows, hh = i - q * nrows;
+        const int h = h0 + hh;
+        cx<R> v = ybuf[hh * Q + fft_pos(q, pl)];
+        v.re *= scale;
+        v.im *= scale;
+        if (G) G[(((size_t)n * T + t) * Qc + q) * H + h] = v;
+        if (F) {
+            // image n_in: Re row 2 n_in = [ar | ai], Im row 2 n_in + 1 = [-ai | ar];
+            // target n_in: column [br | bi]
+            char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
+            const int r0 = is_img ? 2 * n_in : n_in;
+            const int o_re = frag_elem_offset(fbf, H8, r0, 0, h);
+            const int o_im = frag_elem_offset(fbf, H8, r0, 1, h);
+            const int o_nim = is_img ? frag_elem_offset(fbf, H8, r0 + 1, 0, h) : 0;
+            const int o_re2 = is_img ? frag_elem_offset(fbf, H8, r0 + 1, 1, h) : 0;
+            if (!fbf) {
+                *reinterpret_cast<float *>(blk + o_re) = (float)v.re;
+                *reinterpret_cast<float *>(blk + o_im) = (float)v.im;
+                if (is_img) {
+                    *reinterpret_cast<float *>(blk + o_nim) = -(float)v.im;
+                    *reinterpret_cast<float *>(blk + o_re2) = (float)v.re;
+                }
+            } else {
+                uint16_t hr[3], hi_[3];
+                split3_bf16((float)v.re, hr[0], hr[1], hr[2]);
+                split3_bf16((float)v.im, hi_[0], hi_[1], hi_[2]);
+#pragma unroll
+                for (int pl_i = 0; pl_i < 3; ++pl_i) {
+                    if (pl_i >= nplanes) break;
+                    char *pb = blk + (size_t)pl_i * planeB;
+                    *reinterpret_cast<uint16_t *>(pb + o_re) = hr[pl_i];
+                    *reinterpret_cast<uint16_t *>(pb + o_im) = hi_[pl_i];
+                    if (is_img) {
+                        *reinterpret_cast<uint16_t *>(pb + o_nim) = hi_[pl_i] ^ 0x8000u;
+                        *reinterpret_cast<uint16_t *>(pb + o_re2) = hr[pl_i];
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <typename R, int HP>
 __global__ __launch_bounds__(256) void k_rings(
     const cx<R> *__restrict__ X, int n_real, int T, const cx<R> *__restrict__ phase,
@@ -81,14 +142,6 @@ __global__ __launch_bounds__(256) void k_rings(
     const int nthreads = blockDim.x;
     cx<R> *tw = reinterpret_cast<cx<R> *>(smem_raw);             // [Q]
     cx<R> *ybuf = tw + Q;                                         // [FC][Q]
-    const bool fbf = f_kind != 0;
-    const int planeB = frag_plane_bytes(fbf, H8);
-    const size_t blockB = (size_t)nplanes * planeB;
-    const int f_q = (Qc == Q) ? Q : Q / 2 + 1;
-    const int tile = n / f_tile, n_in = n - tile * f_tile;
-    auto fblk = [&](int q) -> char * {
-        return reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
-    };
     if (n >= n_real) return;
 
     for (int i = tid; i < Q; i += nthreads) {
@@ -96,8 +149,10 @@ __global__ __launch_bounds__(256) void k_rings(
         sincospi(-2.0 * (double)i / (double)Q, &s, &c);
         tw[i] = cx<R>{(R)c, (R)s};
     }
-    const FftPlan pl = fft_make_plan(Q);
-    const R scale = (R)(1.0 / sqrt((double)Q));
+    __shared__ FftPlan spl;   // in LDS: the stage loops index it at run time
+    if (threadIdx.x == 0) spl = fft_make_plan(Q);
+    __syncthreads();
+    const FftPlan &pl = spl;
     const cx<R> *Xn = X + (size_t)n * K * Q;
     const cx<R> *ph = phase ? phase + (size_t)t * K * Q : nullptr;
     const int j0 = tid, j1 = tid + nthreads;
@@ -142,48 +197,210 @@ __global__ __launch_bounds__(256) void k_rings(
                 }
             }
             __syncthreads();
-            lds_fft_dif(ybuf, fc, Q, pl, tw);
-            for (int i = tid; i < Qc * fc; i += nthreads) {
-                const int q = i / fc, hh = i - q * fc;
-                const int h = h0 + f0 + hh;
-                cx<R> v = ybuf[hh * Q + fft_pos(q, pl)];
-                v.re *= scale;
-                v.im *= scale;
-                if (G) G[(((size_t)n * T + t) * Qc + q) * H + h] = v;
-                if (F) {
-                    // image n_in: Re row 2 n_in = [ar | ai], Im row 2 n_in + 1 = [-ai | ar];
-                    // target n_in: column [br | bi]
-                    char *blk = fblk(q);
-                    const int r0 = is_img ? 2 * n_in : n_in;
-                    const int o_re = frag_elem_offset(fbf, H8, r0, 0, h);
-                    const int o_im = frag_elem_offset(fbf, H8, r0, 1, h);
-                    const int o_nim = is_img ? frag_elem_offset(fbf, H8, r0 + 1, 0, h) : 0;
-                    const int o_re2 = is_img ? frag_elem_offset(fbf, H8, r0 + 1, 1, h) : 0;
-                    if (!fbf) {
-                        *reinterpret_cast<float *>(blk + o_re) = (float)v.re;
-                        *reinterpret_cast<float *>(blk + o_im) = (float)v.im;
-                        if (is_img) {
-                            *reinterpret_cast<float *>(blk + o_nim) = -(float)v.im;
-                            *reinterpret_cast<float *>(blk + o_re2) = (float)v.re;
-                        }
+            emit_rows<R>(ybuf, fc, h0 + f0, n, t, T, Q, H, Qc, pl, tw, G, F, f_kind, f_tile, f_ntiles, H8, nplanes,
+                         is_img);
+        }
+    }
+}
+
+// Output of the FP32 ring kernel, all H rows of ybuf at once (transformed in
+// place first).  Generic layout: one complex per thread, consecutive (q, h).
+// Fast layout: one thread per (q, fragment slot) gathers the slot's 8 (4 for
+// a half chunk) rank values, splits them into the plane format and writes
+// 16 (8) bytes per plane and row, the unit the pair kernel's lanes load.
+__device__ void emit_fast(cx<float> *ybuf, int n, int t, int T, int Q, int H, int Qc, const FftPlan &pl,
+                          const cx<float> *tw, cx<float> *__restrict__ G, void *__restrict__ F, int f_kind,
+                          int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
+    typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+    typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+    lds_fft_dif(ybuf, H, Q, pl, tw);
+    const float scale = (float)(1.0 / sqrt((double)Q));
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (G) {
+        cx<float> *Gn = G + ((size_t)n * T + t) * Qc * H;
+        for (int i = tid; i < Qc * H; i += nt) {
+            const int q = i / H, h = i - q * H;
+            const cx<float> v = ybuf[h * Q + fft_pos(q, pl)];
+            Gn[i] = cx<float>{v.re * scale, v.im * scale};
+        }
+    }
+    if (!F) return;
+    const bool fbf = f_kind != 0;
+    const int planeB = frag_plane_bytes(fbf, H8);
+    const size_t blockB = (size_t)nplanes * planeB;
+    const int f_q = (Qc == Q) ? Q : Q / 2 + 1;
+    const int tile = n / f_tile, n_in = n - tile * f_tile;
+    const int row0 = is_img ? 2 * n_in : n_in;
+    auto val = [&](int h, int pos, int c) -> float {   // c: 0 re, 1 im
+        if (h >= H) return 0.f;
+        const cx<float> v = ybuf[h * Q + pos];
+        return (c ? v.im : v.re) * scale;
+    };
+    if (fbf) {
+        const int NF = H8 / 16, HF = (H8 % 16) ? 1 : 0;
+        const int nslots = 4 * (NF + HF);
+        for (int i = tid; i < Qc * nslots; i += nt) {
+            const int q = i / nslots, sl = i - q * nslots;
+            const int chunk = sl >> 2, g = sl & 3, c = g >> 1, hsub = g & 1;
+            const bool full = chunk < NF;
+            const int nv = full ? 8 : 4;
+            const int hb = full ? 16 * chunk + 8 * hsub : 16 * NF + 4 * hsub;
+            const int pos = fft_pos(q, pl);
+            char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
+            // Re row / target column: c = 0 -> re, 1 -> im; image Im row: c = 0 -> -im, 1 -> re
+            for (int rr = 0; rr < (is_img ? 2 : 1); ++rr) {
+                uint16_t pk[3][8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    float x = 0.f;
+                    if (e < nv) x = rr == 0 ? val(hb + e, pos, c) : (c ? val(hb + e, pos, 0) : -val(hb + e, pos, 1));
+                    split3_bf16(x, pk[0][e], pk[1][e], pk[2][e]);
+                }
+                const int row = row0 + rr;
+#pragma unroll
+                for (int pl_i = 0; pl_i < 3; ++pl_i) {
+                    if (pl_i >= nplanes) break;
+                    char *pb = blk + (size_t)pl_i * planeB;
+                    if (full) {
+                        u32x4_t wv;
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) wv[d] = (unsigned)pk[pl_i][2 * d] | ((unsigned)pk[pl_i][2 * d + 1] << 16);
+                        *reinterpret_cast<u32x4_t *>(pb + chunk * 1024 + (16 * g + row) * 16) = wv;
                     } else {
-                        uint16_t hr[3], hi_[3];
-                        split3_bf16((float)v.re, hr[0], hr[1], hr[2]);
-                        split3_bf16((float)v.im, hi_[0], hi_[1], hi_[2]);
-                        for (int pl_i = 0; pl_i < nplanes; ++pl_i) {
-                            char *pb = blk + (size_t)pl_i * planeB;
-                            *reinterpret_cast<uint16_t *>(pb + o_re) = hr[pl_i];
-                            *reinterpret_cast<uint16_t *>(pb + o_im) = hi_[pl_i];
-                            if (is_img) {
-                                *reinterpret_cast<uint16_t *>(pb + o_nim) = hi_[pl_i] ^ 0x8000u;
-                                *reinterpret_cast<uint16_t *>(pb + o_re2) = hr[pl_i];
-                            }
-                        }
+                        u32x2_t wv;
+#pragma unroll
+                        for (int d = 0; d < 2; ++d) wv[d] = (unsigned)pk[pl_i][2 * d] | ((unsigned)pk[pl_i][2 * d + 1] << 16);
+                        *reinterpret_cast<u32x2_t *>(pb + NF * 1024 + (16 * g + row) * 8) = wv;
                     }
                 }
             }
         }
+    } else {
+        // FP32 chunks of 16 depth values: lane slot g holds k = 16 chunk + 4 j + g, j = 0..3
+        const int nslots = 4 * (H8 / 8);
+        for (int i = tid; i < Qc * nslots; i += nt) {
+            const int q = i / nslots, sl = i - q * nslots;
+            const int chunk = sl >> 2, g = sl & 3;
+            const int pos = fft_pos(q, pl);
+            char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
+            for (int rr = 0; rr < (is_img ? 2 : 1); ++rr) {
+                u32x4_t wv;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k = 16 * chunk + 4 * j + g;
+                    const int c = k >= H8 ? 1 : 0, h = k - c * H8;
+                    const float x = rr == 0 ? val(h, pos, c) : (c ? val(h, pos, 0) : -val(h, pos, 1));
+                    wv[j] = __float_as_uint(x);
+                }
+                *reinterpret_cast<u32x4_t *>(blk + chunk * 1024 + (16 * g + row0 + rr) * 16) = wv;
+            }
+        }
     }
+}
+
+// FP32 principal rings on the matrix cores.  Per item the recombination is
+// the real GEMM  Y[h][(j, re|im)] = sum_r Ueta[r][h] (phi_t[r][j] X[n][r][j])_{re|im}
+// with M = H (one or two 16-row blocks), N = 2 Q and depth K, on
+// v_mfma_f32_16x16x4_f32: Ueta^T is staged in LDS (lane: row h, depth
+// r = 4 ks + l / 16), each wave takes a quarter of the blocks of 16 columns
+// (8 angles, re and im) with all their accumulators live while it walks r,
+// and the lane multiplies its (r, j) sample by the translation phase before
+// feeding it.  Y goes to LDS, then emit_fast.
+template <int NCBW, bool PHASE>   // column blocks per wave (>= the work); translation phase applied
+__global__ __launch_bounds__(256) void k_rings_mfma(
+    const cx<float> *__restrict__ X, int n_real, int T, const cx<float> *__restrict__ phase,
+    const float *__restrict__ Ueta, int K, int Q, int H, int Qc, cx<float> *__restrict__ G,
+    void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
+    typedef float f32x4_t __attribute__((ext_vector_type(4)));
+    extern __shared__ unsigned char smem_raw[];
+    const int n = blockIdx.x / T;
+    const int t = blockIdx.x - n * T;
+    if (n >= n_real) return;
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    cx<float> *tw = reinterpret_cast<cx<float> *>(smem_raw);   // [Q]
+    cx<float> *ybuf = tw + Q;                                   // [16 NHB][Q]
+    for (int i = tid; i < Q; i += blockDim.x) {
+        double s, c;
+        sincospi(-2.0 * (double)i / (double)Q, &s, &c);
+        tw[i] = cx<float>{(float)c, (float)s};
+    }
+    __shared__ FftPlan spl;   // in LDS: the stage loops index it at run time
+    if (threadIdx.x == 0) spl = fft_make_plan(Q);
+    __syncthreads();
+    const FftPlan &pl = spl;
+    const int KS = (K + 3) >> 2;
+    const bool two = H > 16;
+    const int rl = l >> 4, hl = l & 15;
+    __shared__ float sU[kMaxK][33];   // Ueta[r][h], zero beyond K and H
+    for (int i = tid; i < kMaxK * 32; i += blockDim.x) {
+        const int r = i >> 5, h = i & 31;
+        sU[r][h] = (r < K && h < H) ? Ueta[(size_t)r * H + h] : 0.f;
+    }
+    __syncthreads();
+    const cx<float> *Xn = X + (size_t)n * K * Q;
+    const cx<float> *ph = PHASE ? phase + (size_t)t * K * Q : nullptr;
+    const int part = l & 1, jl = hl >> 1;
+    // wave w owns the contiguous column blocks [w NCBW, (w + 1) NCBW) (16 columns =
+    // 8 angles each) and keeps all their accumulators while it walks the depth r;
+    // out-of-range rows and angles read a valid address and feed a zero
+    const int NCB = (2 * Q + 15) / 16;
+    const int cb0 = w * NCBW;
+    f32x4_t acc0[NCBW], acc1[NCBW];
+#pragma unroll
+    for (int i = 0; i < NCBW; ++i) {
+        acc0[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        acc1[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    // samples of depth step ks are loaded one step ahead (explicit double buffer)
+    cx<float> xc[NCBW], pc[NCBW];
+    auto fetch = [&](int ks, cx<float> (&xv)[NCBW], cx<float> (&pv)[NCBW]) {
+        const size_t rb = (size_t)min(4 * ks + rl, K - 1) * Q;
+#pragma unroll
+        for (int i = 0; i < NCBW; ++i) {
+            const size_t idx = rb + min((cb0 + i) * 8 + jl, Q - 1);
+            xv[i] = Xn[idx];
+            if constexpr (PHASE) pv[i] = ph[idx];
+        }
+    };
+    fetch(0, xc, pc);
+    for (int ks = 0; ks < KS; ++ks) {
+        cx<float> xn[NCBW], pn[NCBW];
+        fetch(min(ks + 1, KS - 1), xn, pn);
+        const int r = 4 * ks + rl;
+        const float a0 = sU[r][hl], a1 = sU[r][hl + 16];
+        const bool rok = r < K;
+#pragma unroll
+        for (int i = 0; i < NCBW; ++i) {
+            const int j = (cb0 + i) * 8 + jl;
+            cx<float> x = xc[i];
+            if constexpr (PHASE) x = cmul(pc[i], x);
+            const float b = (rok && j < Q) ? (part ? x.im : x.re) : 0.f;
+            acc0[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc0[i], 0, 0, 0);
+            acc1[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc1[i], 0, 0, 0);   // zero rows when H <= 16
+        }
+#pragma unroll
+        for (int i = 0; i < NCBW; ++i) {
+            xc[i] = xn[i];
+            if constexpr (PHASE) pc[i] = pn[i];
+        }
+    }
+    (void)NCB;
+    // output lane layout: rows 4 (l / 16) + v, column l % 16 (= angle j, part)
+    float *yb = reinterpret_cast<float *>(ybuf);
+#pragma unroll
+    for (int i = 0; i < NCBW; ++i) {
+        const int j = (cb0 + i) * 8 + jl;
+        if (j < Q) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int h = 4 * rl + v;
+                yb[((size_t)h * Q + j) * 2 + part] = acc0[i][v];
+                if (two) yb[((size_t)(h + 16) * Q + j) * 2 + part] = acc1[i][v];
+            }
+        }
+    }
+    __syncthreads();
+    emit_fast(ybuf, n, t, T, Q, H, Qc, pl, tw, G, F, f_kind, f_tile, f_ntiles, H8, nplanes, is_img);
 }
 
 // zero fill of the fast operand buffers (a kernel rather than a memset, so
@@ -236,6 +453,37 @@ hipError_t launch_ueta(radsvd_plan *p, const double *U_src, int ld, hipStream_t 
     return hipGetLastError();
 }
 
+static hipError_t rings_side_mfma(radsvd_plan *p, const void *X, int n_real, int n_pad, int T, bool use_phase,
+                                  void *G, void *F, int f_tile, int is_img, hipStream_t s) {
+    const int Q = p->Q;
+    const int nhb = p->H > 16 ? 2 : 1;
+    const size_t shmem = (size_t)(1 + 16 * nhb) * Q * sizeof(cx<float>);
+    const int f_kind = p->prec == RADSVD_FP32 ? 0 : 1;
+    const int ncbw = ((2 * Q + 15) / 16 + 3) / 4;
+    auto go = [&](auto kern) -> hipError_t {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(n_real * T), dim3(256), shmem, s, reinterpret_cast<const cx<float> *>(X),
+                           n_real, T, reinterpret_cast<const cx<float> *>(p->phase),
+                           reinterpret_cast<const float *>(p->Ueta), p->K, Q, p->H, p->Qc,
+                           reinterpret_cast<cx<float> *>(G), F, f_kind, f_tile, n_pad / f_tile, p->H8, p->nplanes,
+                           is_img);
+        return hipGetLastError();
+    };
+    auto pick = [&](auto phase_tag) -> hipError_t {
+        constexpr bool PH = decltype(phase_tag)::value;
+        if (ncbw <= 1) return go(k_rings_mfma<1, PH>);
+        if (ncbw <= 2) return go(k_rings_mfma<2, PH>);
+        if (ncbw <= 3) return go(k_rings_mfma<3, PH>);
+        if (ncbw <= 4) return go(k_rings_mfma<4, PH>);
+        if (ncbw <= 6) return go(k_rings_mfma<6, PH>);
+        if (ncbw <= 8) return go(k_rings_mfma<8, PH>);
+        if (ncbw <= 12) return go(k_rings_mfma<12, PH>);
+        return go(k_rings_mfma<16, PH>);
+    };
+    return use_phase ? pick(std::true_type{}) : pick(std::false_type{});
+}
+
 template <typename R, int HP>
 static hipError_t rings_side(radsvd_plan *p, const void *X, int n_real, int n_pad, int T,
                              bool use_phase, void *G, void *F, int f_tile, int is_img, hipStream_t s) {
@@ -272,10 +520,9 @@ hipError_t launch_principal_rings(radsvd_plan *p, hipStream_t s) {
                            p->Bf_bytes / 16);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    e = rings_side<float, 32>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, 1, s);
+    e = rings_side_mfma(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, 1, s);
     if (e != hipSuccess) return e;
-    return rings_side<float, 32>(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, p->Bf,
-                                 kFastTB, 0, s);
+    return rings_side_mfma(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, p->Bf, kFastTB, 0, s);
 }
 
 }  // namespace radsvd

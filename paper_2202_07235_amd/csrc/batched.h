@@ -84,7 +84,9 @@ __device__ __forceinline__ void tile_q(int hi, CArgs &a, int lin0, int cnt, unsi
 template <int KIND>
 __global__ __launch_bounds__(256, 1) void k_pairs_batched(BatchHeader *hdr, const BatchJob *__restrict__ jobs_g) {
     extern __shared__ unsigned char smem_raw[];
-    __shared__ int s_item;
+    // the item handoff uses the tile's staging memory (the tile needs all 160 KB
+    // at Q = 512); the barrier after the read keeps it from being overwritten early
+    int &s_item = *reinterpret_cast<int *>(smem_raw);
     CJob *jobs = (CJob *)jobs_g;
     const int x0 = blockIdx.x & 7;   // workgroups are dealt to the XCDs round-robin
     for (int qn = 0; qn < 8; ++qn) {
@@ -95,6 +97,7 @@ __global__ __launch_bounds__(256, 1) void k_pairs_batched(BatchHeader *hdr, cons
         if (threadIdx.x == 0) s_item = (int)atomicAdd(&hdr->next[x], 1u);
         __syncthreads();
         const int k = s_item;
+        __syncthreads();
         if (k >= qcount) break;   // uniform across the workgroup: every wave leaves
         const int item = (x + 8 * (k / kChunk)) * kChunk + k % kChunk;
         int lo = 0, hi = nj - 1;    // last job with item0 <= item

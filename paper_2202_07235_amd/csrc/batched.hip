@@ -126,7 +126,7 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int grid = std::max(1, std::min(total, device_cus()));
-    const size_t shmem = (size_t)(16 * 128 + (max_q / 8) * 256) * sizeof(cx<float>);
+    const size_t shmem = (size_t)(2 * 16 * 128 + (max_q / 8) * 256) * sizeof(cx<float>);
     switch (kind) {
     case 0: return launch_batched_fp32(hdr, djobs, grid, shmem, s);
     case 1: return launch_batched_bf16(hdr, djobs, grid, shmem, s);

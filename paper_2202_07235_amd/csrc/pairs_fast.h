@@ -276,7 +276,8 @@ struct Frag {
 // precision; NF, HF operand chunks per plane (FP32: NF = H8 / 8 chunks of 16
 // depth values, HF = 0; BF16: NF = H8 / 16, HF = 1 when H8 is an odd multiple
 // of 8).  Called by all 256 threads of a workgroup; smem_raw holds
-// (16 * 128 + Q / 8 * 256) complex FP32 values.  Begins and ends at a barrier.
+// (2 * 16 * 128 + Q / 8 * 256) complex FP32 values (160 KB at Q = 512).
+// Begins and ends at a barrier.
 template <int Q, int KIND, int NF, int HF, class ArgsT>
 __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_in, unsigned char *smem_raw) {
     constexpr int M = Q / 2;
@@ -287,8 +288,9 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     using PR = Prec<KIND>;
     static_assert(M % 16 == 0, "Q must be a multiple of 32");
 
-    cx<float> *stage = reinterpret_cast<cx<float> *>(smem_raw);   // [16][128]
-    cx<float> *upper = stage + 16 * 128;                          // [LH][256]
+    // staging of MFMA results, double-buffered by round parity: [2][16][128]
+    cx<float> *stage = reinterpret_cast<cx<float> *>(smem_raw);
+    cx<float> *upper = stage + 2 * 16 * 128;                      // [LH][256]
 
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -402,9 +404,9 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     // of the MFMA-layout writes; a wave's reads stay within one 32-pair block)
     auto sidx = [](int P) { return P ^ (((P >> 5) & 1) << 4); };
     // rows 4g..4g+3 of the 16x16 block: images 2g, 2g+1 (Re, Im) at target column i16
-    auto put = [&](int slot, f32x4 v) {
-        stage[slot * 128 + sidx((2 * g) * 16 + i16)] = cx<float>{v[0], v[1]};
-        stage[slot * 128 + sidx((2 * g + 1) * 16 + i16)] = cx<float>{v[2], v[3]};
+    auto put = [&](cx<float> *sb, int slot, f32x4 v) {
+        sb[slot * 128 + sidx((2 * g) * 16 + i16)] = cx<float>{v[0], v[1]};
+        sb[slot * 128 + sidx((2 * g + 1) * 16 + i16)] = cx<float>{v[2], v[3]};
     };
     const int Ps = sidx(P);
 
@@ -422,8 +424,13 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             load_at(rB, job_upper(J), job_soff(J), fr[J]);
         });
         // ---------------- step 1: contraction, paired rounds ----------------
+        // One barrier per round: round R stages into buffer R & 1, so the fold of
+        // round R (reads) overlaps the MFMAs and staging of round R + 1 (other
+        // buffer); the barrier of round R + 1 orders fold(R) before round R + 2
+        // reuses the buffer.
         sfor<0, NRP>([&](auto RR) {
             constexpr int R = decltype(RR)::value;
+            cx<float> *sb = stage + (R & 1) * (16 * 128);
             sfor<0, 4>([&](auto JJ) {
                 constexpr int J = 4 * R + decltype(JJ)::value;
                 if constexpr (J + D < NJ) {
@@ -436,14 +443,14 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                 // sink the loads and shorten the prefetch distance)
                 __builtin_amdgcn_sched_barrier(0);
                 const f32x4 acc = mma(fr[J % (D + 1)]);
-                put((decltype(JJ)::value < 2 ? 0 : 8) + 2 * w + (decltype(JJ)::value & 1), acc);
+                put(sb, (decltype(JJ)::value < 2 ? 0 : 8) + 2 * w + (decltype(JJ)::value & 1), acc);
             });
             __syncthreads();
             // Z fold: lane e owns k = 8R + 2jj + e (k and M - k have equal parity)
             sfor<0, 4>([&](auto JJ) {
                 constexpr int jj = decltype(JJ)::value;
-                cx<float> lo = stage[(2 * jj + e) * 128 + Ps];        // S[k]
-                cx<float> hi = stage[(8 + 2 * jj + e) * 128 + Ps];    // S[M - k]
+                cx<float> lo = sb[(2 * jj + e) * 128 + Ps];        // S[k]
+                cx<float> hi = sb[(8 + 2 * jj + e) * 128 + Ps];    // S[M - k]
                 if constexpr (R == 0 && jj == 0) {
                     if (e == 0) {   // S[0], S[M] are real
                         lo.im = 0.f;
@@ -463,15 +470,15 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                     upper[(ubase - e) * 256 + tid] = zc;
                 }
             });
-            __syncthreads();
         });
         {   // middle frequency q = M/2 (even): Z[M/2] = 2 S[M/2], upper slot 0 of lane e = 0
+            cx<float> *sb = stage + (NRP & 1) * (16 * 128);   // not the last round's buffer
             if (w == 0) {
                 const f32x4 acc = mma(fr[NJ % (D + 1)]);
-                put(0, acc);
+                put(sb, 0, acc);
             }
             __syncthreads();
-            const cx<float> sm = stage[Ps];
+            const cx<float> sm = sb[Ps];
             if (e == 0) upper[tid] = cx<float>{2.f * sm.re, 2.f * sm.im};
             __syncthreads();
         }
@@ -603,7 +610,7 @@ __global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
 template <int Q, int KIND, int NF, int HF>
 static hipError_t launch_v(const Args &a, int nwg, hipStream_t s) {
     constexpr int LH = Q / 8;
-    const size_t shmem = (size_t)(16 * 128 + LH * 256) * sizeof(cx<float>);
+    const size_t shmem = (size_t)(2 * 16 * 128 + LH * 256) * sizeof(cx<float>);
     static bool attr_done = false;
     if (!attr_done) {
         hipError_t e = hipFuncSetAttribute((const void *)k_pairs_fast<Q, KIND, NF, HF>,

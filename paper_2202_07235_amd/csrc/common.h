@@ -71,7 +71,18 @@ struct FftPlan {
     int nst;
     int rad[16];
     int span[16];   // block length after stage s (= current length / radix)
+    // x / d = umulhi(x, ceil(2^32 / d)) for the stage divisors d = n / rad and
+    // d = span, exact for x < 2^20 and 2 <= d <= 2^11; d = 1 is stored as 0
+    // (ceil(2^32 / 1) does not fit) and handled by fft_div
+    unsigned mag_seq[16], mag_span[16];
 };
+
+__host__ __device__ inline unsigned fft_magic(unsigned d) {
+    return d <= 1 ? 0u : (unsigned)((((unsigned long long)1 << 32) + d - 1) / d);
+}
+__device__ __forceinline__ int fft_div(int x, unsigned magic) {
+    return magic ? (int)__umulhi((unsigned)x, magic) : x;
+}
 
 __host__ __device__ inline bool fft_size_ok(int n) {
     if (n < 2) return false;
@@ -92,6 +103,8 @@ __host__ __device__ inline FftPlan fft_make_plan(int n) {
     for (int s = 0; s < p.nst; ++s) {
         L /= p.rad[s];
         p.span[s] = L;
+        p.mag_seq[s] = fft_magic((unsigned)(n / p.rad[s]));
+        p.mag_span[s] = fft_magic((unsigned)L);
     }
     return p;
 }
@@ -135,17 +148,14 @@ __device__ __forceinline__ void dft_small(int rad, cx<R> *v) {
 }
 
 template <int RAD, typename R>
-__device__ __forceinline__ void fft_butterfly(cx<R> *x, int span, int k, int tstep, int n, const cx<R> *tw) {
+__device__ __forceinline__ void fft_butterfly(cx<R> *x, int span, int k, int tstep, int, const cx<R> *tw) {
     cx<R> v[RAD];
 #pragma unroll
     for (int r = 0; r < RAD; ++r) v[r] = x[r * span];
     dft_small(RAD, v);
     x[0] = v[0];
 #pragma unroll
-    for (int p = 1; p < RAD; ++p) {
-        const int e = (k * p * tstep) % n;
-        x[p * span] = cmul(v[p], tw[e]);
-    }
+    for (int p = 1; p < RAD; ++p) x[p * span] = cmul(v[p], tw[k * p * tstep]);   // k p tstep < n
 }
 
 // In-place forward FFT (exp(-2 pi i f j / n)) of `cnt` sequences of length n
@@ -162,10 +172,11 @@ __device__ void lds_fft_dif(cx<R> *buf, int cnt, int seq_stride, const FftPlan &
         const int per_seq = n / rad;
         const int nbf = cnt * per_seq;
         const int tstep = n / L;
+        const unsigned ms = pl.mag_seq[s], mp = pl.mag_span[s];
         for (int i = threadIdx.x; i < nbf; i += blockDim.x) {
-            const int sq = i / per_seq;
+            const int sq = fft_div(i, ms);
             const int bi = i - sq * per_seq;
-            const int blk = bi / span;
+            const int blk = fft_div(bi, mp);
             const int k = bi - blk * span;
             cx<R> *x = buf + (size_t)sq * seq_stride + blk * L + k;
             // one butterfly per radix with a fixed-size register array

@@ -39,12 +39,14 @@ __global__ __launch_bounds__(256) void k_ringsum(const cx<R> *__restrict__ B, in
 }
 
 // Partial Gram over targets b in [b0, b1): P[split][r][r'] =
-// sum_{b,j} Re conj(B[b][r][j]) B[b][r'][j].  64x64 output tile per block,
+// sum_b ( sum_j Re conj(B[b][r][j]) B[b][r'][j] - Re conj(S[b][r]) S[b][r'] / Q ),
+// the q != 0 part of each target's term.  64x64 output tile per block,
 // 4x4 outputs per thread; the contraction index (b, j) is staged through LDS
 // in chunks of 16 angles.
 template <typename R>
-__global__ __launch_bounds__(256) void k_gram_partial(const cx<R> *__restrict__ B, int n_tgt, int K,
-                                                      int Q, int b_per_split, double *__restrict__ P) {
+__global__ __launch_bounds__(256) void k_gram_partial(const cx<R> *__restrict__ B, const double *__restrict__ S,
+                                                      int n_tgt, int K, int Q, int b_per_split,
+                                                      double *__restrict__ P) {
     constexpr int TT = 64, CH = 16;
     __shared__ double sre[2][TT][CH + 1];
     __shared__ double sim[2][TT][CH + 1];
@@ -90,6 +92,18 @@ __global__ __launch_bounds__(256) void k_gram_partial(const cx<R> *__restrict__ 
                     for (int j = 0; j < 4; ++j) acc[i][j] += ar[i] * br[j] + ai[i] * bi[j];
             }
         }
+        // the q = 0 term of target b: Re conj(S[r]) S[r'] / Q
+        const double *sb = S + (size_t)b * K * 2;
+        const double iq = 1.0 / (double)Q;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = min(r0 + ty * 4 + i, K - 1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = min(c0 + tx * 4 + j, K - 1);
+                acc[i][j] -= (sb[2 * r] * sb[2 * c] + sb[2 * r + 1] * sb[2 * c + 1]) * iq;
+            }
+        }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -100,9 +114,8 @@ __global__ __launch_bounds__(256) void k_gram_partial(const cx<R> *__restrict__ 
         }
 }
 
-__global__ void k_C_finalize(const double *__restrict__ P, int nsplit, const double *__restrict__ S,
-                             int n_tgt, int K, int Q, const double *__restrict__ eta,
-                             double *__restrict__ C) {
+__global__ void k_C_finalize(const double *__restrict__ P, int nsplit, int n_tgt, int K,
+                             const double *__restrict__ eta, double *__restrict__ C) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= K * K) return;
     const int r = i / K, c = i - r * K;
@@ -110,12 +123,7 @@ __global__ void k_C_finalize(const double *__restrict__ P, int nsplit, const dou
     const int a = r < c ? r : c, bb = r < c ? c : r;
     double g = 0.0;
     for (int s = 0; s < nsplit; ++s) g += P[((size_t)s * K + a) * K + bb];
-    double z = 0.0;
-    for (int b = 0; b < n_tgt; ++b) {
-        const double *sb = S + (size_t)b * K * 2;
-        z += sb[2 * a] * sb[2 * bb] + sb[2 * a + 1] * sb[2 * bb + 1];
-    }
-    C[i] = eta[a] * eta[bb] * (g - z / (double)Q) / (double)n_tgt;
+    C[i] = eta[a] * eta[bb] * g / (double)n_tgt;
 }
 
 hipError_t launch_kernel_C(radsvd_plan *p, hipStream_t s) {
@@ -128,17 +136,17 @@ hipError_t launch_kernel_C(radsvd_plan *p, hipStream_t s) {
         const cx<double> *B = reinterpret_cast<const cx<double> *>(p->B_polar);
         hipLaunchKernelGGL(k_ringsum<double>, dim3((waves + 3) / 4), dim3(256), 0, s, B, nb, K, Q,
                            p->ringsum);
-        hipLaunchKernelGGL(k_gram_partial<double>, dim3(tiles, tiles, nsplit), dim3(256), 0, s, B, nb,
-                           K, Q, bps, p->gram_part);
+        hipLaunchKernelGGL(k_gram_partial<double>, dim3(tiles, tiles, nsplit), dim3(256), 0, s, B,
+                           p->ringsum, nb, K, Q, bps, p->gram_part);
     } else {
         const cx<float> *B = reinterpret_cast<const cx<float> *>(p->B_polar);
         hipLaunchKernelGGL(k_ringsum<float>, dim3((waves + 3) / 4), dim3(256), 0, s, B, nb, K, Q,
                            p->ringsum);
-        hipLaunchKernelGGL(k_gram_partial<float>, dim3(tiles, tiles, nsplit), dim3(256), 0, s, B, nb,
-                           K, Q, bps, p->gram_part);
+        hipLaunchKernelGGL(k_gram_partial<float>, dim3(tiles, tiles, nsplit), dim3(256), 0, s, B,
+                           p->ringsum, nb, K, Q, bps, p->gram_part);
     }
-    hipLaunchKernelGGL(k_C_finalize, dim3((K * K + 255) / 256), dim3(256), 0, s, p->gram_part, nsplit,
-                       p->ringsum, nb, K, Q, p->d_eta, p->C);
+    hipLaunchKernelGGL(k_C_finalize, dim3((K * K + 255) / 256), dim3(256), 0, s, p->gram_part, nsplit, nb, K,
+                       p->d_eta, p->C);
     return hipGetLastError();
 }
 

@@ -208,9 +208,10 @@ __global__ __launch_bounds__(256) void k_rings(
 // Fast layout: one thread per (q, fragment slot) gathers the slot's 8 (4 for
 // a half chunk) rank values, splits them into the plane format and writes
 // 16 (8) bytes per plane and row, the unit the pair kernel's lanes load.
-__device__ void emit_fast(cx<float> *ybuf, int n, int t, int T, int Q, int H, int Qc, const FftPlan &pl,
-                          const cx<float> *tw, cx<float> *__restrict__ G, void *__restrict__ F, int f_kind,
-                          int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
+__device__ void emit_fast(cx<float> *ybuf, const int *pos_tab, int n, int t, int T, int Q, int H, int Qc,
+                          const FftPlan &pl, const cx<float> *tw, cx<float> *__restrict__ G,
+                          void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes,
+                          int is_img) {
     typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
     typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
     lds_fft_dif(ybuf, H, Q, pl, tw);
@@ -220,7 +221,7 @@ __device__ void emit_fast(cx<float> *ybuf, int n, int t, int T, int Q, int H, in
         cx<float> *Gn = G + ((size_t)n * T + t) * Qc * H;
         for (int i = tid; i < Qc * H; i += nt) {
             const int q = i / H, h = i - q * H;
-            const cx<float> v = ybuf[h * Q + fft_pos(q, pl)];
+            const cx<float> v = ybuf[h * Q + pos_tab[q]];
             Gn[i] = cx<float>{v.re * scale, v.im * scale};
         }
     }
@@ -245,7 +246,7 @@ __device__ void emit_fast(cx<float> *ybuf, int n, int t, int T, int Q, int H, in
             const bool full = chunk < NF;
             const int nv = full ? 8 : 4;
             const int hb = full ? 16 * chunk + 8 * hsub : 16 * NF + 4 * hsub;
-            const int pos = fft_pos(q, pl);
+            const int pos = pos_tab[q];
             char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
             // Re row / target column: c = 0 -> re, 1 -> im; image Im row: c = 0 -> -im, 1 -> re
             for (int rr = 0; rr < (is_img ? 2 : 1); ++rr) {
@@ -281,7 +282,7 @@ __device__ void emit_fast(cx<float> *ybuf, int n, int t, int T, int Q, int H, in
         for (int i = tid; i < Qc * nslots; i += nt) {
             const int q = i / nslots, sl = i - q * nslots;
             const int chunk = sl >> 2, g = sl & 3;
-            const int pos = fft_pos(q, pl);
+            const int pos = pos_tab[q];
             char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
             for (int rr = 0; rr < (is_img ? 2 : 1); ++rr) {
                 u32x4_t wv;
@@ -332,6 +333,8 @@ __global__ __launch_bounds__(256) void k_rings_mfma(
     const bool two = H > 16;
     const int rl = l >> 4, hl = l & 15;
     __shared__ float sU[kMaxK][33];   // Ueta[r][h], zero beyond K and H
+    __shared__ int pos_tab[kMaxQ];    // FFT output position of each frequency
+    for (int q = tid; q < Q; q += blockDim.x) pos_tab[q] = fft_pos(q, pl);
     for (int i = tid; i < kMaxK * 32; i += blockDim.x) {
         const int r = i >> 5, h = i & 31;
         sU[r][h] = (r < K && h < H) ? Ueta[(size_t)r * H + h] : 0.f;
@@ -400,7 +403,7 @@ __global__ __launch_bounds__(256) void k_rings_mfma(
         }
     }
     __syncthreads();
-    emit_fast(ybuf, n, t, T, Q, H, Qc, pl, tw, G, F, f_kind, f_tile, f_ntiles, H8, nplanes, is_img);
+    emit_fast(ybuf, pos_tab, n, t, T, Q, H, Qc, pl, tw, G, F, f_kind, f_tile, f_ntiles, H8, nplanes, is_img);
 }
 
 // zero fill of the fast operand buffers (a kernel rather than a memset, so

@@ -96,54 +96,63 @@ __global__ void k_bwd_phase(const double *d_k, const double *d_delta, int K, int
     }
 }
 
-// One workgroup per pair (a0 + blockIdx.y, blockIdx.x): for every t, the
+// One workgroup per pair (a0 + blockIdx.y, blockIdx.x); translations in
+// groups of TG (their rows side by side in LDS, one FFT call per group): the
 // landscape X (contraction + FFT, FP64), Pt = exp(s Re X - c_a), the
 // transform of Pt at the stored q, and the pair's sum of Pt over (t, m).
 template <typename R>
 __global__ __launch_bounds__(256) void k_bwd_phat(const cx<R> *__restrict__ Ag, const cx<R> *__restrict__ Bg,
-                                                  int a0, int n_tgt, int T, int H, int Q, int Qs, int herm,
+                                                  int a0, int n_tgt, int T, int TG, int H, int Q, int Qs, int herm,
                                                   double s2, const float *__restrict__ lse_img,
                                                   cx<double> *__restrict__ Phat, double *__restrict__ psum) {
     __shared__ double red[256];
+    __shared__ FftPlan spl;
     extern __shared__ unsigned char smem_raw[];
     cx<double> *tw = reinterpret_cast<cx<double> *>(smem_raw);
-    cx<double> *X = tw + Q;
-    cx<double> *Pb = X + Q;
+    cx<double> *X = tw + Q;            // [TG][Q]
+    cx<double> *Pb = X + (size_t)TG * Q;   // [TG][Q]
     const int b = blockIdx.x, al = blockIdx.y, a = a0 + al;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int M = Q / 2;
     const size_t NBT = (size_t)n_tgt * T;
     fill_twiddles(tw, Q);
-    const FftPlan pl = fft_make_plan(Q);
+    if (tid == 0) fft_init_plan(spl, Q);
+    __syncthreads();
+    const FftPlan &pl = spl;
     const double ca = (double)lse_img[a];
+    const cx<R> *Aq = Ag + (size_t)a * Qs * H;
     double mysum = 0.0;
-    for (int t = 0; t < T; ++t) {
+    for (int t0 = 0; t0 < T; t0 += TG) {
+        const int tg = min(TG, T - t0);
         __syncthreads();
-        const cx<R> *Aq = Ag + (size_t)a * Qs * H;
-        const cx<R> *Bq = Bg + ((size_t)b * T + t) * Qs * H;
-        for (int q = tid; q < Qs; q += nt) {
+        for (int i = tid; i < tg * Qs; i += nt) {
+            const int tt = i / Qs, q = i - tt * Qs;
+            const cx<R> *Bq = Bg + ((size_t)b * T + t0 + tt) * Qs * H;
             double re = 0.0, im = 0.0;
             for (int h = 0; h < H; ++h) {
                 const cx<double> x = up(Aq[(size_t)q * H + h]), y = up(Bq[(size_t)q * H + h]);
                 re += x.re * y.re + x.im * y.im;   // conj(x) y
                 im += x.re * y.im - x.im * y.re;
             }
-            X[q] = cx<double>{re, im};
-            if (herm && q > 0 && q < M) X[Q - q] = cx<double>{re, -im};
+            cx<double> *Xt = X + (size_t)tt * Q;
+            Xt[q] = cx<double>{re, im};
+            if (herm && q > 0 && q < M) Xt[Q - q] = cx<double>{re, -im};
         }
         __syncthreads();
-        lds_fft_dif(X, 1, Q, pl, tw);   // X[pos(m)] = sum_q S[q] W^{qm}
-        for (int m = tid; m < Q; m += nt) {
-            const double pt = exp(s2 * X[fft_pos(m, pl)].re - ca);
+        lds_fft_dif(X, tg, Q, pl, tw);   // X[tt][pos(m)] = sum_q S[q] W^{qm}
+        for (int i = tid; i < tg * Q; i += nt) {
+            const int tt = i / Q, m = i - tt * Q;
+            const double pt = exp(s2 * X[(size_t)tt * Q + fft_pos(m, pl)].re - ca);
             mysum += pt;
-            Pb[m] = cx<double>{pt, 0.0};
+            Pb[(size_t)tt * Q + m] = cx<double>{pt, 0.0};
         }
         __syncthreads();
-        lds_fft_dif(Pb, 1, Q, pl, tw);   // sum_m P[m] W^{qm}; Phat = its conjugate
-        cx<double> *out = Phat + (size_t)al * Qs * NBT + (size_t)b * T + t;
-        for (int q = tid; q < Qs; q += nt) {
-            const cx<double> v = Pb[fft_pos(q, pl)];
-            out[(size_t)q * NBT] = cx<double>{v.re, -v.im};
+        lds_fft_dif(Pb, tg, Q, pl, tw);   // sum_m P[m] W^{qm}; Phat = its conjugate
+        cx<double> *out = Phat + (size_t)al * Qs * NBT + (size_t)b * T + t0;
+        for (int i = tid; i < tg * Qs; i += nt) {
+            const int q = i / tg, tt = i - q * tg;
+            const cx<double> v = Pb[(size_t)tt * Q + fft_pos(q, pl)];
+            out[(size_t)q * NBT + tt] = cx<double>{v.re, -v.im};
         }
     }
     red[tid] = mysum;
@@ -274,7 +283,10 @@ __global__ __launch_bounds__(256) void k_bwd_inv_rings(const cx<double> *__restr
     const int n = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
     const int M = Q / 2;
     fill_twiddles(tw, Q);
-    const FftPlan pl = fft_make_plan(Q);
+    __shared__ FftPlan spl;   // in LDS: the FFT stage loops index it at run time
+    if (threadIdx.x == 0) fft_init_plan(spl, Q);
+    __syncthreads();
+    const FftPlan &pl = spl;
     const double sc = 1.0 / sqrt((double)Q);
     const cx<double> *Gn = G + (size_t)n * Qs * H;
     for (int h0 = 0; h0 < H; h0 += HC) {
@@ -407,10 +419,17 @@ hipError_t run_backward(const radsvd_plan *p, float inv_s2, const float *lse_img
 
     hipLaunchKernelGGL(k_bwd_phase, dim3((T * K * Q + 255) / 256 < 4096 ? (T * K * Q + 255) / 256 : 4096), dim3(256),
                        0, s, p->d_k, p->d_delta, K, Q, T, ph);
-    const size_t sh_phat = (size_t)3 * Q * sizeof(cx<double>);
+    // translations per group: their rows fill up to ~120 KB of LDS
+    const int TG = max(1, min(T, (int)(((size_t)120 * 1024 / ((size_t)Q * sizeof(cx<double>)) - 1) / 2)));
+    const size_t sh_phat = (size_t)(1 + 2 * TG) * Q * sizeof(cx<double>);
+    {
+        hipError_t e = hipFuncSetAttribute((const void *)k_bwd_phat<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)sh_phat);
+        if (e != hipSuccess) return e;
+    }
     for (int a0 = 0; a0 < na; a0 += L.chunk) {
         const int ca = min(L.chunk, na - a0);
-        hipLaunchKernelGGL(k_bwd_phat<R>, dim3(nb, ca), dim3(256), sh_phat, s, Ag, Bg, a0, nb, T, H, Q, Qs,
+        hipLaunchKernelGGL(k_bwd_phat<R>, dim3(nb, ca), dim3(256), sh_phat, s, Ag, Bg, a0, nb, T, TG, H, Q, Qs,
                            p->herm, (double)inv_s2, lse_img, Phat, psum);
         hipLaunchKernelGGL(k_bwd_kappa, dim3((ca + 255) / 256), dim3(256), 0, s, psum, glse, a0, ca, nb,
                            (double)inv_s2, kappa);

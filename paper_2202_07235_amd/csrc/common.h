@@ -91,8 +91,8 @@ __host__ __device__ inline bool fft_size_ok(int n) {
     return n == 1;
 }
 
-__host__ __device__ inline FftPlan fft_make_plan(int n) {
-    FftPlan p;
+// fills p in place (p may live in LDS: no private-memory copy)
+__host__ __device__ inline void fft_init_plan(FftPlan &p, int n) {
     p.n = n;
     p.nst = 0;
     int m = n;
@@ -106,6 +106,11 @@ __host__ __device__ inline FftPlan fft_make_plan(int n) {
         p.mag_seq[s] = fft_magic((unsigned)(n / p.rad[s]));
         p.mag_span[s] = fft_magic((unsigned)L);
     }
+}
+
+__host__ __device__ inline FftPlan fft_make_plan(int n) {
+    FftPlan p;
+    fft_init_plan(p, n);
     return p;
 }
 

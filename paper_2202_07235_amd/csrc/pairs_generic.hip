@@ -76,7 +76,10 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
         sincospi(-2.0 * (double)i / (double)Q, &s, &c);
         tw[i] = cx<R>{(R)c, (R)s};
     }
-    const FftPlan pl = fft_make_plan(Q);
+    __shared__ FftPlan spl;   // in LDS: the FFT stage loops index it at run time
+    if (threadIdx.x == 0) fft_init_plan(spl, Q);
+    __syncthreads();
+    const FftPlan &pl = spl;
     const int M = Q / 2;
     float best_v = 0.f;
     int best_i = 0x7fffffff;

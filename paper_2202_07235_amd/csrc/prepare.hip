@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_rings(
         tw[i] = cx<R>{(R)c, (R)s};
     }
     __shared__ FftPlan spl;   // in LDS: the stage loops index it at run time
-    if (threadIdx.x == 0) spl = fft_make_plan(Q);
+    if (threadIdx.x == 0) fft_init_plan(spl, Q);
     __syncthreads();
     const FftPlan &pl = spl;
     const cx<R> *Xn = X + (size_t)n * K * Q;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_rings_mfma(
         tw[i] = cx<float>{(float)c, (float)s};
     }
     __shared__ FftPlan spl;   // in LDS: the stage loops index it at run time
-    if (threadIdx.x == 0) spl = fft_make_plan(Q);
+    if (threadIdx.x == 0) fft_init_plan(spl, Q);
     __syncthreads();
     const FftPlan &pl = spl;
     const int KS = (K + 3) >> 2;

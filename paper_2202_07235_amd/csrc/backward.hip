@@ -26,6 +26,8 @@
 // is applied as a per-image factor kappa[a] in the contractions.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -37,8 +39,19 @@ constexpr size_t kPhatBudget = size_t(4) << 30;   // bytes of Phat per image chu
 
 struct BwdLayout {
     int chunk;   // images per chunk
-    size_t off_phat, off_sum, off_kappa, off_gBt, off_gAt, off_gBpsi, off_gApsi, off_ph64, off_part, total;
+    size_t off_phat, off_sum, off_kappa, off_gBt, off_gAt, off_gApart, off_gBpsi, off_gApsi, off_ph64, off_part,
+        total;
 };
+
+// spans of columns of the g_at contraction: enough workgroups to fill the chip,
+// each span at least 256 columns (so the partials stay below Phat / 8)
+int gat_max_split(size_t NBT) { return (int)std::max<size_t>(1, std::min<size_t>(8, NBT / 256)); }
+
+int gat_span(int ca, int Qs, int NBT) {
+    const int nwg = ((ca + 63) / 64) * Qs;
+    const int ns = std::max(1, std::min(gat_max_split(NBT), (4096 + nwg - 1) / nwg));
+    return ((NBT + ns - 1) / ns + 15) / 16 * 16;
+}
 
 BwdLayout bwd_layout(const radsvd_plan *p) {
     const size_t Qs = p->Qc, T = p->T, H = p->H, K = p->K, Q = p->Q;
@@ -61,6 +74,7 @@ BwdLayout bwd_layout(const radsvd_plan *p) {
     L.off_kappa = take(ch * sizeof(double));                // [chunk]
     L.off_gBt = take(NBT * Qs * H * sizeof(cx<double>));    // [NBT][Qs][H]
     L.off_gAt = take(na * Qs * H * sizeof(cx<double>));     // [na][Qs][H]
+    L.off_gApart = take(gat_max_split(NBT) * ch * Qs * H * sizeof(cx<double>));   // [split][chunk][Qs][H]
     L.off_gBpsi = take(NBT * H * Q * sizeof(cx<double>));   // [NBT][H][Q]
     L.off_gApsi = take(na * H * Q * sizeof(cx<double>));    // [na][H][Q]
     L.off_ph64 = take(T * K * Q * sizeof(cx<double>));      // [T][K][Q]
@@ -72,6 +86,33 @@ BwdLayout bwd_layout(const radsvd_plan *p) {
 template <typename R>
 __device__ __forceinline__ cx<double> up(const cx<R> &v) {
     return cx<double>{(double)v.re, (double)v.im};
+}
+
+// re + i im += sum_h conj(x[h]) y[h] over one rank row; the loads of eight
+// ranks are issued together so that a row costs H/8 memory round trips
+template <typename R>
+__device__ __forceinline__ void conj_dot(const cx<R> *__restrict__ x, const cx<R> *__restrict__ y, int H,
+                                         double &re, double &im) {
+    int h = 0;
+    for (; h + 8 <= H; h += 8) {
+        cx<R> xv[8], yv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            xv[k] = x[h + k];
+            yv[k] = y[h + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const cx<double> u = up(xv[k]), v = up(yv[k]);
+            re += u.re * v.re + u.im * v.im;
+            im += u.re * v.im - u.im * v.re;
+        }
+    }
+    for (; h < H; ++h) {
+        const cx<double> u = up(x[h]), v = up(y[h]);
+        re += u.re * v.re + u.im * v.im;
+        im += u.re * v.im - u.im * v.re;
+    }
 }
 
 __device__ __forceinline__ void fill_twiddles(cx<double> *tw, int Q) {
@@ -96,22 +137,37 @@ __global__ void k_bwd_phase(const double *d_k, const double *d_delta, int K, int
     }
 }
 
-// One workgroup per pair (a0 + blockIdx.y, blockIdx.x); translations in
-// groups of TG (their rows side by side in LDS, one FFT call per group): the
-// landscape X (contraction + FFT, FP64), Pt = exp(s Re X - c_a), the
-// transform of Pt at the stored q, and the pair's sum of Pt over (t, m).
+// sum over the 64 lanes of a wave; every lane gets the same value (fixed order)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// One workgroup per (image a0 + blockIdx.y, nbw consecutive targets); for each
+// target, translations in groups of TG: the landscape X (contraction + FFT,
+// FP64), Pt = exp(s Re X - c_a), the transform of Pt at the stored q, and the
+// pair's sum of Pt over (t, m).
+//
+// Hermitian inputs: X_t and Pt_t are real, so two translations share one
+// complex transform each way.  With spectra S_e, S_o extended by
+// S[Q-q] = conj S[q] (real at q = 0 and Q/2), Z = S_e + i S_o transforms to
+// X_e + i X_o; with Y = Pt_e + i Pt_o and its transform Yh,
+// F_e[q] = (Yh[q] + conj Yh[Q-q]) / 2 and F_o[q] = (Yh[q] - conj Yh[Q-q]) / 2i.
 template <typename R>
 __global__ __launch_bounds__(256) void k_bwd_phat(const cx<R> *__restrict__ Ag, const cx<R> *__restrict__ Bg,
-                                                  int a0, int n_tgt, int T, int TG, int H, int Q, int Qs, int herm,
-                                                  double s2, const float *__restrict__ lse_img,
+                                                  int a0, int n_tgt, int nbw, int T, int TG, int H, int Q, int Qs,
+                                                  int herm, double s2, const float *__restrict__ lse_img,
                                                   cx<double> *__restrict__ Phat, double *__restrict__ psum) {
-    __shared__ double red[256];
+    __shared__ double red[16];
     __shared__ FftPlan spl;
     extern __shared__ unsigned char smem_raw[];
+    const int NR = herm ? (TG + 1) / 2 : TG;   // transform rows per group
     cx<double> *tw = reinterpret_cast<cx<double> *>(smem_raw);
-    cx<double> *X = tw + Q;            // [TG][Q]
-    cx<double> *Pb = X + (size_t)TG * Q;   // [TG][Q]
-    const int b = blockIdx.x, al = blockIdx.y, a = a0 + al;
+    cx<double> *X = tw + Q;                     // [NR][Q]
+    cx<double> *Pb = X + (size_t)NR * Q;        // [NR][Q]
+    const int al = blockIdx.y, a = a0 + al;
+    const int b_begin = blockIdx.x * nbw, b_end = min(n_tgt, b_begin + nbw);
     const int tid = threadIdx.x, nt = blockDim.x;
     const int M = Q / 2;
     const size_t NBT = (size_t)n_tgt * T;
@@ -121,46 +177,68 @@ __global__ __launch_bounds__(256) void k_bwd_phat(const cx<R> *__restrict__ Ag, 
     const FftPlan &pl = spl;
     const double ca = (double)lse_img[a];
     const cx<R> *Aq = Ag + (size_t)a * Qs * H;
-    double mysum = 0.0;
-    for (int t0 = 0; t0 < T; t0 += TG) {
-        const int tg = min(TG, T - t0);
-        __syncthreads();
-        for (int i = tid; i < tg * Qs; i += nt) {
-            const int tt = i / Qs, q = i - tt * Qs;
-            const cx<R> *Bq = Bg + ((size_t)b * T + t0 + tt) * Qs * H;
-            double re = 0.0, im = 0.0;
-            for (int h = 0; h < H; ++h) {
-                const cx<double> x = up(Aq[(size_t)q * H + h]), y = up(Bq[(size_t)q * H + h]);
-                re += x.re * y.re + x.im * y.im;   // conj(x) y
-                im += x.re * y.im - x.im * y.re;
+    for (int b = b_begin; b < b_end; ++b) {
+        double mysum = 0.0;
+        for (int t0 = 0; t0 < T; t0 += TG) {
+            const int tg = min(TG, T - t0);
+            const int nr = herm ? (tg + 1) / 2 : tg;
+            const cx<R> *Bt = Bg + ((size_t)b * T + t0) * Qs * H;
+            __syncthreads();   // X, Pb of the previous group are consumed
+            if (herm) {
+                for (int i = tid; i < nr * Qs; i += nt) {
+                    const int rr = i / Qs, q = i - rr * Qs;
+                    double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
+                    conj_dot(Aq + (size_t)q * H, Bt + ((size_t)(2 * rr) * Qs + q) * H, H, er, ei);
+                    if (2 * rr + 1 < tg) conj_dot(Aq + (size_t)q * H, Bt + ((size_t)(2 * rr + 1) * Qs + q) * H, H, orr, oi);
+                    if (q == 0 || q == M) ei = oi = 0.0;   // the real endpoints of a Hermitian spectrum
+                    cx<double> *Z = X + (size_t)rr * Q;
+                    Z[q] = cx<double>{er - oi, ei + orr};
+                    if (q > 0 && q < M) Z[Q - q] = cx<double>{er + oi, orr - ei};
+                }
+            } else {
+                for (int i = tid; i < tg * Qs; i += nt) {
+                    const int tt = i / Qs, q = i - tt * Qs;
+                    double re = 0.0, im = 0.0;
+                    conj_dot(Aq + (size_t)q * H, Bt + ((size_t)tt * Qs + q) * H, H, re, im);
+                    X[(size_t)tt * Q + q] = cx<double>{re, im};
+                }
             }
-            cx<double> *Xt = X + (size_t)tt * Q;
-            Xt[q] = cx<double>{re, im};
-            if (herm && q > 0 && q < M) Xt[Q - q] = cx<double>{re, -im};
+            __syncthreads();
+            lds_fft_dif(X, nr, Q, pl, tw);   // X[row][pos(m)] = sum_q Z[q] W^{qm}
+            for (int i = tid; i < nr * Q; i += nt) {
+                const int rr = i / Q, m = i - rr * Q;
+                const cx<double> x = X[(size_t)rr * Q + fft_pos(m, pl)];
+                const double pe = exp(s2 * x.re - ca);
+                double po = 0.0;
+                if (herm && 2 * rr + 1 < tg) po = exp(s2 * x.im - ca);
+                mysum += pe + po;
+                Pb[(size_t)rr * Q + m] = cx<double>{pe, po};
+            }
+            __syncthreads();
+            lds_fft_dif(Pb, nr, Q, pl, tw);   // sum_m Y[m] W^{qm}; Phat = conj of the unpacked transform
+            cx<double> *out = Phat + (size_t)al * Qs * NBT + (size_t)b * T + t0;
+            for (int i = tid; i < tg * Qs; i += nt) {
+                const int q = i / tg, tt = i - q * tg;
+                cx<double> F;
+                if (herm) {
+                    const cx<double> *Y = Pb + (size_t)(tt >> 1) * Q;
+                    const cx<double> y = Y[fft_pos(q, pl)], z = Y[fft_pos(q == 0 ? 0 : Q - q, pl)];
+                    if ((tt & 1) == 0) F = cx<double>{0.5 * (y.re + z.re), 0.5 * (y.im - z.im)};
+                    else F = cx<double>{0.5 * (y.im + z.im), 0.5 * (z.re - y.re)};
+                } else {
+                    F = Pb[(size_t)tt * Q + fft_pos(q, pl)];
+                }
+                out[(size_t)q * NBT + tt] = cx<double>{F.re, -F.im};
+            }
         }
+        const double v = wave_sum(mysum);
+        if ((tid & 63) == 0) red[tid >> 6] = v;
         __syncthreads();
-        lds_fft_dif(X, tg, Q, pl, tw);   // X[tt][pos(m)] = sum_q S[q] W^{qm}
-        for (int i = tid; i < tg * Q; i += nt) {
-            const int tt = i / Q, m = i - tt * Q;
-            const double pt = exp(s2 * X[(size_t)tt * Q + fft_pos(m, pl)].re - ca);
-            mysum += pt;
-            Pb[(size_t)tt * Q + m] = cx<double>{pt, 0.0};
+        if (tid == 0) {
+            double sacc = 0.0;
+            for (int w = 0; w < (nt >> 6); ++w) sacc += red[w];
+            psum[(size_t)al * n_tgt + b] = sacc;
         }
-        __syncthreads();
-        lds_fft_dif(Pb, tg, Q, pl, tw);   // sum_m P[m] W^{qm}; Phat = its conjugate
-        cx<double> *out = Phat + (size_t)al * Qs * NBT + (size_t)b * T + t0;
-        for (int i = tid; i < tg * Qs; i += nt) {
-            const int q = i / tg, tt = i - q * tg;
-            const cx<double> v = Pb[(size_t)tt * Q + fft_pos(q, pl)];
-            out[(size_t)q * NBT + tt] = cx<double>{v.re, -v.im};
-        }
-    }
-    red[tid] = mysum;
-    __syncthreads();
-    if (tid == 0) {
-        double sacc = 0.0;
-        for (int i = 0; i < nt; ++i) sacc += red[i];
-        psum[(size_t)al * n_tgt + b] = sacc;
     }
 }
 
@@ -225,33 +303,61 @@ __global__ __launch_bounds__(256) void k_bwd_gBt(const cx<R> *__restrict__ Ag, c
     }
 }
 
-// g_at[a][q][h] = sum_bt conj(Phat[a][q][bt]) bt[bt][q][h] for the chunk's
-// images; one workgroup per (64 images, q).
+// Partial g_at over one span of columns: part[sp][al][q][h] =
+// sum_{bt in span sp} conj(Phat[al][q][bt]) bt[bt][q][h]; one workgroup per
+// (64 images, q, span).  The next tile of 16 columns is fetched into registers
+// while the current one is used.
 template <typename R>
 __global__ __launch_bounds__(256) void k_bwd_gAt(const cx<R> *__restrict__ Bg, const cx<double> *__restrict__ Phat,
-                                                 const double *__restrict__ kappa, int a0, int na_chunk, int NBT,
-                                                 int Qs, int H, cx<double> *__restrict__ gAt) {
+                                                 int na_chunk, int NBT, int Qs, int H, int span,
+                                                 cx<double> *__restrict__ part) {
     __shared__ cx<double> sP[64][17];
     __shared__ cx<double> sB[16][kMaxH];
-    const int q = blockIdx.y, al0 = blockIdx.x * 64;
+    const int q = blockIdx.y, al0 = blockIdx.x * 64, sp = blockIdx.z;
+    const int c_begin = sp * span, c_end = min(NBT, c_begin + span);
     const int tid = threadIdx.x, al = tid & 63, hg = tid >> 6;
     cx<double> acc[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) acc[i] = cx<double>{0.0, 0.0};
-    for (int c0 = 0; c0 < NBT; c0 += 16) {
-        for (int e = tid; e < 64 * 16; e += 256) {
-            const int aa = e >> 4, bb = e & 15;
-            cx<double> v = {0.0, 0.0};
-            if (al0 + aa < na_chunk && c0 + bb < NBT) v = Phat[((size_t)(al0 + aa) * Qs + q) * NBT + c0 + bb];
-            sP[aa][bb] = v;
+    cx<double> rp[4], rb[2];
+    auto fetch = [&](int c0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = tid + 256 * k, aa = e >> 4, bb = e & 15;
+            double vr = 0.0, vi = 0.0;
+            if (al0 + aa < na_chunk && c0 + bb < c_end) {
+                const cx<double> *src = Phat + ((size_t)(al0 + aa) * Qs + q) * NBT + c0 + bb;
+                vr = src->re;
+                vi = src->im;
+            }
+            rp[k] = cx<double>{vr, vi};
         }
-        for (int e = tid; e < 16 * H; e += 256) {
-            const int bb = e / H, h = e - bb * H;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int e = tid + 256 * k;
             cx<double> v = {0.0, 0.0};
-            if (c0 + bb < NBT) v = up(Bg[((size_t)(c0 + bb) * Qs + q) * H + h]);
-            sB[bb][h] = v;
+            if (e < 16 * H) {
+                const int bb = e / H, h = e - bb * H;
+                if (c0 + bb < c_end) v = up(Bg[((size_t)(c0 + bb) * Qs + q) * H + h]);
+            }
+            rb[k] = v;
+        }
+    };
+    fetch(c_begin);
+    for (int c0 = c_begin; c0 < c_end; c0 += 16) {
+        __syncthreads();   // the previous tile is consumed
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int e = tid + 256 * k;
+            sP[e >> 4][e & 15] = rp[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int e = tid + 256 * k;
+            if (e < 16 * H) sB[e / H][e % H] = rb[k];
         }
         __syncthreads();
+        if (c0 + 16 < c_end) fetch(c0 + 16);
         for (int bb = 0; bb < 16; ++bb) {
             const cx<double> pv = cconj(sP[al][bb]);
 #pragma unroll
@@ -260,15 +366,24 @@ __global__ __launch_bounds__(256) void k_bwd_gAt(const cx<R> *__restrict__ Bg, c
                 if (h < H) acc[i] = cadd(acc[i], cmul(pv, sB[bb][h]));
             }
         }
-        __syncthreads();
     }
     if (al0 + al < na_chunk) {
-        const double kp = kappa[al0 + al];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int h = hg + 4 * i;
-            if (h < H) gAt[((size_t)(a0 + al0 + al) * Qs + q) * H + h] = cscale(acc[i], kp);
+            if (h < H) part[(((size_t)sp * na_chunk + al0 + al) * Qs + q) * H + h] = acc[i];
         }
+    }
+}
+
+// g_at[a0 + al][q][h] = kappa[al] sum_sp part[sp][al][q][h] (spans in order)
+__global__ void k_bwd_gAt_reduce(const cx<double> *__restrict__ part, const double *__restrict__ kappa, int a0,
+                                 int na_chunk, int QH, int nsplit, cx<double> *__restrict__ gAt) {
+    const size_t total = (size_t)na_chunk * QH;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        cx<double> v = part[i];
+        for (int sp = 1; sp < nsplit; ++sp) v = cadd(v, part[(size_t)sp * total + i]);
+        gAt[(size_t)a0 * QH + i] = cscale(v, kappa[i / QH]);
     }
 }
 
@@ -407,6 +522,7 @@ hipError_t run_backward(const radsvd_plan *p, float inv_s2, const float *lse_img
     double *kappa = reinterpret_cast<double *>(w + L.off_kappa);
     cx<double> *gBt = reinterpret_cast<cx<double> *>(w + L.off_gBt);
     cx<double> *gAt = reinterpret_cast<cx<double> *>(w + L.off_gAt);
+    cx<double> *gApart = reinterpret_cast<cx<double> *>(w + L.off_gApart);
     cx<double> *gBpsi = reinterpret_cast<cx<double> *>(w + L.off_gBpsi);
     cx<double> *gApsi = reinterpret_cast<cx<double> *>(w + L.off_gApsi);
     cx<double> *ph = reinterpret_cast<cx<double> *>(w + L.off_ph64);
@@ -419,9 +535,12 @@ hipError_t run_backward(const radsvd_plan *p, float inv_s2, const float *lse_img
 
     hipLaunchKernelGGL(k_bwd_phase, dim3((T * K * Q + 255) / 256 < 4096 ? (T * K * Q + 255) / 256 : 4096), dim3(256),
                        0, s, p->d_k, p->d_delta, K, Q, T, ph);
-    // translations per group: their rows fill up to ~120 KB of LDS
-    const int TG = max(1, min(T, (int)(((size_t)120 * 1024 / ((size_t)Q * sizeof(cx<double>)) - 1) / 2)));
-    const size_t sh_phat = (size_t)(1 + 2 * TG) * Q * sizeof(cx<double>);
+    // translations per group: twiddles and the two row sets within ~40 KB of LDS
+    // (four workgroups per CU); a Hermitian row holds two translations
+    const int rows = max(1, (int)(((size_t)40 * 1024 / ((size_t)Q * sizeof(cx<double>)) - 1) / 2));
+    const int TG = max(1, min(T, p->herm ? 2 * rows : rows));
+    const int NR = p->herm ? (TG + 1) / 2 : TG;
+    const size_t sh_phat = (size_t)(1 + 2 * NR) * Q * sizeof(cx<double>);
     {
         hipError_t e = hipFuncSetAttribute((const void *)k_bwd_phat<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)sh_phat);
@@ -429,15 +548,23 @@ hipError_t run_backward(const radsvd_plan *p, float inv_s2, const float *lse_img
     }
     for (int a0 = 0; a0 < na; a0 += L.chunk) {
         const int ca = min(L.chunk, na - a0);
-        hipLaunchKernelGGL(k_bwd_phat<R>, dim3(nb, ca), dim3(256), sh_phat, s, Ag, Bg, a0, nb, T, TG, H, Q, Qs,
-                           p->herm, (double)inv_s2, lse_img, Phat, psum);
+        // targets per workgroup: amortise the set-up while keeping ~4k workgroups
+        const int nbw = max(1, min(16, (int)(((size_t)ca * nb) / 4096)));
+        hipLaunchKernelGGL(k_bwd_phat<R>, dim3((nb + nbw - 1) / nbw, ca), dim3(256), sh_phat, s, Ag, Bg, a0, nb, nbw,
+                           T, TG, H, Q, Qs, p->herm, (double)inv_s2, lse_img, Phat, psum);
         hipLaunchKernelGGL(k_bwd_kappa, dim3((ca + 255) / 256), dim3(256), 0, s, psum, glse, a0, ca, nb,
                            (double)inv_s2, kappa);
         hipLaunchKernelGGL(k_bwd_gBt<R>, dim3((NBT + 63) / 64, Qs), dim3(256), 0, s, Ag, Phat, kappa, a0, ca, NBT,
                            Qs, H, a0 > 0 ? 1 : 0, gBt);
-        if (want_U)
-            hipLaunchKernelGGL(k_bwd_gAt<R>, dim3((ca + 63) / 64, Qs), dim3(256), 0, s, Bg, Phat, kappa, a0, ca,
-                               NBT, Qs, H, gAt);
+        if (want_U) {
+            const int span = gat_span(ca, Qs, NBT), nsplit = (NBT + span - 1) / span;
+            hipLaunchKernelGGL(k_bwd_gAt<R>, dim3((ca + 63) / 64, Qs, nsplit), dim3(256), 0, s, Bg, Phat, ca, NBT, Qs,
+                               H, span, gApart);
+            const size_t tot = (size_t)ca * Qs * H;
+            const int nblk = (int)std::min<size_t>(4096, (tot + 255) / 256);
+            hipLaunchKernelGGL(k_bwd_gAt_reduce, dim3(nblk), dim3(256), 0, s, gApart, kappa, a0, ca, Qs * H, nsplit,
+                               gAt);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -40,78 +40,125 @@ __global__ __launch_bounds__(256) void k_ringsum(const cx<R> *__restrict__ B, in
 
 // Partial Gram over targets b in [b0, b1): P[split][r][r'] =
 // sum_b ( sum_j Re conj(B[b][r][j]) B[b][r'][j] - Re conj(S[b][r]) S[b][r'] / Q ),
-// the q != 0 part of each target's term.  64x64 output tile per block,
-// 4x4 outputs per thread; the contraction index (b, j) is staged through LDS
-// in chunks of 16 angles.
+// the q != 0 part of each target's term, for the 32x32 regions on and above
+// the diagonal (the finalisation reads r <= r' only).  Real FP64 GEMM on
+// v_mfma_f64_16x16x4f64 over the depth (b, j, re|im): a lane loads two
+// complex samples (4 reals) of its row and feeds them to four depth steps;
+// rows and columns use the same depth order, so the sum is the Gram entry.
+// One workgroup per (region, target split); its four waves take every fourth
+// target and add their sums in LDS in a fixed order.  Products of FP32 inputs
+// are exact in FP64; everything accumulates in FP64.
 template <typename R>
 __global__ __launch_bounds__(256) void k_gram_partial(const cx<R> *__restrict__ B, const double *__restrict__ S,
                                                       int n_tgt, int K, int Q, int b_per_split,
                                                       double *__restrict__ P) {
-    constexpr int TT = 64, CH = 16;
-    __shared__ double sre[2][TT][CH + 1];
-    __shared__ double sim[2][TT][CH + 1];
-    const int tr = blockIdx.x, tc = blockIdx.y, split = blockIdx.z;
-    const int r0 = tr * TT, c0 = tc * TT;
-    const int tid = threadIdx.x;
-    const int ty = tid / 16, tx = tid % 16;
-    double acc[4][4];
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    __shared__ double red[3][16][64];
+    const int NRB = (K + 31) / 32;
+    // region index -> (ri, ci), ri <= ci, row-major over the upper triangle
+    int ri = 0, rem = blockIdx.x;
+    while (rem >= NRB - ri) {
+        rem -= NRB - ri;
+        ++ri;
+    }
+    const int ci = ri + rem;
+    const int split = blockIdx.y;
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int r16 = l & 15, g = l >> 4;
+    int rowA[2], rowB[2];
+    bool okA[2], okB[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i) {
+        const int ra = ri * 32 + 16 * i + r16, cb = ci * 32 + 16 * i + r16;
+        okA[i] = ra < K;
+        okB[i] = cb < K;
+        rowA[i] = okA[i] ? ra : K - 1;
+        rowB[i] = okB[i] ? cb : K - 1;
+    }
+    f64x4 acc[2][2], accS[2][2];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+            accS[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
     const int b0 = split * b_per_split;
     const int b1 = min(n_tgt, b0 + b_per_split);
-    for (int b = b0; b < b1; ++b) {
+    // lane g of a chunk of 8 samples holds samples 2 g and 2 g + 1
+    auto load4 = [&](const cx<R> *row, int j, bool ok, double (&v)[4]) __attribute__((always_inline)) {
+        cx<R> x0 = {(R)0, (R)0}, x1 = {(R)0, (R)0};
+        if (ok && j < Q) x0 = row[j];
+        if (ok && j + 1 < Q) x1 = row[j + 1];
+        v[0] = (double)x0.re;
+        v[1] = (double)x0.im;
+        v[2] = (double)x1.re;
+        v[3] = (double)x1.im;
+    };
+    for (int b = b0 + w; b < b1; b += 4) {
         const cx<R> *Bb = B + (size_t)b * K * Q;
-        for (int j0 = 0; j0 < Q; j0 += CH) {
-            __syncthreads();
-            for (int i = tid; i < 2 * TT * CH; i += 256) {
-                const int side = i / (TT * CH);
-                const int rem = i - side * TT * CH;
-                const int rr = rem / CH, jj = rem - rr * CH;
-                const int row = (side == 0 ? r0 : c0) + rr;
-                const int j = j0 + jj;
-                cx<R> v = {(R)0, (R)0};
-                if (row < K && j < Q) v = Bb[(size_t)row * Q + j];
-                sre[side][rr][jj] = (double)v.re;
-                sim[side][rr][jj] = (double)v.im;
-            }
-            __syncthreads();
-            for (int jj = 0; jj < CH; ++jj) {
-                double ar[4], ai[4], br[4], bi[4];
+        const cx<R> *pa0 = Bb + (size_t)rowA[0] * Q, *pa1 = Bb + (size_t)rowA[1] * Q;
+        const cx<R> *pb0 = Bb + (size_t)rowB[0] * Q, *pb1 = Bb + (size_t)rowB[1] * Q;
+        for (int j0 = 0; j0 < Q; j0 += 8) {
+            const int j = j0 + 2 * g;
+            double a0[4], a1[4], c0[4], c1[4];
+            load4(pa0, j, okA[0], a0);
+            load4(pa1, j, okA[1], a1);
+            load4(pb0, j, okB[0], c0);
+            load4(pb1, j, okB[1], c1);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    ar[i] = sre[0][ty * 4 + i][jj];
-                    ai[i] = sim[0][ty * 4 + i][jj];
-                    br[i] = sre[1][tx * 4 + i][jj];
-                    bi[i] = sim[1][tx * 4 + i][jj];
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] += ar[i] * br[j] + ai[i] * bi[j];
-            }
-        }
-        // the q = 0 term of target b: Re conj(S[r]) S[r'] / Q
-        const double *sb = S + (size_t)b * K * 2;
-        const double iq = 1.0 / (double)Q;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = min(r0 + ty * 4 + i, K - 1);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = min(c0 + tx * 4 + j, K - 1);
-                acc[i][j] -= (sb[2 * r] * sb[2 * c] + sb[2 * r + 1] * sb[2 * c + 1]) * iq;
+            for (int s = 0; s < 4; ++s) {
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], c0[s], acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], c1[s], acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], c0[s], acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], c1[s], acc[1][1], 0, 0, 0);
             }
         }
     }
+    // the q = 0 terms: depth (b, re|im), lane group g -> target b + (g >> 1), part g & 1
+    for (int bb = b0 + 2 * w; bb < b1; bb += 8) {
+        const int b = bb + (g >> 1), part = g & 1;
+        const bool okb = b < b1;
+        const double *sb = S + (size_t)(okb ? b : b0) * K * 2;
+        double sa[2], sc[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int r = r0 + ty * 4 + i, c = c0 + tx * 4 + j;
-            if (r < K && c < K) P[((size_t)split * K + r) * K + c] = acc[i][j];
+        for (int i = 0; i < 2; ++i) {
+            sa[i] = (okb && okA[i]) ? sb[2 * rowA[i] + part] : 0.0;
+            sc[i] = (okb && okB[i]) ? sb[2 * rowB[i] + part] : 0.0;
         }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+                accS[i][jj] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], sc[jj], accS[i][jj], 0, 0, 0);
+    }
+    // lane layout of the 16x16 FP64 output: element v of lane l is row l / 16 + 4 v, column l % 16
+    const double iq = 1.0 / (double)Q;
+    double out[16];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[(i * 2 + jj) * 4 + v] = acc[i][jj][v] - accS[i][jj][v] * iq;
+    // waves 1..3 hand their sums to wave 0, which adds them in order
+    if (w > 0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) red[w - 1][e][l] = out[e];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            double v = out[e];
+            v += red[0][e][l];
+            v += red[1][e][l];
+            v += red[2][e][l];
+            const int i = e >> 3, jj = (e >> 2) & 1, vv = e & 3;
+            const int r = ri * 32 + 16 * i + g + 4 * vv, c = ci * 32 + 16 * jj + r16;
+            if (r < K && c < K) P[((size_t)split * K + r) * K + c] = v;
+        }
+    }
 }
 
 __global__ void k_C_finalize(const double *__restrict__ P, int nsplit, int n_tgt, int K,
@@ -129,20 +176,20 @@ __global__ void k_C_finalize(const double *__restrict__ P, int nsplit, int n_tgt
 hipError_t launch_kernel_C(radsvd_plan *p, hipStream_t s) {
     const int K = p->K, Q = p->Q, nb = p->n_tgt;
     const int waves = nb * K;
-    const int tiles = (K + 63) / 64;
+    const int nrb = (K + 31) / 32, nreg = nrb * (nrb + 1) / 2;
     const int nsplit = p->gram_nsplit;
     const int bps = (nb + nsplit - 1) / nsplit;
     if (p->prec == RADSVD_FP64) {
         const cx<double> *B = reinterpret_cast<const cx<double> *>(p->B_polar);
         hipLaunchKernelGGL(k_ringsum<double>, dim3((waves + 3) / 4), dim3(256), 0, s, B, nb, K, Q,
                            p->ringsum);
-        hipLaunchKernelGGL(k_gram_partial<double>, dim3(tiles, tiles, nsplit), dim3(256), 0, s, B,
+        hipLaunchKernelGGL(k_gram_partial<double>, dim3(nreg, nsplit), dim3(256), 0, s, B,
                            p->ringsum, nb, K, Q, bps, p->gram_part);
     } else {
         const cx<float> *B = reinterpret_cast<const cx<float> *>(p->B_polar);
         hipLaunchKernelGGL(k_ringsum<float>, dim3((waves + 3) / 4), dim3(256), 0, s, B, nb, K, Q,
                            p->ringsum);
-        hipLaunchKernelGGL(k_gram_partial<float>, dim3(tiles, tiles, nsplit), dim3(256), 0, s, B,
+        hipLaunchKernelGGL(k_gram_partial<float>, dim3(nreg, nsplit), dim3(256), 0, s, B,
                            p->ringsum, nb, K, Q, bps, p->gram_part);
     }
     hipLaunchKernelGGL(k_C_finalize, dim3((K * K + 255) / 256), dim3(256), 0, s, p->gram_part, nsplit, nb, K,

@@ -7,8 +7,12 @@
 // positive (first such entry on ties).
 //
 // Phase 1 rotates C (in LDS) to diagonal form and records every round's
-// rotations in a global log; phase 2 replays the log on V = I (in LDS, one
-// row per thread group), so neither phase waits on global-memory round trips.
+// rotations in a global log.  A round's K/2 rotations act on disjoint index
+// pairs, so the two-sided update splits into independent 2x2 blocks (pair k
+// rows x pair l columns) that one pass updates in place.  Phase 2 replays the
+// log on V = I (in LDS): a row of V only ever mixes with itself, so each wave
+// owns a set of rows and replays every round on them with no workgroup
+// barrier, fetching the next round's rotations while it applies the current.
 #include <math.h>
 
 #include "common.h"
@@ -99,24 +103,22 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
                 log[(size_t)nrounds * npair + tid] = Rot{p, q, c, s};
             }
             __syncthreads();
-            for (int i = tid; i < npair * KP; i += nt) {
-                const int k = i / KP, j = i - k * KP;
-                const double c = sc[k], s = ss[k];
-                if (s == 0.0) continue;
-                const int p = sp[k], q = sq[k];
-                const double a = A[p * ld + j], b = A[q * ld + j];
-                A[p * ld + j] = c * a - s * b;
-                A[q * ld + j] = s * a + c * b;
-            }
-            __syncthreads();
-            for (int i = tid; i < npair * KP; i += nt) {
-                const int k = i / KP, r = i - k * KP;
-                const double c = sc[k], s = ss[k];
-                if (s == 0.0) continue;
-                const int p = sp[k], q = sq[k];
-                const double a = A[r * ld + p], b = A[r * ld + q];
-                A[r * ld + p] = c * a - s * b;
-                A[r * ld + q] = s * a + c * b;
+            // block (k, l): rows {p_k, q_k} x columns {p_l, q_l}; rows rotate by
+            // (c_k, s_k), then columns by (c_l, s_l): x' = c x - s y, y' = s x + c y
+            for (int e = tid; e < 64 * 64; e += nt) {
+                const int k = e >> 6, l = e & 63;
+                if (k >= npair || l >= npair) continue;
+                const double ck = sc[k], sk = ss[k], cl = sc[l], sl = ss[l];
+                if (sk == 0.0 && sl == 0.0) continue;
+                const int pk = sp[k], qk = sq[k], pl = sp[l], ql = sq[l];
+                const double a00 = A[pk * ld + pl], a01 = A[pk * ld + ql];
+                const double a10 = A[qk * ld + pl], a11 = A[qk * ld + ql];
+                const double r00 = ck * a00 - sk * a10, r10 = sk * a00 + ck * a10;
+                const double r01 = ck * a01 - sk * a11, r11 = sk * a01 + ck * a11;
+                A[pk * ld + pl] = cl * r00 - sl * r01;
+                A[pk * ld + ql] = sl * r00 + cl * r01;
+                A[qk * ld + pl] = cl * r10 - sl * r11;
+                A[qk * ld + ql] = sl * r10 + cl * r11;
             }
             __syncthreads();
             ++nrounds;
@@ -128,33 +130,36 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
     __threadfence_block();
     __syncthreads();
     nrounds = nrounds_s;
-    // phase 2: V = product of the recorded rotations, applied to the identity
+    // phase 2: V = product of the recorded rotations, applied to the identity;
+    // wave wv owns rows wv, wv + nw, ..., lane k applies rotation k of a round
     double *V = sm;
     for (int i = tid; i < KP * KP; i += nt) {
         const int r = i / KP, c = i - r * KP;
         V[r * ld + c] = (r == c) ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int rd = 0; rd < nrounds; ++rd) {
-        if (tid < npair) {
-            const Rot g = log[(size_t)rd * npair + tid];
-            sp[tid] = g.p;
-            sq[tid] = g.q;
-            sc[tid] = g.c;
-            ss[tid] = g.s;
+    {
+        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+        const bool act = lane < npair;
+        Rot nx = {0, 0, 1.0, 0.0};
+        if (act && nrounds > 0) nx = log[lane];
+        for (int rd = 0; rd < nrounds; ++rd) {
+            const Rot g = nx;
+            if (act && rd + 1 < nrounds) nx = log[(size_t)(rd + 1) * npair + lane];
+            if (act && g.s != 0.0) {
+                for (int r = wv; r < KP; r += nw) {
+                    const double a = V[r * ld + g.p], b = V[r * ld + g.q];
+                    V[r * ld + g.p] = g.c * a - g.s * b;
+                    V[r * ld + g.q] = g.s * a + g.c * b;
+                }
+            }
+            // the next round's lanes read what other lanes of this wave wrote
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        __syncthreads();
-        for (int i = tid; i < npair * KP; i += nt) {
-            const int k = i / KP, r = i - k * KP;
-            const double c = sc[k], s = ss[k];
-            if (s == 0.0) continue;
-            const int p = sp[k], q = sq[k];
-            const double a = V[r * ld + p], b = V[r * ld + q];
-            V[r * ld + p] = c * a - s * b;
-            V[r * ld + q] = s * a + c * b;
-        }
-        __syncthreads();
     }
+    __syncthreads();
     // rank by descending eigenvalue (ties: lower index first)
     for (int i = tid; i < K; i += nt) {
         const double di = sdiag[i];

@@ -10,6 +10,8 @@
 
 #include <type_traits>
 
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -203,26 +205,25 @@ __global__ __launch_bounds__(256) void k_rings(
     }
 }
 
-// Output of the FP32 ring kernel, all H rows of ybuf at once (transformed in
-// place first).  Generic layout: one complex per thread, consecutive (q, h).
-// Fast layout: one thread per (q, fragment slot) gathers the slot's 8 (4 for
-// a half chunk) rank values, splits them into the plane format and writes
-// 16 (8) bytes per plane and row, the unit the pair kernel's lanes load.
-__device__ void emit_fast(cx<float> *ybuf, const int *pos_tab, int n, int t, int T, int Q, int H, int Qc,
-                          const FftPlan &pl, const cx<float> *tw, cx<float> *__restrict__ G,
-                          void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes,
-                          int is_img) {
+// Output of one block of rank rows h0 .. h0 + nr - 1 of a ring (nr <= 16; h0 a
+// multiple of 16), transformed in place in yb[0 .. nr).  Generic layout: one
+// complex per (q, h).  Fast layout (buffers zero-filled beforehand, so rows at
+// or beyond H are not written): a bf16 fragment slot gathers 8 (4 for a half
+// chunk) rank values, splits them into the plane format and writes 16 (8)
+// bytes per plane and row; an FP32 slot half holds depth k = 8 hc + 4 j + g,
+// j = 0, 1, of one re or im half-chunk hc (8 bytes).
+__device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_tab, int n, int t, int T, int Q,
+                           int H, int Qc, float scale, cx<float> *__restrict__ G, void *__restrict__ F, int f_kind,
+                           int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
     typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
     typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-    lds_fft_dif(ybuf, H, Q, pl, tw);
-    const float scale = (float)(1.0 / sqrt((double)Q));
     const int tid = threadIdx.x, nt = blockDim.x;
     if (G) {
         cx<float> *Gn = G + ((size_t)n * T + t) * Qc * H;
-        for (int i = tid; i < Qc * H; i += nt) {
-            const int q = i / H, h = i - q * H;
-            const cx<float> v = ybuf[h * Q + pos_tab[q]];
-            Gn[i] = cx<float>{v.re * scale, v.im * scale};
+        for (int i = tid; i < Qc * nr; i += nt) {
+            const int q = i / nr, hh = i - q * nr;
+            const cx<float> v = yb[hh * Q + pos_tab[q]];
+            Gn[(size_t)q * H + h0 + hh] = cx<float>{v.re * scale, v.im * scale};
         }
     }
     if (!F) return;
@@ -232,19 +233,19 @@ __device__ void emit_fast(cx<float> *ybuf, const int *pos_tab, int n, int t, int
     const int f_q = (Qc == Q) ? Q : Q / 2 + 1;
     const int tile = n / f_tile, n_in = n - tile * f_tile;
     const int row0 = is_img ? 2 * n_in : n_in;
-    auto val = [&](int h, int pos, int c) -> float {   // c: 0 re, 1 im
-        if (h >= H) return 0.f;
-        const cx<float> v = ybuf[h * Q + pos];
+    auto val = [&](int h, int pos, int c) -> float {   // c: 0 re, 1 im; zero past the block's rows
+        const int hh = h - h0;
+        if (hh < 0 || hh >= nr) return 0.f;
+        const cx<float> v = yb[hh * Q + pos];
         return (c ? v.im : v.re) * scale;
     };
     if (fbf) {
-        const int NF = H8 / 16, HF = (H8 % 16) ? 1 : 0;
-        const int nslots = 4 * (NF + HF);
-        for (int i = tid; i < Qc * nslots; i += nt) {
-            const int q = i / nslots, sl = i - q * nslots;
-            const int chunk = sl >> 2, g = sl & 3, c = g >> 1, hsub = g & 1;
-            const bool full = chunk < NF;
-            const int nv = full ? 8 : 4;
+        const int NF = H8 / 16;
+        const int chunk = h0 / 16;
+        const bool full = chunk < NF;
+        const int nv = full ? 8 : 4;
+        for (int i = tid; i < Qc * 4; i += nt) {
+            const int q = i >> 2, g = i & 3, c = g >> 1, hsub = g & 1;
             const int hb = full ? 16 * chunk + 8 * hsub : 16 * NF + 4 * hsub;
             const int pos = pos_tab[q];
             char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
@@ -277,133 +278,165 @@ __device__ void emit_fast(cx<float> *ybuf, const int *pos_tab, int n, int t, int
             }
         }
     } else {
-        // FP32 chunks of 16 depth values: lane slot g holds k = 16 chunk + 4 j + g, j = 0..3
-        const int nslots = 4 * (H8 / 8);
-        for (int i = tid; i < Qc * nslots; i += nt) {
-            const int q = i / nslots, sl = i - q * nslots;
-            const int chunk = sl >> 2, g = sl & 3;
+        // FP32 chunks of 16 depth values (re rows 0 .. H8 - 1, then im): slot g of
+        // chunk k / 16 holds k = 16 chunk + 4 j + g, j = 0..3; half-chunk hc =
+        // k / 8 is the slot's bytes 8 (hc & 1) .. + 8
+        const int nh = H8 / 8;
+        for (int i = tid; i < Qc * 16; i += nt) {
+            const int q = i >> 4, sel = (i >> 2) & 3, g = i & 3;
+            const int c = sel >> 1, hcr = h0 / 8 + (sel & 1);
+            if (8 * hcr >= h0 + nr) continue;   // rows past H: left zero
+            const int hc = c * nh + hcr;
             const int pos = pos_tab[q];
             char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
             for (int rr = 0; rr < (is_img ? 2 : 1); ++rr) {
-                u32x4_t wv;
+                u32x2_t wv;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int k = 16 * chunk + 4 * j + g;
-                    const int c = k >= H8 ? 1 : 0, h = k - c * H8;
+                for (int jj = 0; jj < 2; ++jj) {
+                    const int h = 8 * hcr + 4 * jj + g;
                     const float x = rr == 0 ? val(h, pos, c) : (c ? val(h, pos, 0) : -val(h, pos, 1));
-                    wv[j] = __float_as_uint(x);
+                    wv[jj] = __float_as_uint(x);
                 }
-                *reinterpret_cast<u32x4_t *>(blk + chunk * 1024 + (16 * g + row0 + rr) * 16) = wv;
+                *reinterpret_cast<u32x2_t *>(blk + (hc >> 1) * 1024 + (16 * g + row0 + rr) * 16 + 8 * (hc & 1)) = wv;
             }
         }
     }
 }
 
-// FP32 principal rings on the matrix cores.  Per item the recombination is
-// the real GEMM  Y[h][(j, re|im)] = sum_r Ueta[r][h] (phi_t[r][j] X[n][r][j])_{re|im}
+// FP32 principal rings on the matrix cores.  Per ring (item n, translation t)
+// the recombination is the real GEMM
+//   Y[h][(j, re|im)] = sum_r Ueta[r][h] (phi_t[r][j] X[n][r][j])_{re|im}
 // with M = H (one or two 16-row blocks), N = 2 Q and depth K, on
-// v_mfma_f32_16x16x4_f32: Ueta^T is staged in LDS (lane: row h, depth
-// r = 4 ks + l / 16), each wave takes a quarter of the blocks of 16 columns
-// (8 angles, re and im) with all their accumulators live while it walks r,
-// and the lane multiplies its (r, j) sample by the translation phase before
-// feeding it.  Y goes to LDS, then emit_fast.
-template <int NCBW, bool PHASE>   // column blocks per wave (>= the work); translation phase applied
+// v_mfma_f32_16x16x4_f32.  Lane (r16 = l % 16, rg = l / 16) takes depth
+// r = 4 ks + rg; one 16-byte load gives it angles j = 32 grp + 2 r16 and j + 1,
+// whose re and im parts feed four column blocks, so no sample is loaded twice
+// (weights Ueta come from global memory; lane r16 is rank row h).  Wave w
+// takes the angle groups w, w + 4, ...  Y is then transformed and written in
+// blocks of 16 rank rows, which keeps LDS small enough for two workgroups per
+// CU.  Workgroups loop over rings; each XCD runs one contiguous range of rings,
+// so the T translations of an item share its samples in one L2.
+template <int NG, bool PHASE, bool TWO>
 __global__ __launch_bounds__(256) void k_rings_mfma(
     const cx<float> *__restrict__ X, int n_real, int T, const cx<float> *__restrict__ phase,
     const float *__restrict__ Ueta, int K, int Q, int H, int Qc, cx<float> *__restrict__ G,
     void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
     typedef float f32x4_t __attribute__((ext_vector_type(4)));
     extern __shared__ unsigned char smem_raw[];
-    const int n = blockIdx.x / T;
-    const int t = blockIdx.x - n * T;
-    if (n >= n_real) return;
-    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    __shared__ FftPlan spl;           // in LDS: the stage loops index it at run time
+    __shared__ int pos_tab[kMaxQ];    // FFT output position of each frequency
     cx<float> *tw = reinterpret_cast<cx<float> *>(smem_raw);   // [Q]
-    cx<float> *ybuf = tw + Q;                                   // [16 NHB][Q]
+    cx<float> *ybuf = tw + Q;                                   // [16][Q]
+    const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     for (int i = tid; i < Q; i += blockDim.x) {
         double s, c;
         sincospi(-2.0 * (double)i / (double)Q, &s, &c);
         tw[i] = cx<float>{(float)c, (float)s};
     }
-    __shared__ FftPlan spl;   // in LDS: the stage loops index it at run time
-    if (threadIdx.x == 0) fft_init_plan(spl, Q);
+    if (tid == 0) fft_init_plan(spl, Q);
     __syncthreads();
     const FftPlan &pl = spl;
+    for (int q = tid; q < Q; q += blockDim.x) pos_tab[q] = fft_pos(q, pl);   // read after the ring loop's barriers
+    const float scale = (float)(1.0 / sqrt((double)Q));
     const int KS = (K + 3) >> 2;
-    const bool two = H > 16;
-    const int rl = l >> 4, hl = l & 15;
-    __shared__ float sU[kMaxK][33];   // Ueta[r][h], zero beyond K and H
-    __shared__ int pos_tab[kMaxQ];    // FFT output position of each frequency
-    for (int q = tid; q < Q; q += blockDim.x) pos_tab[q] = fft_pos(q, pl);
-    for (int i = tid; i < kMaxK * 32; i += blockDim.x) {
-        const int r = i >> 5, h = i & 31;
-        sU[r][h] = (r < K && h < H) ? Ueta[(size_t)r * H + h] : 0.f;
+    const int r16 = l & 15, rg = l >> 4;
+    const int R = n_real * T, nwg = gridDim.x, wg = blockIdx.x;
+    int first, last, step;
+    if (nwg >= 8) {   // XCD x = wg % 8 owns rings [R x / 8, R (x + 1) / 8)
+        const int x = wg & 7;
+        first = (int)(((long long)R * x) >> 3) + (wg >> 3);
+        last = (int)(((long long)R * (x + 1)) >> 3);
+        step = (nwg - x + 7) >> 3;
+    } else {
+        first = wg;
+        last = R;
+        step = nwg;
     }
-    __syncthreads();
-    const cx<float> *Xn = X + (size_t)n * K * Q;
-    const cx<float> *ph = PHASE ? phase + (size_t)t * K * Q : nullptr;
-    const int part = l & 1, jl = hl >> 1;
-    // wave w owns the contiguous column blocks [w NCBW, (w + 1) NCBW) (16 columns =
-    // 8 angles each) and keeps all their accumulators while it walks the depth r;
-    // out-of-range rows and angles read a valid address and feed a zero
-    const int NCB = (2 * Q + 15) / 16;
-    const int cb0 = w * NCBW;
-    f32x4_t acc0[NCBW], acc1[NCBW];
+    for (int ring = first; ring < last; ring += step) {
+        const int n = ring / T, t = ring - n * T;
+        const cx<float> *Xn = X + (size_t)n * K * Q;
+        const cx<float> *ph = PHASE ? phase + (size_t)t * K * Q : nullptr;
+        f32x4_t acc0[NG][4], acc1[NG][4];
 #pragma unroll
-    for (int i = 0; i < NCBW; ++i) {
-        acc0[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-        acc1[i] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    }
-    // samples of depth step ks are loaded one step ahead (explicit double buffer)
-    cx<float> xc[NCBW], pc[NCBW];
-    auto fetch = [&](int ks, cx<float> (&xv)[NCBW], cx<float> (&pv)[NCBW]) {
-        const size_t rb = (size_t)min(4 * ks + rl, K - 1) * Q;
+        for (int gi = 0; gi < NG; ++gi)
 #pragma unroll
-        for (int i = 0; i < NCBW; ++i) {
-            const size_t idx = rb + min((cb0 + i) * 8 + jl, Q - 1);
-            xv[i] = Xn[idx];
-            if constexpr (PHASE) pv[i] = ph[idx];
-        }
-    };
-    fetch(0, xc, pc);
-    for (int ks = 0; ks < KS; ++ks) {
-        cx<float> xn[NCBW], pn[NCBW];
-        fetch(min(ks + 1, KS - 1), xn, pn);
-        const int r = 4 * ks + rl;
-        const float a0 = sU[r][hl], a1 = sU[r][hl + 16];
-        const bool rok = r < K;
-#pragma unroll
-        for (int i = 0; i < NCBW; ++i) {
-            const int j = (cb0 + i) * 8 + jl;
-            cx<float> x = xc[i];
-            if constexpr (PHASE) x = cmul(pc[i], x);
-            const float b = (rok && j < Q) ? (part ? x.im : x.re) : 0.f;
-            acc0[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc0[i], 0, 0, 0);
-            acc1[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc1[i], 0, 0, 0);   // zero rows when H <= 16
-        }
-#pragma unroll
-        for (int i = 0; i < NCBW; ++i) {
-            xc[i] = xn[i];
-            if constexpr (PHASE) pc[i] = pn[i];
-        }
-    }
-    (void)NCB;
-    // output lane layout: rows 4 (l / 16) + v, column l % 16 (= angle j, part)
-    float *yb = reinterpret_cast<float *>(ybuf);
-#pragma unroll
-    for (int i = 0; i < NCBW; ++i) {
-        const int j = (cb0 + i) * 8 + jl;
-        if (j < Q) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int h = 4 * rl + v;
-                yb[((size_t)h * Q + j) * 2 + part] = acc0[i][v];
-                if (two) yb[((size_t)(h + 16) * Q + j) * 2 + part] = acc1[i][v];
+            for (int s4 = 0; s4 < 4; ++s4) {
+                acc0[gi][s4] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+                acc1[gi][s4] = f32x4_t{0.f, 0.f, 0.f, 0.f};
             }
+        // depth step ks: 16 bytes per angle group (clamped in range: rows >= K
+        // meet zero weights, angles >= Q are not written), one step ahead
+        auto fetch = [&](int ks, f32x4_t (&xv)[NG], f32x4_t (&pv)[NG], float &u0, float &u1)
+                         __attribute__((always_inline)) {
+            const int r = 4 * ks + rg;
+            const size_t rb = (size_t)min(r, K - 1) * Q;
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                const int j = min(32 * (w + 4 * gi) + 2 * r16, Q - 2);
+                xv[gi] = *reinterpret_cast<const f32x4_t *>(Xn + rb + j);
+                if constexpr (PHASE) pv[gi] = *reinterpret_cast<const f32x4_t *>(ph + rb + j);
+            }
+            u0 = (r < K && r16 < H) ? Ueta[(size_t)r * H + r16] : 0.f;
+            u1 = (TWO && r < K && r16 + 16 < H) ? Ueta[(size_t)r * H + r16 + 16] : 0.f;
+        };
+        f32x4_t xc[NG], pc[NG];
+        float uc0, uc1;
+        fetch(0, xc, pc, uc0, uc1);
+        for (int ks = 0; ks < KS; ++ks) {
+            f32x4_t xn[NG], pn[NG];
+            float un0, un1;
+            fetch(min(ks + 1, KS - 1), xn, pn, un0, un1);
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                f32x4_t v = xc[gi];
+                if constexpr (PHASE) {
+                    const f32x4_t p = pc[gi];
+                    v = f32x4_t{p[0] * xc[gi][0] - p[1] * xc[gi][1], p[0] * xc[gi][1] + p[1] * xc[gi][0],
+                                p[2] * xc[gi][2] - p[3] * xc[gi][3], p[2] * xc[gi][3] + p[3] * xc[gi][2]};
+                }
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    acc0[gi][s4] = __builtin_amdgcn_mfma_f32_16x16x4f32(uc0, v[s4], acc0[gi][s4], 0, 0, 0);
+                    if constexpr (TWO)
+                        acc1[gi][s4] = __builtin_amdgcn_mfma_f32_16x16x4f32(uc1, v[s4], acc1[gi][s4], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                xc[gi] = xn[gi];
+                if constexpr (PHASE) pc[gi] = pn[gi];
+            }
+            uc0 = un0;
+            uc1 = un1;
+        }
+        // output lane layout: rows 4 rg + v, column r16 of each column block;
+        // column blocks (re j, im j, re j+1, im j+1) are two adjacent complex
+        auto put = [&](f32x4_t (&acc)[NG][4], int nr) __attribute__((always_inline)) {
+#pragma unroll
+            for (int gi = 0; gi < NG; ++gi) {
+                const int j = 32 * (w + 4 * gi) + 2 * r16;
+                if (j < Q) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 4 * rg + v;
+                        if (row < nr)
+                            *reinterpret_cast<f32x4_t *>(ybuf + (size_t)row * Q + j) =
+                                f32x4_t{acc[gi][0][v], acc[gi][1][v], acc[gi][2][v], acc[gi][3][v]};
+                    }
+                }
+            }
+        };
+#pragma unroll
+        for (int bi = 0; bi < (TWO ? 2 : 1); ++bi) {
+            const int h0 = 16 * bi, nr = min(16, H - h0);
+            __syncthreads();   // earlier readers of ybuf are done
+            if (bi == 0) put(acc0, nr);
+            else put(acc1, nr);
+            __syncthreads();
+            lds_fft_dif(ybuf, nr, Q, pl, tw);
+            emit_block(ybuf, h0, nr, pos_tab, n, t, T, Q, H, Qc, scale, G, F, f_kind, f_tile, f_ntiles, H8, nplanes,
+                       is_img);
         }
     }
-    __syncthreads();
-    emit_fast(ybuf, pos_tab, n, t, T, Q, H, Qc, pl, tw, G, F, f_kind, f_tile, f_ntiles, H8, nplanes, is_img);
 }
 
 // zero fill of the fast operand buffers (a kernel rather than a memset, so
@@ -459,30 +492,31 @@ hipError_t launch_ueta(radsvd_plan *p, const double *U_src, int ld, hipStream_t 
 static hipError_t rings_side_mfma(radsvd_plan *p, const void *X, int n_real, int n_pad, int T, bool use_phase,
                                   void *G, void *F, int f_tile, int is_img, hipStream_t s) {
     const int Q = p->Q;
-    const int nhb = p->H > 16 ? 2 : 1;
-    const size_t shmem = (size_t)(1 + 16 * nhb) * Q * sizeof(cx<float>);
+    const size_t shmem = (size_t)17 * Q * sizeof(cx<float>);   // twiddles + 16 rows
     const int f_kind = p->prec == RADSVD_FP32 ? 0 : 1;
-    const int ncbw = ((2 * Q + 15) / 16 + 3) / 4;
+    const int ng = ((Q + 31) / 32 + 3) / 4;                     // angle groups per wave
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int rings = n_real * T;
+    const int grid = std::max(1, std::min(rings, 2 * cus));
     auto go = [&](auto kern) -> hipError_t {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(n_real * T), dim3(256), shmem, s, reinterpret_cast<const cx<float> *>(X),
-                           n_real, T, reinterpret_cast<const cx<float> *>(p->phase),
-                           reinterpret_cast<const float *>(p->Ueta), p->K, Q, p->H, p->Qc,
-                           reinterpret_cast<cx<float> *>(G), F, f_kind, f_tile, n_pad / f_tile, p->H8, p->nplanes,
-                           is_img);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), shmem, s, reinterpret_cast<const cx<float> *>(X), n_real, T,
+                           reinterpret_cast<const cx<float> *>(p->phase), reinterpret_cast<const float *>(p->Ueta),
+                           p->K, Q, p->H, p->Qc, reinterpret_cast<cx<float> *>(G), F, f_kind, f_tile,
+                           n_pad / f_tile, p->H8, p->nplanes, is_img);
         return hipGetLastError();
     };
+    auto pick2 = [&](auto phase_tag, auto two_tag) -> hipError_t {
+        constexpr bool PH = decltype(phase_tag)::value, TW = decltype(two_tag)::value;
+        if (ng <= 1) return go(k_rings_mfma<1, PH, TW>);
+        if (ng <= 2) return go(k_rings_mfma<2, PH, TW>);
+        if (ng <= 3) return go(k_rings_mfma<3, PH, TW>);
+        return go(k_rings_mfma<4, PH, TW>);
+    };
     auto pick = [&](auto phase_tag) -> hipError_t {
-        constexpr bool PH = decltype(phase_tag)::value;
-        if (ncbw <= 1) return go(k_rings_mfma<1, PH>);
-        if (ncbw <= 2) return go(k_rings_mfma<2, PH>);
-        if (ncbw <= 3) return go(k_rings_mfma<3, PH>);
-        if (ncbw <= 4) return go(k_rings_mfma<4, PH>);
-        if (ncbw <= 6) return go(k_rings_mfma<6, PH>);
-        if (ncbw <= 8) return go(k_rings_mfma<8, PH>);
-        if (ncbw <= 12) return go(k_rings_mfma<12, PH>);
-        return go(k_rings_mfma<16, PH>);
+        return p->H > 16 ? pick2(phase_tag, std::true_type{}) : pick2(phase_tag, std::false_type{});
     };
     return use_phase ? pick(std::true_type{}) : pick(std::false_type{});
 }

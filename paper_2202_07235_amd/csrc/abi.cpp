@@ -64,7 +64,7 @@ struct Layout {
     size_t off_k, off_eta, off_delta, off_phase, off_C, off_U, off_lam, off_ueta, off_rsum, off_gram,
         off_Ag, off_Bg, off_Af, off_Bf, off_log, total;
     size_t Af_bytes, Bf_bytes;
-    int nsplit, H8, nplanes, na_pad, nb_pad, Qc;
+    int nsplit, H8, nplanes, ffmt, na_pad, nb_pad, Qc;
     bool fast;
 };
 
@@ -76,7 +76,11 @@ Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
     L.Qc = pr->hermitian ? Q / 2 + 1 : Q;
     L.fast = pr->hermitian && pr->prec != RADSVD_FP64;
     L.H8 = (H + 7) / 8 * 8;
-    L.nplanes = (pr->prec == RADSVD_BF16X3) ? (pr->products == 3 ? 2 : 3) : 1;
+    // bf16x3 with 6 products keeps FP32 values (in bf16 fragment order) and
+    // splits them into three bf16 terms in registers; 3 products load two planes
+    const bool split_in_regs = pr->prec == RADSVD_BF16X3 && pr->products != 3;
+    L.ffmt = pr->prec == RADSVD_FP32 ? kFragF32 : (split_in_regs ? kFragF32B : kFragBF16);
+    L.nplanes = (pr->prec == RADSVD_BF16X3 && pr->products == 3) ? 2 : 1;
     L.na_pad = (n_img + kFastTA - 1) / kFastTA * kFastTA;
     L.nb_pad = (n_tgt + kFastTB - 1) / kFastTB * kFastTB;
     const int tiles = (K + 63) / 64;
@@ -107,7 +111,7 @@ Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
     L.off_Bg = take((size_t)n_tgt * T * L.Qc * H * CX);
     if (L.fast) {
         // one fragment-ordered operand block per (tile, q): 8 images or 16 targets
-        const size_t blk = (size_t)L.nplanes * frag_plane_bytes(pr->prec != RADSVD_FP32, L.H8);
+        const size_t blk = (size_t)L.nplanes * frag_plane_bytes(L.ffmt, L.H8);
         L.Af_bytes = (size_t)(L.na_pad / kFastTA) * L.Qc * blk;
         L.Bf_bytes = (size_t)T * (L.nb_pad / kFastTB) * L.Qc * blk;
         L.off_Af = take(L.Af_bytes);
@@ -168,6 +172,7 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
     p->Qc = L.Qc;
     p->H8 = L.H8;
     p->nplanes = L.nplanes;
+    p->ffmt = L.ffmt;
     p->na_pad = L.na_pad;
     p->nb_pad = L.nb_pad;
     p->user_U = U_in != nullptr;

@@ -35,27 +35,38 @@ constexpr int kFastTB = 16;    // targets per tile  (16 MFMA columns)
 // (512 B) block.  The depth index of the real embedding of conj(a) b is
 // k = c * H8 + h with c = 0 / 1 the first / second block:
 //   image Re row [ar | ai], image Im row [-ai | ar], target column [br | bi].
-// BF16 planes: chunks of 16 h (v_mfma_f32_16x16x32_bf16; lane l: row l % 16,
-//   c = (l / 16) / 2, h = 16 chunk + 8 ((l / 16) % 2) + 0..7) and, when H8 is
-//   an odd multiple of 8, one half chunk of 8 h (v_mfma_f32_16x16x16_bf16;
-//   lane l: c = (l / 16) / 2, h = 4 ((l / 16) % 2) + 0..3, 8 bytes per lane).
-// FP32 plane: chunks of 16 consecutive k (v_mfma_f32_16x16x4_f32; lane l's
+// Formats (kFragF32, kFragBF16, kFragF32B):
+// * BF16 planes: chunks of 16 h (v_mfma_f32_16x16x32_bf16; lane l: row
+//   l % 16, c = (l / 16) / 2, h = 16 chunk + 8 ((l / 16) % 2) + 0..7) and,
+//   when H8 is an odd multiple of 8, one half chunk of 8 h
+//   (v_mfma_f32_16x16x16_bf16; lane l: c = (l / 16) / 2,
+//   h = 4 ((l / 16) % 2) + 0..3, 8 bytes per lane).
+// * FP32 in BF16 fragment order (one plane, split into bf16 terms in
+//   registers): the same lane mapping with FP32 values; a chunk is two 1 KB
+//   halves (lane l's values 0..3, then 4..7, 16 bytes each), the half chunk
+//   one 1 KB block (lane l's 4 values).
+// * FP32 plane: chunks of 16 consecutive k (v_mfma_f32_16x16x4_f32; lane l's
 //   element j feeds the chunk's MFMA j with k = 16 chunk + 4 j + l / 16).
-__host__ __device__ inline int frag_plane_bytes(bool bf16, int H8) {
-    return bf16 ? (H8 / 16) * 1024 + ((H8 % 16) ? 512 : 0) : (H8 / 8) * 1024;
+constexpr int kFragF32 = 0, kFragBF16 = 1, kFragF32B = 2;
+__host__ __device__ inline int frag_plane_bytes(int fmt, int H8) {
+    if (fmt == kFragBF16) return (H8 / 16) * 1024 + ((H8 % 16) ? 512 : 0);
+    if (fmt == kFragF32B) return (H8 / 16) * 2048 + ((H8 % 16) ? 1024 : 0);
+    return (H8 / 8) * 1024;
 }
 // byte offset of element (row, c, h) within one plane of an operand block
-__host__ __device__ inline int frag_elem_offset(bool bf16, int H8, int row, int c, int h) {
-    if (bf16) {
+__host__ __device__ inline int frag_elem_offset(int fmt, int H8, int row, int c, int h) {
+    if (fmt != kFragF32) {
+        const bool b16 = fmt == kFragBF16;
         const int nfull = H8 / 16;
         if (h < 16 * nfull) {
             const int hb = h >> 4, hh = h & 15;
-            const int g = 2 * c + (hh >> 3);
-            return hb * 1024 + (16 * g + row) * 16 + (hh & 7) * 2;
+            const int g = 2 * c + (hh >> 3), e = hh & 7;
+            return b16 ? hb * 1024 + (16 * g + row) * 16 + e * 2
+                       : hb * 2048 + (e >> 2) * 1024 + (16 * g + row) * 16 + (e & 3) * 4;
         }
         const int hh = h - 16 * nfull;
-        const int g = 2 * c + (hh >> 2);
-        return nfull * 1024 + (16 * g + row) * 8 + (hh & 3) * 2;
+        const int g = 2 * c + (hh >> 2), e = hh & 3;
+        return b16 ? nfull * 1024 + (16 * g + row) * 8 + e * 2 : nfull * 2048 + (16 * g + row) * 16 + e * 4;
     }
     const int k = c * H8 + h;
     const int chunk = k >> 4, kk = k & 15;
@@ -69,7 +80,8 @@ struct radsvd_plan {
     int M;       // Q / 2
     int Qc;      // frequencies stored: herm ? Q/2 + 1 : Q
     int H8;      // H rounded up to a multiple of 8 (fast operand rows)
-    int nplanes; // fast operand planes (bf16: 1/2/3; fp32: 1)
+    int nplanes; // fast operand planes (bf16: 1/2; fp32 and fp32-in-bf16-order: 1)
+    int ffmt;    // fast operand format: kFragF32, kFragBF16 or kFragF32B
     int na_pad, nb_pad;   // counts padded to the fast tile sizes
     int user_U;
     int band;    // image tiles per XCD band of the fast path's tile order (0 = default)

@@ -252,10 +252,12 @@ __device__ __forceinline__ void tile_of(int wg, int nwg, int nTA, int nTB, int b
 //   KIND 0: FP32 operands, v_mfma_f32_16x16x4_f32
 //   KIND 1: bf16 (one product), v_mfma_f32_16x16x32_bf16 (+ 16x16x16 for a half chunk)
 //   KIND 2: split bf16, products hi*hi, hi*mid, mid*hi
-//   KIND 3: split bf16, + mid*mid, hi*lo, lo*hi
+//   KIND 3: split bf16, + mid*mid, hi*lo, lo*hi; the operands are stored as
+//           FP32 values in bf16 fragment order and split in registers
 template <int KIND>
 struct Prec {
-    static constexpr int NPL = KIND == 0 ? 1 : (KIND == 3 ? 3 : (KIND == 2 ? 2 : 1));   // planes loaded
+    static constexpr int NPL = KIND == 0 ? 1 : (KIND == 3 ? 3 : (KIND == 2 ? 2 : 1));   // planes multiplied
+    static constexpr int NPL_MEM = KIND == 3 ? 1 : NPL;                                 // planes loaded
     static constexpr int NPROD = KIND == 3 ? 6 : (KIND == 2 ? 3 : 1);
     static constexpr int pa(int p) { return p == 2 ? 1 : (p == 3 ? 1 : (p == 5 ? 2 : 0)); }   // A plane
     static constexpr int pb(int p) { return p == 1 ? 1 : (p == 3 ? 1 : (p == 4 ? 2 : 0)); }   // B plane
@@ -271,6 +273,51 @@ struct Frag {
     u32x2 ah[Prec<KIND>::NPL];
     u32x2 bh[Prec<KIND>::NPL];
 };
+// KIND 3: the FP32 values themselves, 8 per lane and chunk (two 16-byte
+// halves), 4 in the half chunk
+template <int NF, int HF>
+struct Frag<3, NF, HF> {
+    u32x4 a[NF > 0 ? NF : 1][2];
+    u32x4 b[NF > 0 ? NF : 1][2];
+    u32x4 ah, bh;
+};
+
+// x = hi + mid + lo in bf16 (round to nearest even at each step; the
+// remainders x - hi and x - hi - mid are exact in FP32), two values at a time
+// on v_cvt_pk_bf16_f32.  Same terms as the host-side split of the bf16 planes.
+__device__ __forceinline__ void split3_pair(unsigned x0, unsigned x1, unsigned &hi, unsigned &mid, unsigned &lo) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    f32x2 x = {__uint_as_float(x0), __uint_as_float(x1)};
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2));
+    x = f32x2{x[0] - __uint_as_float(hi << 16), x[1] - __uint_as_float(hi & 0xffff0000u)};
+    mid = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2));
+    x = f32x2{x[0] - __uint_as_float(mid << 16), x[1] - __uint_as_float(mid & 0xffff0000u)};
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf16x2));
+}
+// 8 FP32 values (r0: values 0..3, r1: 4..7) -> bf16x8 hi, mid, lo
+__device__ __forceinline__ void split3_frag8(const u32x4 &r0, const u32x4 &r1, u32x4 (&pl)[3]) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const u32x4 &r = d < 2 ? r0 : r1;
+        unsigned h, m, o;
+        split3_pair(r[2 * (d & 1)], r[2 * (d & 1) + 1], h, m, o);
+        pl[0][d] = h;
+        pl[1][d] = m;
+        pl[2][d] = o;
+    }
+}
+// 4 FP32 values -> bf16x4 hi, mid, lo
+__device__ __forceinline__ void split3_frag4(const u32x4 &r, u32x2 (&pl)[3]) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        unsigned h, m, o;
+        split3_pair(r[2 * d], r[2 * d + 1], h, m, o);
+        pl[0][d] = h;
+        pl[1][d] = m;
+        pl[2][d] = o;
+    }
+}
 
 // One tile (ta, tb) for all translations.  Q angles; KIND contraction
 // precision; NF, HF operand chunks per plane (FP32: NF = H8 / 8 chunks of 16
@@ -322,12 +369,14 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     // M - 8R - 2w - (j - 2) (upper, j = 2, 3); the wave part of q lives in the
     // per-lane offsets, the round part is a compile-time scalar offset.
     const int g = l >> 4, i16 = l & 15;        // MFMA output: rows 4g..4g+3, column i16
-    constexpr int PB = NF * 1024 + HF * 512;   // bytes per plane
-    constexpr int BB = PR::NPL * PB;           // bytes per (tile, q) block
+    constexpr bool F32B = KIND == 3;              // FP32 values in bf16 fragment order
+    constexpr int CHB = F32B ? 2048 : 1024;       // bytes per full chunk
+    constexpr int PB = NF * CHB + HF * (CHB / 2); // bytes per plane
+    constexpr int BB = PR::NPL_MEM * PB;          // bytes per (tile, q) block
     const int vlo = 2 * w * BB;
     const int vhi = (M / 2 + 7 - 2 * w) * BB;
     const int vF_lo = 16 * l + vlo, vF_hi = 16 * l + vhi;
-    const int vH_lo = 8 * l + NF * 1024 + vlo, vH_hi = 8 * l + NF * 1024 + vhi;
+    const int vH_lo = (F32B ? 16 : 8) * l + NF * CHB + vlo, vH_hi = (F32B ? 16 : 8) * l + NF * CHB + vhi;
     const char *Abase = Af + (size_t)ta * (M + 1) * BB;
     const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
         (void *)Abase, (short)0, (M + 1) * BB, 0x00020000);
@@ -355,6 +404,20 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     auto load_at = [&](const __amdgpu_buffer_rsrc_t &rB, bool upper, int soff, FragT &f) {
         const int vF = upper ? vF_hi : vF_lo;
         const int vH = upper ? vH_hi : vH_lo;
+        if constexpr (F32B) {
+#pragma unroll
+            for (int hb = 0; hb < NF; ++hb)
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    f.a[hb][s2] = __builtin_amdgcn_raw_buffer_load_b128(rA, vF + hb * 2048 + s2 * 1024, soff, 0);
+                    f.b[hb][s2] = __builtin_amdgcn_raw_buffer_load_b128(rB, vF + hb * 2048 + s2 * 1024, soff, 0);
+                }
+            if constexpr (HF) {
+                f.ah = __builtin_amdgcn_raw_buffer_load_b128(rA, vH, soff, 0);
+                f.bh = __builtin_amdgcn_raw_buffer_load_b128(rB, vH, soff, 0);
+            }
+            return;
+        } else {
 #pragma unroll
         for (int pl = 0; pl < PR::NPL; ++pl) {
 #pragma unroll
@@ -367,10 +430,41 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                 f.bh[pl] = __builtin_amdgcn_raw_buffer_load_b64(rB, vH + pl * PB, soff, 0);
             }
         }
+        }
     };
     auto mma = [&](const FragT &f) -> f32x4 {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (BF) {
+        if constexpr (F32B) {
+            // split the FP32 values into hi, mid, lo, then the products of KIND 3 in its order
+            f32x4 acch = {0.f, 0.f, 0.f, 0.f};
+            u32x4 pa_[NF > 0 ? NF : 1][3], pb_[NF > 0 ? NF : 1][3];
+            u32x2 pah[3], pbh[3];
+#pragma unroll
+            for (int hb = 0; hb < NF; ++hb) {
+                split3_frag8(f.a[hb][0], f.a[hb][1], pa_[hb]);
+                split3_frag8(f.b[hb][0], f.b[hb][1], pb_[hb]);
+            }
+            if constexpr (HF) {
+                split3_frag4(f.ah, pah);
+                split3_frag4(f.bh, pbh);
+            }
+#pragma unroll
+            for (int p = 0; p < PR::NPROD; ++p) {
+#pragma unroll
+                for (int hb = 0; hb < NF; ++hb)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pa_[hb][PR::pa(p)]),
+                                                                 __builtin_bit_cast(bf16x8, pb_[hb][PR::pb(p)]),
+                                                                 acc, 0, 0, 0);
+                if constexpr (HF)
+                    acch = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, pah[PR::pa(p)]),
+                                                                    __builtin_bit_cast(s16x4, pbh[PR::pb(p)]),
+                                                                    acch, 0, 0, 0);
+            }
+            if constexpr (HF) {
+                if constexpr (NF > 0) acc += acch;
+                else acc = acch;
+            }
+        } else if constexpr (BF) {
             // the half chunk (v_mfma_f32_16x16x16_bf16) accumulates in a chain of its own:
             // every accumulation chain then has a single MFMA opcode
             f32x4 acch = {0.f, 0.f, 0.f, 0.f};
@@ -410,7 +504,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     };
     const int Ps = sidx(P);
 
-    constexpr int FRAG_REGS = 2 * PR::NPL * (4 * NF + 2 * HF);
+    constexpr int FRAG_REGS = F32B ? 2 * (8 * NF + 4 * HF) : 2 * PR::NPL * (4 * NF + 2 * HF);
     // prefetch depth in jobs: as deep as the registers beside the FFT state allow
     constexpr int D = FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 32 ? 4 : (FRAG_REGS <= 48 ? 3 : 2));
     constexpr int NJ = 4 * NRP;

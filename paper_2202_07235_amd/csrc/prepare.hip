@@ -81,8 +81,8 @@ template <typename R>
 __device__ void emit_rows(cx<R> *ybuf, int nrows, int h0, int n, int t, int T, int Q, int H, int Qc,
                           const FftPlan &pl, const cx<R> *tw, cx<R> *__restrict__ G, void *__restrict__ F,
                           int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
-    const bool fbf = f_kind != 0;
-    const int planeB = frag_plane_bytes(fbf, H8);
+    const bool fbf = f_kind == kFragBF16;   // bf16 planes; otherwise FP32 values
+    const int planeB = frag_plane_bytes(f_kind, H8);
     const size_t blockB = (size_t)nplanes * planeB;
     const int f_q = (Qc == Q) ? Q : Q / 2 + 1;
     const int tile = n / f_tile, n_in = n - tile * f_tile;
@@ -100,10 +100,10 @@ __device__ void emit_rows(cx<R> *ybuf, int nrows, int h0, int n, int t, int T, i
             // target n_in: column [br | bi]
             char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
             const int r0 = is_img ? 2 * n_in : n_in;
-            const int o_re = frag_elem_offset(fbf, H8, r0, 0, h);
-            const int o_im = frag_elem_offset(fbf, H8, r0, 1, h);
-            const int o_nim = is_img ? frag_elem_offset(fbf, H8, r0 + 1, 0, h) : 0;
-            const int o_re2 = is_img ? frag_elem_offset(fbf, H8, r0 + 1, 1, h) : 0;
+            const int o_re = frag_elem_offset(f_kind, H8, r0, 0, h);
+            const int o_im = frag_elem_offset(f_kind, H8, r0, 1, h);
+            const int o_nim = is_img ? frag_elem_offset(f_kind, H8, r0 + 1, 0, h) : 0;
+            const int o_re2 = is_img ? frag_elem_offset(f_kind, H8, r0 + 1, 1, h) : 0;
             if (!fbf) {
                 *reinterpret_cast<float *>(blk + o_re) = (float)v.re;
                 *reinterpret_cast<float *>(blk + o_im) = (float)v.im;
@@ -227,8 +227,9 @@ __device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_t
         }
     }
     if (!F) return;
-    const bool fbf = f_kind != 0;
-    const int planeB = frag_plane_bytes(fbf, H8);
+    const bool fbf = f_kind != kFragF32;
+    const bool f32b = f_kind == kFragF32B;
+    const int planeB = frag_plane_bytes(f_kind, H8);
     const size_t blockB = (size_t)nplanes * planeB;
     const int f_q = (Qc == Q) ? Q : Q / 2 + 1;
     const int tile = n / f_tile, n_in = n - tile * f_tile;
@@ -252,13 +253,30 @@ __device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_t
             // Re row / target column: c = 0 -> re, 1 -> im; image Im row: c = 0 -> -im, 1 -> re
             for (int rr = 0; rr < (is_img ? 2 : 1); ++rr) {
                 uint16_t pk[3][8];
+                float xs[8];
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     float x = 0.f;
                     if (e < nv) x = rr == 0 ? val(hb + e, pos, c) : (c ? val(hb + e, pos, 0) : -val(hb + e, pos, 1));
-                    split3_bf16(x, pk[0][e], pk[1][e], pk[2][e]);
+                    xs[e] = x;
+                    if (!f32b) split3_bf16(x, pk[0][e], pk[1][e], pk[2][e]);
                 }
                 const int row = row0 + rr;
+                if (f32b) {   // FP32 values in bf16 fragment order: 16-byte halves 1 KB apart
+                    u32x4_t w0, w1;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        w0[d] = __float_as_uint(xs[d]);
+                        w1[d] = __float_as_uint(xs[4 + d]);
+                    }
+                    if (full) {
+                        *reinterpret_cast<u32x4_t *>(blk + chunk * 2048 + (16 * g + row) * 16) = w0;
+                        *reinterpret_cast<u32x4_t *>(blk + chunk * 2048 + 1024 + (16 * g + row) * 16) = w1;
+                    } else {
+                        *reinterpret_cast<u32x4_t *>(blk + NF * 2048 + (16 * g + row) * 16) = w0;
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int pl_i = 0; pl_i < 3; ++pl_i) {
                     if (pl_i >= nplanes) break;
@@ -493,7 +511,7 @@ static hipError_t rings_side_mfma(radsvd_plan *p, const void *X, int n_real, int
                                   void *G, void *F, int f_tile, int is_img, hipStream_t s) {
     const int Q = p->Q;
     const size_t shmem = (size_t)17 * Q * sizeof(cx<float>);   // twiddles + 16 rows
-    const int f_kind = p->prec == RADSVD_FP32 ? 0 : 1;
+    const int f_kind = p->ffmt;
     const int ng = ((Q + 31) / 32 + 3) / 4;                     // angle groups per wave
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -530,7 +548,7 @@ static hipError_t rings_side(radsvd_plan *p, const void *X, int n_real, int n_pa
     if (FC < 1) FC = 1;
     if (FC > HP) FC = HP;
     const size_t shmem = (size_t)Q * cxb + (size_t)FC * Q * cxb;
-    const int f_kind = (p->prec == RADSVD_FP32 || p->prec == RADSVD_FP64) ? 0 : 1;
+    const int f_kind = p->prec == RADSVD_FP64 ? kFragF32 : p->ffmt;
     const int f_ntiles = n_pad / f_tile;
     const int items = n_real * T;   // padding items of the fast layout stay zero
     hipLaunchKernelGGL((k_rings<R, HP>), dim3(items), dim3(256), shmem, s,

@@ -331,7 +331,9 @@ def main():
         flops_contract / (PEAK_FP32_MATRIX_TFLOPS * 1e12)
     t_valu = flops_fft / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
     H8 = (H + 7) // 8 * 8
-    planes = {"fp32": 2, "bf16": 1, "bf16x3": 2 if a.products == 3 else 3}[a.precision]
+    # operand bytes per real value, in 2-byte units: FP32 4 B; bf16 2 B; bf16x3 two bf16 planes
+    # (3 products) or FP32 values split in registers (6 products), 4 B either way
+    planes = {"fp32": 2, "bf16": 1, "bf16x3": 2}[a.precision]
     bytes_min = (cfg.n_img + cfg.n_tgt * cfg.T) * M1 * 2 * H8 * 2 * planes + n_pairs * 12
     t_hbm = bytes_min / (PEAK_HBM_GBS * 1e9)
     bound = max(("mfma", t_mfma), ("alu", t_valu), ("hbm", t_hbm), key=lambda kv: kv[1])

@@ -432,11 +432,24 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
         }
         }
     };
+    // The MFMAs of one job accumulate in several independent chains (a
+    // product's predecessor in its chain is several instructions back, so the
+    // wave does not wait on each result), summed in a fixed order at the end.
+    // Full chunks and the half chunk (v_mfma_f32_16x16x16_bf16) never share a
+    // chain: every chain has a single MFMA opcode.
+    // Chains per kind (measured): split bf16 with 3 products 3 + 2; the other
+    // kinds one chain each (with 6 products more chains cost prefetch depth
+    // or VALU and measured slower; FP32 measured slower too).
+    constexpr int NCF = KIND == 2 ? 3 : 1;
+    constexpr int NCH = KIND == 2 ? 2 : 1;
     auto mma = [&](const FragT &f) -> f32x4 {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        f32x4 ac[NCF], ah[NCH];
+#pragma unroll
+        for (int c = 0; c < NCF; ++c) ac[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) ah[c] = f32x4{0.f, 0.f, 0.f, 0.f};
         if constexpr (F32B) {
-            // split the FP32 values into hi, mid, lo, then the products of KIND 3 in its order
-            f32x4 acch = {0.f, 0.f, 0.f, 0.f};
+            // split the FP32 values into hi, mid, lo, then the products of KIND 3
             u32x4 pa_[NF > 0 ? NF : 1][3], pb_[NF > 0 ? NF : 1][3];
             u32x2 pah[3], pbh[3];
 #pragma unroll
@@ -451,46 +464,51 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 #pragma unroll
             for (int p = 0; p < PR::NPROD; ++p) {
 #pragma unroll
-                for (int hb = 0; hb < NF; ++hb)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pa_[hb][PR::pa(p)]),
-                                                                 __builtin_bit_cast(bf16x8, pb_[hb][PR::pb(p)]),
-                                                                 acc, 0, 0, 0);
-                if constexpr (HF)
-                    acch = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, pah[PR::pa(p)]),
-                                                                    __builtin_bit_cast(s16x4, pbh[PR::pb(p)]),
-                                                                    acch, 0, 0, 0);
-            }
-            if constexpr (HF) {
-                if constexpr (NF > 0) acc += acch;
-                else acc = acch;
+                for (int hb = 0; hb < NF; ++hb) {
+                    f32x4 &c = ac[(p * NF + hb) % NCF];
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pa_[hb][PR::pa(p)]),
+                                                               __builtin_bit_cast(bf16x8, pb_[hb][PR::pb(p)]), c, 0, 0, 0);
+                }
+                if constexpr (HF) {
+                    f32x4 &c = ah[p % NCH];
+                    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, pah[PR::pa(p)]),
+                                                                 __builtin_bit_cast(s16x4, pbh[PR::pb(p)]), c, 0, 0, 0);
+                }
             }
         } else if constexpr (BF) {
-            // the half chunk (v_mfma_f32_16x16x16_bf16) accumulates in a chain of its own:
-            // every accumulation chain then has a single MFMA opcode
-            f32x4 acch = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int p = 0; p < PR::NPROD; ++p) {
 #pragma unroll
-                for (int hb = 0; hb < NF; ++hb)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, f.a[PR::pa(p)][hb]),
-                                                                 __builtin_bit_cast(bf16x8, f.b[PR::pb(p)][hb]),
-                                                                 acc, 0, 0, 0);
-                if constexpr (HF)
-                    acch = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, f.ah[PR::pa(p)]),
-                                                                    __builtin_bit_cast(s16x4, f.bh[PR::pb(p)]),
-                                                                    acch, 0, 0, 0);
-            }
-            if constexpr (HF) {
-                if constexpr (NF > 0) acc += acch;
-                else acc = acch;
+                for (int hb = 0; hb < NF; ++hb) {
+                    f32x4 &c = ac[(p * NF + hb) % NCF];
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, f.a[PR::pa(p)][hb]),
+                                                               __builtin_bit_cast(bf16x8, f.b[PR::pb(p)][hb]), c, 0, 0, 0);
+                }
+                if constexpr (HF) {
+                    f32x4 &c = ah[p % NCH];
+                    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, f.ah[PR::pa(p)]),
+                                                                 __builtin_bit_cast(s16x4, f.bh[PR::pb(p)]), c, 0, 0, 0);
+                }
             }
         } else {
 #pragma unroll
             for (int hb = 0; hb < NF; ++hb)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(f.a[0][hb][j]),
-                                                              __uint_as_float(f.b[0][hb][j]), acc, 0, 0, 0);
+                for (int j = 0; j < 4; ++j) {
+                    f32x4 &c = ac[(hb * 4 + j) % NCF];
+                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(f.a[0][hb][j]), __uint_as_float(f.b[0][hb][j]),
+                                                            c, 0, 0, 0);
+                }
+        }
+        f32x4 acc = ac[0];
+#pragma unroll
+        for (int c = 1; c < NCF; ++c) acc += ac[c];
+        if constexpr (HF) {
+            f32x4 hs = ah[0];
+#pragma unroll
+            for (int c = 1; c < NCH; ++c) hs += ah[c];
+            if constexpr (NF > 0) acc += hs;
+            else acc = hs;
         }
         return acc;
     };
@@ -506,7 +524,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 
     constexpr int FRAG_REGS = F32B ? 2 * (8 * NF + 4 * HF) : 2 * PR::NPL * (4 * NF + 2 * HF);
     // prefetch depth in jobs: as deep as the registers beside the FFT state allow
-    constexpr int D = FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 32 ? 4 : (FRAG_REGS <= 48 ? 3 : 2));
+    constexpr int D = FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 48 ? 3 : 2);
     constexpr int NJ = 4 * NRP;
     FragT fr[D + 1];
 

@@ -5,7 +5,7 @@
 //                  hi + mid + lo bf16 terms (each term is the rounding of what
 //                  the previous terms left), the operand format of the
 //                  split-precision contraction.
-// * FftPlan / lds_fft_dif : in-place mixed-radix (4, 2, 3) decimation-in-
+// * FftPlan / lds_fft_dif : in-place mixed-radix (8, 4, 2, 3) decimation-in-
 //                  frequency FFT of sequences held in LDS; the output of
 //                  frequency f sits at position fft_pos(f).
 #pragma once
@@ -96,6 +96,7 @@ __host__ __device__ inline void fft_init_plan(FftPlan &p, int n) {
     p.n = n;
     p.nst = 0;
     int m = n;
+    while (m % 8 == 0) { p.rad[p.nst++] = 8; m /= 8; }
     while (m % 4 == 0) { p.rad[p.nst++] = 4; m /= 4; }
     while (m % 2 == 0) { p.rad[p.nst++] = 2; m /= 2; }
     while (m % 3 == 0) { p.rad[p.nst++] = 3; m /= 3; }
@@ -126,20 +127,42 @@ __host__ __device__ inline int fft_pos(int f, const FftPlan &p) {
     return pos;
 }
 
-// Forward DFT of radix 2/3/4 on v[0..R): y_p = sum_r v_r exp(-2 pi i r p / R).
+template <typename R>
+__device__ __forceinline__ void dft4(cx<R> *v) {
+    cx<R> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    cx<R> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, cmul_mi(t3));
+    v[3] = csub(t1, cmul_mi(t3));
+}
+
+// Forward DFT of radix 2/3/4/8 on v[0..R): y_p = sum_r v_r exp(-2 pi i r p / R).
 template <typename R>
 __device__ __forceinline__ void dft_small(int rad, cx<R> *v) {
-    if (rad == 2) {
+    if (rad == 8) {
+        // two length-4 DFTs (even, odd samples) joined by W_8^p, W_8 = (1 - i) / sqrt 2
+        cx<R> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        dft4(e);
+        dft4(o);
+        const R s = (R)0.7071067811865475244008443621048490;
+        const cx<R> o1 = {s * (o[1].re + o[1].im), s * (o[1].im - o[1].re)};    // W_8 o[1]
+        const cx<R> o2 = cmul_mi(o[2]);                                         // W_8^2 = -i
+        const cx<R> o3 = {s * (o[3].im - o[3].re), -s * (o[3].re + o[3].im)};   // W_8^3 = -(1 + i) / sqrt 2
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    } else if (rad == 2) {
         cx<R> a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     } else if (rad == 4) {
-        cx<R> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
-        cx<R> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
-        v[0] = cadd(t0, t2);
-        v[2] = csub(t0, t2);
-        v[1] = cadd(t1, cmul_mi(t3));
-        v[3] = csub(t1, cmul_mi(t3));
+        dft4(v);
     } else {  // 3
         const R h = (R)0.8660254037844386467637231707529362;   // sqrt(3)/2
         cx<R> a = v[0];
@@ -185,7 +208,8 @@ __device__ void lds_fft_dif(cx<R> *buf, int cnt, int seq_stride, const FftPlan &
             const int k = bi - blk * span;
             cx<R> *x = buf + (size_t)sq * seq_stride + blk * L + k;
             // one butterfly per radix with a fixed-size register array
-            if (rad == 4) fft_butterfly<4>(x, span, k, tstep, n, tw);
+            if (rad == 8) fft_butterfly<8>(x, span, k, tstep, n, tw);
+            else if (rad == 4) fft_butterfly<4>(x, span, k, tstep, n, tw);
             else if (rad == 2) fft_butterfly<2>(x, span, k, tstep, n, tw);
             else fft_butterfly<3>(x, span, k, tstep, n, tw);
         }

@@ -449,20 +449,58 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 #pragma unroll
         for (int c = 0; c < NCH; ++c) ah[c] = f32x4{0.f, 0.f, 0.f, 0.f};
         if constexpr (F32B) {
-            // split the FP32 values into hi, mid, lo, then the products of KIND 3
-            u32x4 pa_[NF > 0 ? NF : 1][3], pb_[NF > 0 ? NF : 1][3];
+            // Split in three stages, each followed by the products it completes,
+            // so that the bf16 conversions of one stage run beside the MFMAs of
+            // the one before: hi -> hi*hi; mid -> hi*mid, mid*hi, mid*mid;
+            // lo -> hi*lo, lo*hi (the products and order of the stored planes).
+            typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+            typedef float f32x2 __attribute__((ext_vector_type(2)));
+            constexpr int NFA = NF > 0 ? NF : 1;
+            u32x4 pa_[NFA][3], pb_[NFA][3];
             u32x2 pah[3], pbh[3];
+            unsigned ra[NFA][8], rb[NFA][8], rah[4], rbh[4];   // residuals (FP32 bits)
 #pragma unroll
-            for (int hb = 0; hb < NF; ++hb) {
-                split3_frag8(f.a[hb][0], f.a[hb][1], pa_[hb]);
-                split3_frag8(f.b[hb][0], f.b[hb][1], pb_[hb]);
-            }
-            if constexpr (HF) {
-                split3_frag4(f.ah, pah);
-                split3_frag4(f.bh, pbh);
-            }
+            for (int hb = 0; hb < NF; ++hb)
 #pragma unroll
-            for (int p = 0; p < PR::NPROD; ++p) {
+                for (int e = 0; e < 8; ++e) {
+                    ra[hb][e] = f.a[hb][e >> 2][e & 3];
+                    rb[hb][e] = f.b[hb][e >> 2][e & 3];
+                }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                rah[e] = f.ah[e];
+                rbh[e] = f.bh[e];
+            }
+            // one term of a pair of values: convert (round to nearest even), then
+            // leave the exact remainder for the next term
+            auto term = [](unsigned &x0, unsigned &x1, bool last) -> unsigned {
+                const unsigned t = __builtin_bit_cast(unsigned, __builtin_convertvector(
+                                                                    f32x2{__uint_as_float(x0), __uint_as_float(x1)}, bf16x2));
+                if (!last) {
+                    x0 = __float_as_uint(__uint_as_float(x0) - __uint_as_float(t << 16));
+                    x1 = __float_as_uint(__uint_as_float(x1) - __uint_as_float(t & 0xffff0000u));
+                }
+                return t;
+            };
+            auto stage = [&](auto KK) {
+                constexpr int k = decltype(KK)::value;
+#pragma unroll
+                for (int hb = 0; hb < NF; ++hb)
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        pa_[hb][k][d] = term(ra[hb][2 * d], ra[hb][2 * d + 1], k == 2);
+                        pb_[hb][k][d] = term(rb[hb][2 * d], rb[hb][2 * d + 1], k == 2);
+                    }
+                if constexpr (HF) {
+#pragma unroll
+                    for (int d = 0; d < 2; ++d) {
+                        pah[k][d] = term(rah[2 * d], rah[2 * d + 1], k == 2);
+                        pbh[k][d] = term(rbh[2 * d], rbh[2 * d + 1], k == 2);
+                    }
+                }
+            };
+            auto prod = [&](auto PP) {
+                constexpr int p = decltype(PP)::value;
 #pragma unroll
                 for (int hb = 0; hb < NF; ++hb) {
                     f32x4 &c = ac[(p * NF + hb) % NCF];
@@ -474,7 +512,28 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                     c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, pah[PR::pa(p)]),
                                                                  __builtin_bit_cast(s16x4, pbh[PR::pb(p)]), c, 0, 0, 0);
                 }
-            }
+            };
+            stage(IC<0>{});
+            prod(IC<0>{});
+            stage(IC<1>{});
+            prod(IC<1>{});
+            prod(IC<2>{});
+            prod(IC<3>{});
+            stage(IC<2>{});
+            prod(IC<4>{});
+            prod(IC<5>{});
+            // instruction order for the scheduler: the conversions of the next
+            // stage between the MFMAs of the current one
+            constexpr int NPAIR = 2 * (4 * NF + 2 * HF);   // value pairs of both operands
+            constexpr int NMF = NF + HF;                    // MFMAs per product
+            __builtin_amdgcn_sched_group_barrier(0x002, 5 * NPAIR, 0);   // hi
+            __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // hi*hi
+            __builtin_amdgcn_sched_group_barrier(0x002, 5 * NPAIR, 0);   // mid
+            __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // hi*mid
+            __builtin_amdgcn_sched_group_barrier(0x002, NPAIR / 2, 0);   // lo, first half
+            __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // mid*hi
+            __builtin_amdgcn_sched_group_barrier(0x002, NPAIR / 2, 0);   // lo, second half
+            __builtin_amdgcn_sched_group_barrier(0x008, 3 * NMF, 0);     // mid*mid, hi*lo, lo*hi
         } else if constexpr (BF) {
 #pragma unroll
             for (int p = 0; p < PR::NPROD; ++p) {

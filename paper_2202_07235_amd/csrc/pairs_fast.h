@@ -442,7 +442,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     // or VALU and measured slower; FP32 measured slower too).
     constexpr int NCF = KIND == 2 ? 3 : 1;
     constexpr int NCH = KIND == 2 ? 2 : 1;
-    auto mma = [&](const FragT &f) -> f32x4 {
+    auto mma = [&](const FragT &f, auto &&after_hi) -> f32x4 {
         f32x4 ac[NCF], ah[NCH];
 #pragma unroll
         for (int c = 0; c < NCF; ++c) ac[c] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -514,6 +514,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                 }
             };
             stage(IC<0>{});
+            after_hi();
             prod(IC<0>{});
             stage(IC<1>{});
             prod(IC<1>{});
@@ -527,6 +528,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             constexpr int NPAIR = 2 * (4 * NF + 2 * HF);   // value pairs of both operands
             constexpr int NMF = NF + HF;                    // MFMAs per product
             __builtin_amdgcn_sched_group_barrier(0x002, 5 * NPAIR, 0);   // hi
+            __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);           // the previous job's result to LDS
             __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // hi*hi
             __builtin_amdgcn_sched_group_barrier(0x002, 5 * NPAIR, 0);   // mid
             __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // hi*mid
@@ -535,6 +537,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             __builtin_amdgcn_sched_group_barrier(0x002, NPAIR / 2, 0);   // lo, second half
             __builtin_amdgcn_sched_group_barrier(0x008, 3 * NMF, 0);     // mid*mid, hi*lo, lo*hi
         } else if constexpr (BF) {
+            after_hi();
 #pragma unroll
             for (int p = 0; p < PR::NPROD; ++p) {
 #pragma unroll
@@ -550,6 +553,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                 }
             }
         } else {
+            after_hi();
 #pragma unroll
             for (int hb = 0; hb < NF; ++hb)
 #pragma unroll
@@ -583,7 +587,11 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 
     constexpr int FRAG_REGS = F32B ? 2 * (8 * NF + 4 * HF) : 2 * PR::NPL * (4 * NF + 2 * HF);
     // prefetch depth in jobs: as deep as the registers beside the FFT state allow
-    constexpr int D = FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 48 ? 3 : 2);
+    // split bf16 from FP32: a job's result goes to LDS during the next job (after
+    // its hi terms), so the wave does not wait for the MFMA chain; a prefetch
+    // depth of 4 measured faster than 5 with it
+    constexpr bool PIPE_PUT = F32B;
+    constexpr int D = (FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 48 ? 3 : 2)) - (PIPE_PUT && FRAG_REGS <= 24 ? 1 : 0);
     constexpr int NJ = 4 * NRP;
     FragT fr[D + 1];
 
@@ -602,6 +610,8 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
         sfor<0, NRP>([&](auto RR) {
             constexpr int R = decltype(RR)::value;
             cx<float> *sb = stage + (R & 1) * (16 * 128);
+            f32x4 pend = {0.f, 0.f, 0.f, 0.f};
+            auto slot = [](int jj) { return (jj < 2 ? 0 : 8) + (jj & 1); };
             sfor<0, 4>([&](auto JJ) {
                 constexpr int J = 4 * R + decltype(JJ)::value;
                 if constexpr (J + D < NJ) {
@@ -613,9 +623,14 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                 // keep the prefetch ahead of this job's MFMAs (the scheduler would otherwise
                 // sink the loads and shorten the prefetch distance)
                 __builtin_amdgcn_sched_barrier(0);
-                const f32x4 acc = mma(fr[J % (D + 1)]);
-                put(sb, (decltype(JJ)::value < 2 ? 0 : 8) + 2 * w + (decltype(JJ)::value & 1), acc);
+                constexpr int jj = decltype(JJ)::value;
+                const f32x4 acc = mma(fr[J % (D + 1)], [&]() {
+                    if constexpr (PIPE_PUT && jj > 0) put(sb, slot(jj - 1) + 2 * w, pend);
+                });
+                if constexpr (PIPE_PUT) pend = acc;
+                else put(sb, slot(jj) + 2 * w, acc);
             });
+            if constexpr (PIPE_PUT) put(sb, slot(3) + 2 * w, pend);
             __syncthreads();
             // Z fold: lane e owns k = 8R + 2jj + e (k and M - k have equal parity)
             sfor<0, 4>([&](auto JJ) {
@@ -645,7 +660,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
         {   // middle frequency q = M/2 (even): Z[M/2] = 2 S[M/2], upper slot 0 of lane e = 0
             cx<float> *sb = stage + (NRP & 1) * (16 * 128);   // not the last round's buffer
             if (w == 0) {
-                const f32x4 acc = mma(fr[NJ % (D + 1)]);
+                const f32x4 acc = mma(fr[NJ % (D + 1)], []() {});
                 put(sb, 0, acc);
             }
             __syncthreads();

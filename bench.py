@@ -331,10 +331,12 @@ def main():
         flops_contract / (PEAK_FP32_MATRIX_TFLOPS * 1e12)
     t_valu = flops_fft / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
     H8 = (H + 7) // 8 * 8
-    # operand bytes per real value, in 2-byte units: FP32 4 B; bf16 2 B; bf16x3 two bf16 planes
-    # (3 products) or FP32 values split in registers (6 products), 4 B either way
-    planes = {"fp32": 2, "bf16": 1, "bf16x3": 2}[a.precision]
-    bytes_min = (cfg.n_img + cfg.n_tgt * cfg.T) * M1 * 2 * H8 * 2 * planes + n_pairs * 12
+    # operand bytes per real value (images, targets): FP32 4 B; bf16 2 B; bf16x3 with 3 products
+    # two bf16 planes (4 B); with 6 products the images' three bf16 planes (6 B) and the
+    # targets' FP32 values, split in registers (4 B)
+    bpr_a, bpr_b = {"fp32": (4, 4), "bf16": (2, 2),
+                    "bf16x3": (4, 4) if a.products == 3 else (6, 4)}[a.precision]
+    bytes_min = (cfg.n_img * bpr_a + cfg.n_tgt * cfg.T * bpr_b) * M1 * 2 * H8 + n_pairs * 12
     t_hbm = bytes_min / (PEAK_HBM_GBS * 1e9)
     bound = max(("mfma", t_mfma), ("alu", t_valu), ("hbm", t_hbm), key=lambda kv: kv[1])
     if bound[0] == "alu":

@@ -64,7 +64,7 @@ struct Layout {
     size_t off_k, off_eta, off_delta, off_phase, off_C, off_U, off_lam, off_ueta, off_rsum, off_gram,
         off_Ag, off_Bg, off_Af, off_Bf, off_log, total;
     size_t Af_bytes, Bf_bytes;
-    int nsplit, H8, nplanes, ffmt, na_pad, nb_pad, Qc;
+    int nsplit, H8, nplanes_a, nplanes_b, ffmt_a, ffmt_b, na_pad, nb_pad, Qc;
     bool fast;
 };
 
@@ -76,11 +76,15 @@ Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
     L.Qc = pr->hermitian ? Q / 2 + 1 : Q;
     L.fast = pr->hermitian && pr->prec != RADSVD_FP64;
     L.H8 = (H + 7) / 8 * 8;
-    // bf16x3 with 6 products keeps FP32 values (in bf16 fragment order) and
-    // splits them into three bf16 terms in registers; 3 products load two planes
-    const bool split_in_regs = pr->prec == RADSVD_BF16X3 && pr->products != 3;
-    L.ffmt = pr->prec == RADSVD_FP32 ? kFragF32 : (split_in_regs ? kFragF32B : kFragBF16);
-    L.nplanes = (pr->prec == RADSVD_BF16X3 && pr->products == 3) ? 2 : 1;
+    // bf16x3 loads two bf16 planes per side with 3 products; with 6 products
+    // the images keep their three planes and the targets keep FP32 values (in
+    // bf16 fragment order), split into three bf16 terms in registers
+    const bool b3 = pr->prec == RADSVD_BF16X3;
+    const bool split_b = b3 && pr->products != 3;
+    L.ffmt_a = pr->prec == RADSVD_FP32 ? kFragF32 : kFragBF16;
+    L.ffmt_b = pr->prec == RADSVD_FP32 ? kFragF32 : (split_b ? kFragF32B : kFragBF16);
+    L.nplanes_a = b3 ? (pr->products == 3 ? 2 : 3) : 1;
+    L.nplanes_b = b3 ? (pr->products == 3 ? 2 : 1) : 1;
     L.na_pad = (n_img + kFastTA - 1) / kFastTA * kFastTA;
     L.nb_pad = (n_tgt + kFastTB - 1) / kFastTB * kFastTB;
     const int tiles = (K + 63) / 64;
@@ -111,9 +115,10 @@ Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
     L.off_Bg = take((size_t)n_tgt * T * L.Qc * H * CX);
     if (L.fast) {
         // one fragment-ordered operand block per (tile, q): 8 images or 16 targets
-        const size_t blk = (size_t)L.nplanes * frag_plane_bytes(L.ffmt, L.H8);
-        L.Af_bytes = (size_t)(L.na_pad / kFastTA) * L.Qc * blk;
-        L.Bf_bytes = (size_t)T * (L.nb_pad / kFastTB) * L.Qc * blk;
+        const size_t blk_a = (size_t)L.nplanes_a * frag_plane_bytes(L.ffmt_a, L.H8);
+        const size_t blk_b = (size_t)L.nplanes_b * frag_plane_bytes(L.ffmt_b, L.H8);
+        L.Af_bytes = (size_t)(L.na_pad / kFastTA) * L.Qc * blk_a;
+        L.Bf_bytes = (size_t)T * (L.nb_pad / kFastTB) * L.Qc * blk_b;
         L.off_Af = take(L.Af_bytes);
         L.off_Bf = take(L.Bf_bytes);
     }
@@ -171,8 +176,10 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
     p->M = prob->Q / 2;
     p->Qc = L.Qc;
     p->H8 = L.H8;
-    p->nplanes = L.nplanes;
-    p->ffmt = L.ffmt;
+    p->nplanes_a = L.nplanes_a;
+    p->nplanes_b = L.nplanes_b;
+    p->ffmt_a = L.ffmt_a;
+    p->ffmt_b = L.ffmt_b;
     p->na_pad = L.na_pad;
     p->nb_pad = L.nb_pad;
     p->user_U = U_in != nullptr;

@@ -91,7 +91,7 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
         a.nTB = p->nb_pad / kFastTB;
         a.band = p->band ? p->band : kDefaultBand;
         a.H8 = p->H8;
-        a.nplanes = p->nplanes;
+        a.nplanes = p->nplanes_a;
         a.flags = RADSVD_OUT_BEST;
         a.inv_s2 = 1.f;
         a.best_score = outs[i].best_score;

@@ -80,8 +80,8 @@ struct radsvd_plan {
     int M;       // Q / 2
     int Qc;      // frequencies stored: herm ? Q/2 + 1 : Q
     int H8;      // H rounded up to a multiple of 8 (fast operand rows)
-    int nplanes; // fast operand planes (bf16: 1/2; fp32 and fp32-in-bf16-order: 1)
-    int ffmt;    // fast operand format: kFragF32, kFragBF16 or kFragF32B
+    int nplanes_a, nplanes_b;   // fast operand planes, images / targets
+    int ffmt_a, ffmt_b;         // fast operand formats (kFragF32, kFragBF16, kFragF32B)
     int na_pad, nb_pad;   // counts padded to the fast tile sizes
     int user_U;
     int band;    // image tiles per XCD band of the fast path's tile order (0 = default)

@@ -252,12 +252,13 @@ __device__ __forceinline__ void tile_of(int wg, int nwg, int nTA, int nTB, int b
 //   KIND 0: FP32 operands, v_mfma_f32_16x16x4_f32
 //   KIND 1: bf16 (one product), v_mfma_f32_16x16x32_bf16 (+ 16x16x16 for a half chunk)
 //   KIND 2: split bf16, products hi*hi, hi*mid, mid*hi
-//   KIND 3: split bf16, + mid*mid, hi*lo, lo*hi; the operands are stored as
-//           FP32 values in bf16 fragment order and split in registers
+//   KIND 3: split bf16, + mid*mid, hi*lo, lo*hi; the image operand is stored
+//           as its three bf16 planes, the target operand as FP32 values in
+//           bf16 fragment order, split in registers
 template <int KIND>
 struct Prec {
     static constexpr int NPL = KIND == 0 ? 1 : (KIND == 3 ? 3 : (KIND == 2 ? 2 : 1));   // planes multiplied
-    static constexpr int NPL_MEM = KIND == 3 ? 1 : NPL;                                 // planes loaded
+    static constexpr int NPL_B = KIND == 3 ? 1 : NPL;                                   // target planes loaded
     static constexpr int NPROD = KIND == 3 ? 6 : (KIND == 2 ? 3 : 1);
     static constexpr int pa(int p) { return p == 2 ? 1 : (p == 3 ? 1 : (p == 5 ? 2 : 0)); }   // A plane
     static constexpr int pb(int p) { return p == 1 ? 1 : (p == 3 ? 1 : (p == 4 ? 2 : 0)); }   // B plane
@@ -273,13 +274,14 @@ struct Frag {
     u32x2 ah[Prec<KIND>::NPL];
     u32x2 bh[Prec<KIND>::NPL];
 };
-// KIND 3: the FP32 values themselves, 8 per lane and chunk (two 16-byte
-// halves), 4 in the half chunk
+// KIND 3: the image planes as loaded; for the targets the FP32 values
+// themselves, 8 per lane and chunk (two 16-byte halves), 4 in the half chunk
 template <int NF, int HF>
 struct Frag<3, NF, HF> {
-    u32x4 a[NF > 0 ? NF : 1][2];
+    u32x4 a[3][NF > 0 ? NF : 1];
+    u32x2 ah[3];
     u32x4 b[NF > 0 ? NF : 1][2];
-    u32x4 ah, bh;
+    u32x4 bh;
 };
 
 // x = hi + mid + lo in bf16 (round to nearest even at each step; the
@@ -369,17 +371,21 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     // M - 8R - 2w - (j - 2) (upper, j = 2, 3); the wave part of q lives in the
     // per-lane offsets, the round part is a compile-time scalar offset.
     const int g = l >> 4, i16 = l & 15;        // MFMA output: rows 4g..4g+3, column i16
-    constexpr bool F32B = KIND == 3;              // FP32 values in bf16 fragment order
-    constexpr int CHB = F32B ? 2048 : 1024;       // bytes per full chunk
-    constexpr int PB = NF * CHB + HF * (CHB / 2); // bytes per plane
-    constexpr int BB = PR::NPL_MEM * PB;          // bytes per (tile, q) block
-    const int vlo = 2 * w * BB;
-    const int vhi = (M / 2 + 7 - 2 * w) * BB;
-    const int vF_lo = 16 * l + vlo, vF_hi = 16 * l + vhi;
-    const int vH_lo = (F32B ? 16 : 8) * l + NF * CHB + vlo, vH_hi = (F32B ? 16 : 8) * l + NF * CHB + vhi;
-    const char *Abase = Af + (size_t)ta * (M + 1) * BB;
+    constexpr bool F32B = KIND == 3;              // targets: FP32 values in bf16 fragment order
+    constexpr int PB = NF * 1024 + HF * 512;      // bytes per bf16 / FP32 plane
+    constexpr int BBA = PR::NPL * PB;             // bytes per (tile, q) block, images
+    constexpr int PBB = F32B ? 2 * PB : PB;       // bytes per target plane
+    constexpr int BBB = PR::NPL_B * PBB;          // bytes per (tile, q) block, targets
+    const int vloA = 2 * w * BBA, vhiA = (M / 2 + 7 - 2 * w) * BBA;
+    const int vloB = 2 * w * BBB, vhiB = (M / 2 + 7 - 2 * w) * BBB;
+    const int vFA_lo = 16 * l + vloA, vFA_hi = 16 * l + vhiA;
+    const int vHA_lo = 8 * l + NF * 1024 + vloA, vHA_hi = 8 * l + NF * 1024 + vhiA;
+    const int vFB_lo = 16 * l + vloB, vFB_hi = 16 * l + vhiB;
+    const int vHB_lo = (F32B ? 16 : 8) * l + NF * (F32B ? 2048 : 1024) + vloB;
+    const int vHB_hi = (F32B ? 16 : 8) * l + NF * (F32B ? 2048 : 1024) + vhiB;
+    const char *Abase = Af + (size_t)ta * (M + 1) * BBA;
     const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)Abase, (short)0, (M + 1) * BB, 0x00020000);
+        (void *)Abase, (short)0, (M + 1) * BBA, 0x00020000);
 
     // per-lane twiddle factor W_Q^e
     const float fe_c = e ? (float)trig2pi(1, Q, false) : 1.f;
@@ -391,45 +397,43 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     float run_m = -INFINITY, run_s = 0.f;
 
     auto rsrcB = [&](int t) {
-        const char *Bbase = Bf + ((size_t)t * nTB + tb) * (M + 1) * BB;
-        return __builtin_amdgcn_make_buffer_rsrc((void *)Bbase, (short)0, (M + 1) * BB, 0x00020000);
+        const char *Bbase = Bf + ((size_t)t * nTB + tb) * (M + 1) * BBB;
+        return __builtin_amdgcn_make_buffer_rsrc((void *)Bbase, (short)0, (M + 1) * BBB, 0x00020000);
     };
     // job J = 4R + j: upper (j >= 2) or lower, and its compile-time block offset
     auto job_upper = [](int J) { return (J & 3) >= 2; };
-    auto job_soff = [](int J) {
+    // block index of job J (times the block size of a side gives its scalar offset)
+    auto job_blk = [](int J) {
         const int R = J >> 2, j = J & 3;
-        return (j < 2) ? (8 * R + (j & 1)) * BB : (8 * (NRP - 1 - R) + 1 - (j & 1)) * BB;
+        return (j < 2) ? (8 * R + (j & 1)) : (8 * (NRP - 1 - R) + 1 - (j & 1));
     };
     using FragT = Frag<KIND, NF, HF>;
-    auto load_at = [&](const __amdgpu_buffer_rsrc_t &rB, bool upper, int soff, FragT &f) {
-        const int vF = upper ? vF_hi : vF_lo;
-        const int vH = upper ? vH_hi : vH_lo;
+    auto load_at = [&](const __amdgpu_buffer_rsrc_t &rB, bool upper, int blk, FragT &f) {
+        const int soffA = blk * BBA, soffB = blk * BBB;
+        const int vFA = upper ? vFA_hi : vFA_lo, vHA = upper ? vHA_hi : vHA_lo;
+        const int vFB = upper ? vFB_hi : vFB_lo, vHB = upper ? vHB_hi : vHB_lo;
+#pragma unroll
+        for (int pl = 0; pl < PR::NPL; ++pl) {
+#pragma unroll
+            for (int hb = 0; hb < NF; ++hb)
+                f.a[pl][hb] = __builtin_amdgcn_raw_buffer_load_b128(rA, vFA + pl * PB + hb * 1024, soffA, 0);
+            if constexpr (HF) f.ah[pl] = __builtin_amdgcn_raw_buffer_load_b64(rA, vHA + pl * PB, soffA, 0);
+        }
         if constexpr (F32B) {
 #pragma unroll
             for (int hb = 0; hb < NF; ++hb)
 #pragma unroll
-                for (int s2 = 0; s2 < 2; ++s2) {
-                    f.a[hb][s2] = __builtin_amdgcn_raw_buffer_load_b128(rA, vF + hb * 2048 + s2 * 1024, soff, 0);
-                    f.b[hb][s2] = __builtin_amdgcn_raw_buffer_load_b128(rB, vF + hb * 2048 + s2 * 1024, soff, 0);
-                }
-            if constexpr (HF) {
-                f.ah = __builtin_amdgcn_raw_buffer_load_b128(rA, vH, soff, 0);
-                f.bh = __builtin_amdgcn_raw_buffer_load_b128(rB, vH, soff, 0);
-            }
-            return;
+                for (int s2 = 0; s2 < 2; ++s2)
+                    f.b[hb][s2] = __builtin_amdgcn_raw_buffer_load_b128(rB, vFB + hb * 2048 + s2 * 1024, soffB, 0);
+            if constexpr (HF) f.bh = __builtin_amdgcn_raw_buffer_load_b128(rB, vHB, soffB, 0);
         } else {
 #pragma unroll
-        for (int pl = 0; pl < PR::NPL; ++pl) {
+            for (int pl = 0; pl < PR::NPL; ++pl) {
 #pragma unroll
-            for (int hb = 0; hb < NF; ++hb) {
-                f.a[pl][hb] = __builtin_amdgcn_raw_buffer_load_b128(rA, vF + pl * PB + hb * 1024, soff, 0);
-                f.b[pl][hb] = __builtin_amdgcn_raw_buffer_load_b128(rB, vF + pl * PB + hb * 1024, soff, 0);
+                for (int hb = 0; hb < NF; ++hb)
+                    f.b[pl][hb] = __builtin_amdgcn_raw_buffer_load_b128(rB, vFB + pl * PB + hb * 1024, soffB, 0);
+                if constexpr (HF) f.bh[pl] = __builtin_amdgcn_raw_buffer_load_b64(rB, vHB + pl * PB, soffB, 0);
             }
-            if constexpr (HF) {
-                f.ah[pl] = __builtin_amdgcn_raw_buffer_load_b64(rA, vH + pl * PB, soff, 0);
-                f.bh[pl] = __builtin_amdgcn_raw_buffer_load_b64(rB, vH + pl * PB, soff, 0);
-            }
-        }
         }
     };
     // The MFMAs of one job accumulate in several independent chains (a
@@ -455,22 +459,17 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             // lo -> hi*lo, lo*hi (the products and order of the stored planes).
             typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
             typedef float f32x2 __attribute__((ext_vector_type(2)));
+            // (the image planes come from memory; only the target values are split)
             constexpr int NFA = NF > 0 ? NF : 1;
-            u32x4 pa_[NFA][3], pb_[NFA][3];
-            u32x2 pah[3], pbh[3];
-            unsigned ra[NFA][8], rb[NFA][8], rah[4], rbh[4];   // residuals (FP32 bits)
+            u32x4 pb_[NFA][3];
+            u32x2 pbh[3];
+            unsigned rb[NFA][8], rbh[4];   // residuals (FP32 bits)
 #pragma unroll
             for (int hb = 0; hb < NF; ++hb)
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    ra[hb][e] = f.a[hb][e >> 2][e & 3];
-                    rb[hb][e] = f.b[hb][e >> 2][e & 3];
-                }
+                for (int e = 0; e < 8; ++e) rb[hb][e] = f.b[hb][e >> 2][e & 3];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                rah[e] = f.ah[e];
-                rbh[e] = f.bh[e];
-            }
+            for (int e = 0; e < 4; ++e) rbh[e] = f.bh[e];
             // one term of a pair of values: convert (round to nearest even), then
             // leave the exact remainder for the next term
             auto term = [](unsigned &x0, unsigned &x1, bool last) -> unsigned {
@@ -487,16 +486,10 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 #pragma unroll
                 for (int hb = 0; hb < NF; ++hb)
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        pa_[hb][k][d] = term(ra[hb][2 * d], ra[hb][2 * d + 1], k == 2);
-                        pb_[hb][k][d] = term(rb[hb][2 * d], rb[hb][2 * d + 1], k == 2);
-                    }
+                    for (int d = 0; d < 4; ++d) pb_[hb][k][d] = term(rb[hb][2 * d], rb[hb][2 * d + 1], k == 2);
                 if constexpr (HF) {
 #pragma unroll
-                    for (int d = 0; d < 2; ++d) {
-                        pah[k][d] = term(rah[2 * d], rah[2 * d + 1], k == 2);
-                        pbh[k][d] = term(rbh[2 * d], rbh[2 * d + 1], k == 2);
-                    }
+                    for (int d = 0; d < 2; ++d) pbh[k][d] = term(rbh[2 * d], rbh[2 * d + 1], k == 2);
                 }
             };
             auto prod = [&](auto PP) {
@@ -504,12 +497,12 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 #pragma unroll
                 for (int hb = 0; hb < NF; ++hb) {
                     f32x4 &c = ac[(p * NF + hb) % NCF];
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pa_[hb][PR::pa(p)]),
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, f.a[PR::pa(p)][hb]),
                                                                __builtin_bit_cast(bf16x8, pb_[hb][PR::pb(p)]), c, 0, 0, 0);
                 }
                 if constexpr (HF) {
                     f32x4 &c = ah[p % NCH];
-                    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, pah[PR::pa(p)]),
+                    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, f.ah[PR::pa(p)]),
                                                                  __builtin_bit_cast(s16x4, pbh[PR::pb(p)]), c, 0, 0, 0);
                 }
             };
@@ -525,7 +518,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             prod(IC<5>{});
             // instruction order for the scheduler: the conversions of the next
             // stage between the MFMAs of the current one
-            constexpr int NPAIR = 2 * (4 * NF + 2 * HF);   // value pairs of both operands
+            constexpr int NPAIR = 4 * NF + 2 * HF;         // value pairs of the target operand
             constexpr int NMF = NF + HF;                    // MFMAs per product
             __builtin_amdgcn_sched_group_barrier(0x002, 5 * NPAIR, 0);   // hi
             __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);           // the previous job's result to LDS
@@ -585,13 +578,14 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     };
     const int Ps = sidx(P);
 
-    constexpr int FRAG_REGS = F32B ? 2 * (8 * NF + 4 * HF) : 2 * PR::NPL * (4 * NF + 2 * HF);
+    constexpr int FRAG_REGS = F32B ? PR::NPL * (4 * NF + 2 * HF) + 8 * NF + 4 * HF : 2 * PR::NPL * (4 * NF + 2 * HF);
     // prefetch depth in jobs: as deep as the registers beside the FFT state allow
     // split bf16 from FP32: a job's result goes to LDS during the next job (after
-    // its hi terms), so the wave does not wait for the MFMA chain; a prefetch
-    // depth of 4 measured faster than 5 with it
+    // its hi terms), so the wave does not wait for the MFMA chain; the prefetch
+    // depth leaves room for the split's registers
     constexpr bool PIPE_PUT = F32B;
-    constexpr int D = (FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 48 ? 3 : 2)) - (PIPE_PUT && FRAG_REGS <= 24 ? 1 : 0);
+    constexpr int D = PIPE_PUT ? (FRAG_REGS <= 24 ? 4 : (FRAG_REGS <= 32 ? 3 : 2))
+                               : (FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 48 ? 3 : 2));
     constexpr int NJ = 4 * NRP;
     FragT fr[D + 1];
 
@@ -600,7 +594,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
         cx<float> x[LH];
         sfor<0, D>([&](auto II) {
             constexpr int J = decltype(II)::value;
-            load_at(rB, job_upper(J), job_soff(J), fr[J]);
+            load_at(rB, job_upper(J), job_blk(J), fr[J]);
         });
         // ---------------- step 1: contraction, paired rounds ----------------
         // One barrier per round: round R stages into buffer R & 1, so the fold of
@@ -615,10 +609,10 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             sfor<0, 4>([&](auto JJ) {
                 constexpr int J = 4 * R + decltype(JJ)::value;
                 if constexpr (J + D < NJ) {
-                    load_at(rB, job_upper(J + D), job_soff(J + D), fr[(J + D) % (D + 1)]);
+                    load_at(rB, job_upper(J + D), job_blk(J + D), fr[(J + D) % (D + 1)]);
                 } else if constexpr (J + D == NJ) {
                     // middle frequency q = M/2, wave 0 (whose lower offsets are the bare lane part)
-                    if (w == 0) load_at(rB, false, (M / 2) * BB, fr[(J + D) % (D + 1)]);
+                    if (w == 0) load_at(rB, false, M / 2, fr[(J + D) % (D + 1)]);
                 }
                 // keep the prefetch ahead of this job's MFMAs (the scheduler would otherwise
                 // sink the loads and shorten the prefetch distance)

@@ -32,7 +32,7 @@ hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, floa
     a.nTB = p->nb_pad / kFastTB;
     a.band = p->band ? p->band : kDefaultBand;
     a.H8 = p->H8;
-    a.nplanes = p->nplanes;
+    a.nplanes = p->nplanes_a;
     a.flags = flags;
     a.inv_s2 = inv_s2;
     a.best_score = best_score;

@@ -511,7 +511,8 @@ static hipError_t rings_side_mfma(radsvd_plan *p, const void *X, int n_real, int
                                   void *G, void *F, int f_tile, int is_img, hipStream_t s) {
     const int Q = p->Q;
     const size_t shmem = (size_t)17 * Q * sizeof(cx<float>);   // twiddles + 16 rows
-    const int f_kind = p->ffmt;
+    const int f_kind = is_img ? p->ffmt_a : p->ffmt_b;
+    const int nplanes = is_img ? p->nplanes_a : p->nplanes_b;
     const int ng = ((Q + 31) / 32 + 3) / 4;                     // angle groups per wave
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -523,7 +524,7 @@ static hipError_t rings_side_mfma(radsvd_plan *p, const void *X, int n_real, int
         hipLaunchKernelGGL(kern, dim3(grid), dim3(256), shmem, s, reinterpret_cast<const cx<float> *>(X), n_real, T,
                            reinterpret_cast<const cx<float> *>(p->phase), reinterpret_cast<const float *>(p->Ueta),
                            p->K, Q, p->H, p->Qc, reinterpret_cast<cx<float> *>(G), F, f_kind, f_tile,
-                           n_pad / f_tile, p->H8, p->nplanes, is_img);
+                           n_pad / f_tile, p->H8, nplanes, is_img);
         return hipGetLastError();
     };
     auto pick2 = [&](auto phase_tag, auto two_tag) -> hipError_t {
@@ -548,14 +549,15 @@ static hipError_t rings_side(radsvd_plan *p, const void *X, int n_real, int n_pa
     if (FC < 1) FC = 1;
     if (FC > HP) FC = HP;
     const size_t shmem = (size_t)Q * cxb + (size_t)FC * Q * cxb;
-    const int f_kind = p->prec == RADSVD_FP64 ? kFragF32 : p->ffmt;
+    const int f_kind = p->prec == RADSVD_FP64 ? kFragF32 : (is_img ? p->ffmt_a : p->ffmt_b);
+    const int nplanes = is_img ? p->nplanes_a : p->nplanes_b;
     const int f_ntiles = n_pad / f_tile;
     const int items = n_real * T;   // padding items of the fast layout stay zero
     hipLaunchKernelGGL((k_rings<R, HP>), dim3(items), dim3(256), shmem, s,
                        reinterpret_cast<const cx<R> *>(X), n_real, T,
                        use_phase ? reinterpret_cast<const cx<R> *>(p->phase) : nullptr,
                        reinterpret_cast<const R *>(p->Ueta), K, Q, H, p->Qc, FC,
-                       reinterpret_cast<cx<R> *>(G), F, f_kind, f_tile, f_ntiles, p->H8, p->nplanes, is_img);
+                       reinterpret_cast<cx<R> *>(G), F, f_kind, f_tile, f_ntiles, p->H8, nplanes, is_img);
     return hipGetLastError();
 }
 

@@ -408,6 +408,11 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
         return (j < 2) ? (8 * R + (j & 1)) : (8 * (NRP - 1 - R) + 1 - (j & 1));
     };
     using FragT = Frag<KIND, NF, HF>;
+    // bf16 pairs (-1, 0) and (0, -1) for the remainders of the split, kept in
+    // registers: folded into an instruction as the inline constant -1.0, the
+    // first pair was read as (0, -1) on gfx950
+    unsigned dmask0 = 0x0000bf80u, dmask1 = 0xbf800000u;
+    if constexpr (KIND == 3) asm volatile("" : "+v"(dmask0), "+v"(dmask1));
     auto load_at = [&](const __amdgpu_buffer_rsrc_t &rB, bool upper, int blk, FragT &f) {
         const int soffA = blk * BBA, soffB = blk * BBB;
         const int vFA = upper ? vFA_hi : vFA_lo, vHA = upper ? vHA_hi : vHA_lo;
@@ -471,15 +476,17 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 #pragma unroll
             for (int e = 0; e < 4; ++e) rbh[e] = f.bh[e];
             // one term of a pair of values: convert (round to nearest even), then
-            // leave the exact remainder for the next term
-            auto term = [](unsigned &x0, unsigned &x1, bool last) -> unsigned {
-                const unsigned t = __builtin_bit_cast(unsigned, __builtin_convertvector(
-                                                                    f32x2{__uint_as_float(x0), __uint_as_float(x1)}, bf16x2));
+            // leave the exact remainder x - term for the next term, one bf16 dot
+            // product each (x + (-1) t0 + 0 t1: exact products, exact difference)
+            auto term = [&](unsigned &x0, unsigned &x1, bool last) -> unsigned {
+                const bf16x2 t = __builtin_convertvector(f32x2{__uint_as_float(x0), __uint_as_float(x1)}, bf16x2);
                 if (!last) {
-                    x0 = __float_as_uint(__uint_as_float(x0) - __uint_as_float(t << 16));
-                    x1 = __float_as_uint(__uint_as_float(x1) - __uint_as_float(t & 0xffff0000u));
+                    x0 = __float_as_uint(__builtin_amdgcn_fdot2_f32_bf16(t, __builtin_bit_cast(bf16x2, dmask0),
+                                                                         __uint_as_float(x0), false));
+                    x1 = __float_as_uint(__builtin_amdgcn_fdot2_f32_bf16(t, __builtin_bit_cast(bf16x2, dmask1),
+                                                                         __uint_as_float(x1), false));
                 }
-                return t;
+                return __builtin_bit_cast(unsigned, t);
             };
             auto stage = [&](auto KK) {
                 constexpr int k = decltype(KK)::value;
@@ -520,10 +527,10 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             // stage between the MFMAs of the current one
             constexpr int NPAIR = 4 * NF + 2 * HF;         // value pairs of the target operand
             constexpr int NMF = NF + HF;                    // MFMAs per product
-            __builtin_amdgcn_sched_group_barrier(0x002, 5 * NPAIR, 0);   // hi
+            __builtin_amdgcn_sched_group_barrier(0x002, 3 * NPAIR, 0);   // hi
             __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);           // the previous job's result to LDS
             __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // hi*hi
-            __builtin_amdgcn_sched_group_barrier(0x002, 5 * NPAIR, 0);   // mid
+            __builtin_amdgcn_sched_group_barrier(0x002, 3 * NPAIR, 0);   // mid
             __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // hi*mid
             __builtin_amdgcn_sched_group_barrier(0x002, NPAIR / 2, 0);   // lo, first half
             __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // mid*hi

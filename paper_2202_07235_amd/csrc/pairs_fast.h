@@ -387,9 +387,6 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
         (void *)Abase, (short)0, (M + 1) * BBA, 0x00020000);
 
-    // per-lane twiddle factor W_Q^e
-    const float fe_c = e ? (float)trig2pi(1, Q, false) : 1.f;
-    const float fe_s = e ? (float)(-trig2pi(1, Q, true)) : 0.f;
 
     float run_best = -INFINITY;
     int run_idx = 0x7fffffff;
@@ -598,6 +595,10 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 
     for (int t = 0; t < nT; ++t) {
         const __amdgpu_buffer_rsrc_t rB = rsrcB(t);
+        // the lane's parity, opaque per translation: the fold's per-lane twiddles
+        // are then formed where they are used, not kept live across the loop
+        int et = e;
+        asm volatile("" : "+v"(et));
         cx<float> x[LH];
         sfor<0, D>([&](auto II) {
             constexpr int J = decltype(II)::value;
@@ -645,9 +646,13 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                     }
                 }
                 const cx<float> u = {lo.re + hi.re, lo.im - hi.im};
-                cx<float> v = {lo.re - hi.re, lo.im + hi.im};
-                v = cx<float>{v.re * fe_c - v.im * fe_s, v.re * fe_s + v.im * fe_c};   // * W_Q^e
-                const cx<float> p = twmul<8 * R + 2 * jj, Q>(v);                      // * W_Q^{k-e}
+                const cx<float> v = {lo.re - hi.re, lo.im + hi.im};
+                // * W_Q^k, k = 8R + 2jj + e: the lane picks its twiddle
+                constexpr int k0 = 8 * R + 2 * jj;
+                constexpr float c0 = (float)trig2pi(k0, Q, false), s0 = (float)(-trig2pi(k0, Q, true));
+                constexpr float c1 = (float)trig2pi(k0 + 1, Q, false), s1 = (float)(-trig2pi(k0 + 1, Q, true));
+                const float tc = et ? c1 : c0, ts = et ? s1 : s0;
+                const cx<float> p = {v.re * tc - v.im * ts, v.re * ts + v.im * tc};
                 x[4 * R + jj] = cx<float>{u.re - p.im, u.im + p.re};                  // Z[k]
                 const cx<float> zc = {u.re + p.im, p.re - u.im};                      // Z[M - k]
                 constexpr int ubase = LH - 4 * R - jj;                                 // upper slot + e
@@ -681,7 +686,8 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             upper[k * 256 + tid] = twmul<k, L>(csub(a, b));
         });
         float bv[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};   // even-lo, even-hi, odd-lo, odd-hi
-        int bi[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};
+        int bi[4] = {0x7fffffff, 0x7fffffff, 0x7fffffff, 0x7fffffff};  // m of the winning (re, im) pair
+        float br[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};   // that pair's re value
         float lse_mx = -INFINITY, lse_sum = 0.f;
         bool nanX = false;
         auto half_pass = [&](auto PARITY) {
@@ -708,10 +714,11 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                     constexpr int f = decltype(FF)::value;
                     constexpr int m0 = 4 * f + 2 * par;
                     const cx<float> zl = x[ct_pos(LH, f)], zh = x[ct_pos(LH, f + LH / 2)];
-                    if (zl.re > bv[2 * par]) { bv[2 * par] = zl.re; bi[2 * par] = m0; }
-                    if (zl.im > bv[2 * par]) { bv[2 * par] = zl.im; bi[2 * par] = m0 + 1; }
-                    if (zh.re > bv[2 * par + 1]) { bv[2 * par + 1] = zh.re; bi[2 * par + 1] = m0 + M; }
-                    if (zh.im > bv[2 * par + 1]) { bv[2 * par + 1] = zh.im; bi[2 * par + 1] = m0 + M + 1; }
+                    // a pair (re at m, im at m + 1) replaces the winner only when strictly
+                    // larger, so earlier m keep ties; NaN never wins (fmaxf drops it)
+                    const float ml = fmaxf(zl.re, zl.im), mh = fmaxf(zh.re, zh.im);
+                    if (ml > bv[2 * par]) { bv[2 * par] = ml; bi[2 * par] = m0; br[2 * par] = zl.re; }
+                    if (mh > bv[2 * par + 1]) { bv[2 * par + 1] = mh; bi[2 * par + 1] = m0 + M; br[2 * par + 1] = zh.re; }
                 });
             }
             if (do_lse) {
@@ -740,6 +747,9 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 
         const bool isnanX = nanX || __builtin_isnan(__shfl_xor(nanX ? __builtin_nanf("") : 0.f, 32, 64));
         if (do_best) {
+            // the winning pair's im value when its re value is smaller
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) bi[c4] += (br[c4] == bv[c4]) ? 0 : 1;
             // lane-local winner: ties go to the smaller m (even/odd interleave)
             float b0 = bv[0];
             int i0 = bi[0];

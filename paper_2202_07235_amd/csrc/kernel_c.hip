@@ -85,33 +85,48 @@ __global__ __launch_bounds__(256) void k_gram_partial(const cx<R> *__restrict__ 
         }
     const int b0 = split * b_per_split;
     const int b1 = min(n_tgt, b0 + b_per_split);
-    // lane g of a chunk of 8 samples holds samples 2 g and 2 g + 1
+    // lane g of a chunk of 8 samples holds samples 2 g and 2 g + 1 (Q is even, so
+    // both or neither are in range; rows past K and samples past Q read a valid
+    // address and feed zeros)
     auto load4 = [&](const cx<R> *row, int j, bool ok, double (&v)[4]) __attribute__((always_inline)) {
-        cx<R> x0 = {(R)0, (R)0}, x1 = {(R)0, (R)0};
-        if (ok && j < Q) x0 = row[j];
-        if (ok && j + 1 < Q) x1 = row[j + 1];
-        v[0] = (double)x0.re;
-        v[1] = (double)x0.im;
-        v[2] = (double)x1.re;
-        v[3] = (double)x1.im;
+        const bool use = ok && j < Q;
+        const cx<R> *src = row + (j < Q ? j : Q - 2);
+        const cx<R> x0 = src[0], x1 = src[1];
+        v[0] = use ? (double)x0.re : 0.0;
+        v[1] = use ? (double)x0.im : 0.0;
+        v[2] = use ? (double)x1.re : 0.0;
+        v[3] = use ? (double)x1.im : 0.0;
     };
     for (int b = b0 + w; b < b1; b += 4) {
         const cx<R> *Bb = B + (size_t)b * K * Q;
         const cx<R> *pa0 = Bb + (size_t)rowA[0] * Q, *pa1 = Bb + (size_t)rowA[1] * Q;
         const cx<R> *pb0 = Bb + (size_t)rowB[0] * Q, *pb1 = Bb + (size_t)rowB[1] * Q;
+        // the next chunk is loaded while the current one feeds the MFMAs
+        double a0[4], a1[4], c0[4], c1[4];
+        load4(pa0, 2 * g, okA[0], a0);
+        load4(pa1, 2 * g, okA[1], a1);
+        load4(pb0, 2 * g, okB[0], c0);
+        load4(pb1, 2 * g, okB[1], c1);
         for (int j0 = 0; j0 < Q; j0 += 8) {
-            const int j = j0 + 2 * g;
-            double a0[4], a1[4], c0[4], c1[4];
-            load4(pa0, j, okA[0], a0);
-            load4(pa1, j, okA[1], a1);
-            load4(pb0, j, okB[0], c0);
-            load4(pb1, j, okB[1], c1);
+            double na0[4], na1[4], nc0[4], nc1[4];
+            const int jn = j0 + 8 + 2 * g;
+            load4(pa0, jn, okA[0], na0);
+            load4(pa1, jn, okA[1], na1);
+            load4(pb0, jn, okB[0], nc0);
+            load4(pb1, jn, okB[1], nc1);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], c0[s], acc[0][0], 0, 0, 0);
                 acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], c1[s], acc[0][1], 0, 0, 0);
                 acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], c0[s], acc[1][0], 0, 0, 0);
                 acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], c1[s], acc[1][1], 0, 0, 0);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                a0[s] = na0[s];
+                a1[s] = na1[s];
+                c0[s] = nc0[s];
+                c1[s] = nc1[s];
             }
         }
     }

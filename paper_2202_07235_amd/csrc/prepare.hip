@@ -571,10 +571,17 @@ hipError_t launch_principal_rings(radsvd_plan *p, hipStream_t s) {
                                       kFastTB, 0, s);
     }
     if (p->Af) {   // both fast buffers are contiguous multiples of 256 bytes
-        hipLaunchKernelGGL(k_zero16, dim3(2048), dim3(256), 0, s, reinterpret_cast<u32x4_t *>(p->Af),
-                           p->Af_bytes / 16);
-        hipLaunchKernelGGL(k_zero16, dim3(2048), dim3(256), 0, s, reinterpret_cast<u32x4_t *>(p->Bf),
-                           p->Bf_bytes / 16);
+        // The ring kernel writes every byte of a real item's blocks (zeros for ranks
+        // at or past H) except in the FP32 format, which leaves ranks past H alone;
+        // padding items of the last tile are never written.  Fill only then.
+        const bool zero_a = (p->n_img % kFastTA) != 0 || (p->ffmt_a == kFragF32 && p->H != p->H8);
+        const bool zero_b = (p->n_tgt % kFastTB) != 0 || (p->ffmt_b == kFragF32 && p->H != p->H8);
+        if (zero_a)
+            hipLaunchKernelGGL(k_zero16, dim3(2048), dim3(256), 0, s, reinterpret_cast<u32x4_t *>(p->Af),
+                               p->Af_bytes / 16);
+        if (zero_b)
+            hipLaunchKernelGGL(k_zero16, dim3(2048), dim3(256), 0, s, reinterpret_cast<u32x4_t *>(p->Bf),
+                               p->Bf_bytes / 16);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     e = rings_side_mfma(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, 1, s);

@@ -20,7 +20,8 @@
 // BF16x3: v_mfma_f32_16x16x32_bf16 over the split products (hi*hi, hi*mid,
 //         mid*hi [, mid*mid, hi*lo, lo*hi]); FP32 accumulation.  A half chunk
 //         (ranks an odd multiple of 8) runs on v_mfma_f32_16x16x16_bf16 in an
-//         accumulation chain of its own.
+//         accumulation chain of its own; with six products, two products of the
+//         half chunk share one v_mfma_f32_16x16x32_bf16 instead.
 // The prepare kernel writes the operands of each (tile, q) as one block in
 // register-fragment order (frag_elem_offset), so every load instruction of a
 // wavefront reads one contiguous 1 KB (or 512 B) span.
@@ -448,6 +449,8 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     // or VALU and measured slower; FP32 measured slower too).
     constexpr int NCF = KIND == 2 ? 3 : 1;
     constexpr int NCH = KIND == 2 ? 2 : 1;
+    // KIND 3 issues its half-chunk products as full-size MFMAs in the chain of the full chunks
+    constexpr bool HALF_SEP = HF && KIND != 3;
     auto mma = [&](const FragT &f, auto &&after_hi) -> f32x4 {
         f32x4 ac[NCF], ah[NCH];
 #pragma unroll
@@ -504,11 +507,19 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, f.a[PR::pa(p)][hb]),
                                                                __builtin_bit_cast(bf16x8, pb_[hb][PR::pb(p)]), c, 0, 0, 0);
                 }
-                if constexpr (HF) {
-                    f32x4 &c = ah[p % NCH];
-                    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, f.ah[PR::pa(p)]),
-                                                                 __builtin_bit_cast(s16x4, pbh[PR::pb(p)]), c, 0, 0, 0);
-                }
+            };
+            // Half chunk: two products share one v_mfma_f32_16x16x32_bf16.  A lane's
+            // eight depth slots hold its four slots of the first product, then its
+            // four of the second, in A and in B alike, so the sum over the 32 slots
+            // is the sum of the two 16-deep products (the 16x16x16 form costs about
+            // as much issue time as the 16x16x32 one).  Pairs (A planes | B planes):
+            // hi*mid + hi*hi and mid*mid + lo*hi after the mid stage, mid*hi + hi*lo
+            // after the lo stage.
+            auto half2 = [&](const u32x2 &a0, const u32x2 &a1, const u32x2 &b0, const u32x2 &b1) {
+                const u32x4 av = {a0[0], a0[1], a1[0], a1[1]};
+                const u32x4 bv = {b0[0], b0[1], b1[0], b1[1]};
+                ac[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                               __builtin_bit_cast(bf16x8, bv), ac[0], 0, 0, 0);
             };
             stage(IC<0>{});
             after_hi();
@@ -517,22 +528,28 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             prod(IC<1>{});
             prod(IC<2>{});
             prod(IC<3>{});
+            if constexpr (HF) {
+                half2(f.ah[0], f.ah[0], pbh[1], pbh[0]);
+                half2(f.ah[1], f.ah[2], pbh[1], pbh[0]);
+            }
             stage(IC<2>{});
             prod(IC<4>{});
             prod(IC<5>{});
+            if constexpr (HF) half2(f.ah[1], f.ah[0], pbh[0], pbh[2]);
             // instruction order for the scheduler: the conversions of the next
             // stage between the MFMAs of the current one
             constexpr int NPAIR = 4 * NF + 2 * HF;         // value pairs of the target operand
-            constexpr int NMF = NF + HF;                    // MFMAs per product
             __builtin_amdgcn_sched_group_barrier(0x002, 3 * NPAIR, 0);   // hi
             __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);           // the previous job's result to LDS
-            __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // hi*hi
-            __builtin_amdgcn_sched_group_barrier(0x002, 3 * NPAIR, 0);   // mid
-            __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // hi*mid
-            __builtin_amdgcn_sched_group_barrier(0x002, NPAIR / 2, 0);   // lo, first half
-            __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);         // mid*hi
-            __builtin_amdgcn_sched_group_barrier(0x002, NPAIR / 2, 0);   // lo, second half
-            __builtin_amdgcn_sched_group_barrier(0x008, 3 * NMF, 0);     // mid*mid, hi*lo, lo*hi
+            if constexpr (NF > 0) {
+                __builtin_amdgcn_sched_group_barrier(0x008, NF, 0);      // hi*hi
+                __builtin_amdgcn_sched_group_barrier(0x002, 3 * NPAIR, 0);   // mid
+                __builtin_amdgcn_sched_group_barrier(0x008, NF, 0);      // hi*mid
+                __builtin_amdgcn_sched_group_barrier(0x002, NPAIR / 2, 0);   // lo, first half
+                __builtin_amdgcn_sched_group_barrier(0x008, NF, 0);      // mid*hi
+                __builtin_amdgcn_sched_group_barrier(0x002, NPAIR / 2, 0);   // lo, second half
+                __builtin_amdgcn_sched_group_barrier(0x008, 3 * NF + 3 * HF, 0);   // the rest
+            }
         } else if constexpr (BF) {
             after_hi();
 #pragma unroll
@@ -563,7 +580,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
         f32x4 acc = ac[0];
 #pragma unroll
         for (int c = 1; c < NCF; ++c) acc += ac[c];
-        if constexpr (HF) {
+        if constexpr (HALF_SEP) {
             f32x4 hs = ah[0];
 #pragma unroll
             for (int c = 1; c < NCH; ++c) hs += ah[c];

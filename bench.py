@@ -254,8 +254,8 @@ def main():
         print(reduce_counters(*a.reduce_counters))
         return 0
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); nothing in this build runs across "
-              f"GPUs.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the library has no multi-GPU "
+              f"path.", file=sys.stderr)
         return 2
     import numpy as np
     import torch

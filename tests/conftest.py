@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests run in one process on the GPU machine; on a machine without a GPU
+    # GPU tests run in one process on a machine with a GPU; on one without
     # they are skipped unless explicitly selected with -m gpu.
     try:
         import torch

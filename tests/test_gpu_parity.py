@@ -6,8 +6,8 @@ rounds in FP32 (eps = 6e-8); the deepest chains are the K-term ring sum
 (K <= 128), two length-Q FFTs (log2 Q <= 9 stages each) and the 2H-term
 contraction, so the error relative to max|X| is a random-sign sum of
 O(K + 2H + 2 log2 Q) roundings of terms of size <= max|X|: sqrt(300) * 6e-8
-~ 1e-6; the bound used is 1e-5 (the spec bar for the split-precision
-path).  BF16 (one product): unit roundoff 2^-9 per operand -> 2^-8 relative
+~ 1e-6; the bound used is 1e-5 (the accuracy the split-precision path is
+required to meet).  BF16 (one product): unit roundoff 2^-9 per operand -> 2^-8 relative
 per product, averaged over sums: 1e-2.
 """
 import math

@@ -813,8 +813,13 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     }
 }
 
+// Up to Q = 128 the LDS (stage and parked Z values, 64 KB) leaves room for a
+// second workgroup per CU, and the registers are held to 256 per lane so that
+// it fits: two waves per SIMD then hide each other's memory waits (measured
+// 46.1 -> 31.2 ms at Q = 128, H = 24, 4096 x 4096 pairs, 9 translations).  At
+// Q = 192 the registers would spill heavily; from Q = 256 the LDS allows one.
 template <int Q, int KIND, int NF, int HF>
-__global__ __launch_bounds__(256, 1) void k_pairs_fast(Args args) {
+__global__ __launch_bounds__(256, Q <= 128 ? 2 : 1) void k_pairs_fast(Args args) {
     extern __shared__ unsigned char smem_raw[];
     int ta, tb;
     tile_of(blockIdx.x, gridDim.x, args.nTA, args.nTB, args.band, ta, tb);

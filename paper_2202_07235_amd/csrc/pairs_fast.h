@@ -265,6 +265,13 @@ struct Prec {
     static constexpr int pb(int p) { return p == 1 ? 1 : (p == 3 ? 1 : (p == 4 ? 2 : 0)); }   // B plane
 };
 
+// registers per lane of one job's operands (the Frag layouts below)
+template <int KIND, int NF, int HF>
+constexpr int frag_regs() {
+    return KIND == 3 ? Prec<3>::NPL * (4 * NF + 2 * HF) + 8 * NF + 4 * HF
+                     : 2 * Prec<KIND>::NPL * (4 * NF + 2 * HF);
+}
+
 // One job's operand registers: NF full chunks (16 bytes per lane) and, for
 // BF16 ranks that are odd multiples of 8, one half chunk (8 bytes per lane),
 // per loaded plane, for the image rows (a) and the target columns (b).
@@ -599,7 +606,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     };
     const int Ps = sidx(P);
 
-    constexpr int FRAG_REGS = F32B ? PR::NPL * (4 * NF + 2 * HF) + 8 * NF + 4 * HF : 2 * PR::NPL * (4 * NF + 2 * HF);
+    constexpr int FRAG_REGS = frag_regs<KIND, NF, HF>();
     // prefetch depth in jobs: as deep as the registers beside the FFT state allow
     // split bf16 from FP32: a job's result goes to LDS during the next job (after
     // its hi terms), so the wave does not wait for the MFMA chain; the prefetch
@@ -813,13 +820,20 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     }
 }
 
-// Up to Q = 128 the LDS (stage and parked Z values, 64 KB) leaves room for a
-// second workgroup per CU, and the registers are held to 256 per lane so that
-// it fits: two waves per SIMD then hide each other's memory waits (measured
-// 46.1 -> 31.2 ms at Q = 128, H = 24, 4096 x 4096 pairs, 9 translations).  At
-// Q = 192 the registers would spill heavily; from Q = 256 the LDS allows one.
+// Workgroups per CU.  Up to Q = 192 the LDS (stage and parked Z values, at
+// most 80 KB) leaves room for a second workgroup, and the registers are then
+// held to 256 per lane: two waves per SIMD hide each other's memory waits
+// (4096 x 4096 pairs, 9 translations, 6 products: Q = 128, H = 24 46.1 ->
+// 31.2 ms; Q = 192, H = 16 52.8 -> 33.8 ms).  At Q = 192 with more than 30
+// operand registers per job (H = 32) the spills cost more than the second
+// wave gains (78.3 -> 87.8 ms); from Q = 256 the LDS holds one workgroup.
 template <int Q, int KIND, int NF, int HF>
-__global__ __launch_bounds__(256, Q <= 128 ? 2 : 1) void k_pairs_fast(Args args) {
+constexpr int fast_wg_per_cu() {
+    return (Q <= 128 || (Q <= 192 && frag_regs<KIND, NF, HF>() <= 30)) ? 2 : 1;
+}
+
+template <int Q, int KIND, int NF, int HF>
+__global__ __launch_bounds__(256, (fast_wg_per_cu<Q, KIND, NF, HF>())) void k_pairs_fast(Args args) {
     extern __shared__ unsigned char smem_raw[];
     int ta, tb;
     tile_of(blockIdx.x, gridDim.x, args.nTA, args.nTB, args.band, ta, tb);

@@ -329,6 +329,18 @@ __device__ __forceinline__ void split3_frag4(const u32x4 &r, u32x2 (&pl)[3]) {
     }
 }
 
+// Staging buffers for the MFMA results: two (round parity) unless a single one
+// lets a second workgroup fit in the LDS (Q = 256: 16 + 64 KB).
+template <int Q, int KIND, int NF, int HF>
+constexpr int fast_nstage() {
+    return (Q == 256 && frag_regs<KIND, NF, HF>() <= 20) ? 1 : 2;
+}
+// Workgroups per CU (see k_pairs_fast).
+template <int Q, int KIND, int NF, int HF>
+constexpr int fast_wg_per_cu() {
+    return (Q <= 128 || (Q <= 192 && frag_regs<KIND, NF, HF>() <= 30) || fast_nstage<Q, KIND, NF, HF>() == 1) ? 2 : 1;
+}
+
 // One tile (ta, tb) for all translations.  Q angles; KIND contraction
 // precision; NF, HF operand chunks per plane (FP32: NF = H8 / 8 chunks of 16
 // depth values, HF = 0; BF16: NF = H8 / 16, HF = 1 when H8 is an odd multiple
@@ -345,9 +357,10 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     using PR = Prec<KIND>;
     static_assert(M % 16 == 0, "Q must be a multiple of 32");
 
-    // staging of MFMA results, double-buffered by round parity: [2][16][128]
+    // staging of MFMA results, double-buffered by round parity: [NSTAGE][16][128]
+    constexpr int NSTAGE = fast_nstage<Q, KIND, NF, HF>();
     cx<float> *stage = reinterpret_cast<cx<float> *>(smem_raw);
-    cx<float> *upper = stage + 2 * 16 * 128;                      // [LH][256]
+    cx<float> *upper = stage + NSTAGE * 16 * 128;                 // [LH][256]
 
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -635,7 +648,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
         // reuses the buffer.
         sfor<0, NRP>([&](auto RR) {
             constexpr int R = decltype(RR)::value;
-            cx<float> *sb = stage + (R & 1) * (16 * 128);
+            cx<float> *sb = stage + (NSTAGE == 2 ? (R & 1) * (16 * 128) : 0);
             f32x4 pend = {0.f, 0.f, 0.f, 0.f};
             auto slot = [](int jj) { return (jj < 2 ? 0 : 8) + (jj & 1); };
             sfor<0, 4>([&](auto JJ) {
@@ -686,9 +699,11 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                     upper[(ubase - e) * 256 + tid] = zc;
                 }
             });
+            // one staging buffer: the next round (or the middle frequency) writes it again
+            if constexpr (NSTAGE == 1) __syncthreads();
         });
         {   // middle frequency q = M/2 (even): Z[M/2] = 2 S[M/2], upper slot 0 of lane e = 0
-            cx<float> *sb = stage + (NRP & 1) * (16 * 128);   // not the last round's buffer
+            cx<float> *sb = stage + (NSTAGE == 2 ? (NRP & 1) * (16 * 128) : 0);   // not the last round's buffer
             if (w == 0) {
                 const f32x4 acc = mma(fr[NJ % (D + 1)], []() {});
                 put(sb, 0, acc);
@@ -820,17 +835,15 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     }
 }
 
-// Workgroups per CU.  Up to Q = 192 the LDS (stage and parked Z values, at
-// most 80 KB) leaves room for a second workgroup, and the registers are then
-// held to 256 per lane: two waves per SIMD hide each other's memory waits
-// (4096 x 4096 pairs, 9 translations, 6 products: Q = 128, H = 24 46.1 ->
-// 31.2 ms; Q = 192, H = 16 52.8 -> 33.8 ms).  At Q = 192 with more than 30
-// operand registers per job (H = 32) the spills cost more than the second
-// wave gains (78.3 -> 87.8 ms); from Q = 256 the LDS holds one workgroup.
-template <int Q, int KIND, int NF, int HF>
-constexpr int fast_wg_per_cu() {
-    return (Q <= 128 || (Q <= 192 && frag_regs<KIND, NF, HF>() <= 30)) ? 2 : 1;
-}
+// Workgroups per CU.  Up to Q = 192, and at Q = 256 with one staging buffer,
+// the LDS (staging and parked Z values, at most 80 KB) leaves room for a
+// second workgroup, and the registers are then held to 256 per lane: two waves
+// per SIMD hide each other's memory waits (4096 x 4096 pairs, 9 translations,
+// 6 products: Q = 128, H = 24 46.1 -> 31.2 ms; Q = 192, H = 16 52.8 -> 33.8
+// ms; Q = 256, H = 16 68.5 -> 47.5 ms).  With more operand registers per job
+// (Q = 192 beyond 30, Q = 256 beyond 20) the spills cost more than the second
+// wave gains (Q = 192, H = 32: 78.3 -> 87.8 ms); beyond Q = 256 the LDS holds
+// one workgroup.
 
 template <int Q, int KIND, int NF, int HF>
 __global__ __launch_bounds__(256, (fast_wg_per_cu<Q, KIND, NF, HF>())) void k_pairs_fast(Args args) {
@@ -843,7 +856,7 @@ __global__ __launch_bounds__(256, (fast_wg_per_cu<Q, KIND, NF, HF>())) void k_pa
 template <int Q, int KIND, int NF, int HF>
 static hipError_t launch_v(const Args &a, int nwg, hipStream_t s) {
     constexpr int LH = Q / 8;
-    const size_t shmem = (size_t)(2 * 16 * 128 + LH * 256) * sizeof(cx<float>);
+    const size_t shmem = (size_t)(fast_nstage<Q, KIND, NF, HF>() * 16 * 128 + LH * 256) * sizeof(cx<float>);
     static bool attr_done = false;
     if (!attr_done) {
         hipError_t e = hipFuncSetAttribute((const void *)k_pairs_fast<Q, KIND, NF, HF>,

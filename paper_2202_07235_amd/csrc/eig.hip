@@ -105,20 +105,25 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
             __syncthreads();
             // block (k, l): rows {p_k, q_k} x columns {p_l, q_l}; rows rotate by
             // (c_k, s_k), then columns by (c_l, s_l): x' = c x - s y, y' = s x + c y
-            for (int e = tid; e < 64 * 64; e += nt) {
-                const int k = e >> 6, l = e & 63;
-                if (k >= npair || l >= npair) continue;
-                const double ck = sc[k], sk = ss[k], cl = sc[l], sl = ss[l];
-                if (sk == 0.0 && sl == 0.0) continue;
-                const int pk = sp[k], qk = sq[k], pl = sp[l], ql = sq[l];
-                const double a00 = A[pk * ld + pl], a01 = A[pk * ld + ql];
-                const double a10 = A[qk * ld + pl], a11 = A[qk * ld + ql];
-                const double r00 = ck * a00 - sk * a10, r10 = sk * a00 + ck * a10;
-                const double r01 = ck * a01 - sk * a11, r11 = sk * a01 + ck * a11;
-                A[pk * ld + pl] = cl * r00 - sl * r01;
-                A[pk * ld + ql] = sl * r00 + cl * r01;
-                A[qk * ld + pl] = cl * r10 - sl * r11;
-                A[qk * ld + ql] = sl * r10 + cl * r11;
+            // thread t owns column pair l = t % 64 (nt is a multiple of 64) and row
+            // pairs k = t / 64, t / 64 + nt / 64, ...; the column rotation is read once
+            const int l = tid & 63;
+            if (l < npair) {
+                const double cl = sc[l], sl = ss[l];
+                const int pl = sp[l], ql = sq[l];
+                for (int k = tid >> 6; k < npair; k += nt >> 6) {
+                    const double ck = sc[k], sk = ss[k];
+                    if (sk == 0.0 && sl == 0.0) continue;
+                    const int pk = sp[k], qk = sq[k];
+                    const double a00 = A[pk * ld + pl], a01 = A[pk * ld + ql];
+                    const double a10 = A[qk * ld + pl], a11 = A[qk * ld + ql];
+                    const double r00 = ck * a00 - sk * a10, r10 = sk * a00 + ck * a10;
+                    const double r01 = ck * a01 - sk * a11, r11 = sk * a01 + ck * a11;
+                    A[pk * ld + pl] = cl * r00 - sl * r01;
+                    A[pk * ld + ql] = sl * r00 + cl * r01;
+                    A[qk * ld + pl] = cl * r10 - sl * r11;
+                    A[qk * ld + ql] = sl * r10 + cl * r11;
+                }
             }
             __syncthreads();
             ++nrounds;

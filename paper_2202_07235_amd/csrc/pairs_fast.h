@@ -333,7 +333,7 @@ __device__ __forceinline__ void split3_frag4(const u32x4 &r, u32x2 (&pl)[3]) {
 // lets a second workgroup fit in the LDS (Q = 256: 16 + 64 KB).
 template <int Q, int KIND, int NF, int HF>
 constexpr int fast_nstage() {
-    return (Q == 256 && frag_regs<KIND, NF, HF>() <= 20) ? 1 : 2;
+    return (Q == 256 && frag_regs<KIND, NF, HF>() <= 24) ? 1 : 2;
 }
 // Workgroups per CU (see k_pairs_fast).
 template <int Q, int KIND, int NF, int HF>
@@ -840,10 +840,11 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 // second workgroup, and the registers are then held to 256 per lane: two waves
 // per SIMD hide each other's memory waits (4096 x 4096 pairs, 9 translations,
 // 6 products: Q = 128, H = 24 46.1 -> 31.2 ms; Q = 192, H = 16 52.8 -> 33.8
-// ms; Q = 256, H = 16 68.5 -> 47.5 ms).  With more operand registers per job
-// (Q = 192 beyond 30, Q = 256 beyond 20) the spills cost more than the second
-// wave gains (Q = 192, H = 32: 78.3 -> 87.8 ms); beyond Q = 256 the LDS holds
-// one workgroup.
+// ms; Q = 256, H = 16 68.5 -> 47.5 ms; FP32, Q = 256, H = 24 81.9 -> 70.6
+// ms).  With more operand registers per job (Q = 192 beyond 30, Q = 256 beyond
+// 24) the spills cost more than the second wave gains (Q = 192, H = 32: 78.3
+// -> 87.8 ms; Q = 256, H = 24, 6 products: 88.5 -> 99.0 ms); beyond Q = 256
+// the LDS holds one workgroup.
 
 template <int Q, int KIND, int NF, int HF>
 __global__ __launch_bounds__(256, (fast_wg_per_cu<Q, KIND, NF, HF>())) void k_pairs_fast(Args args) {

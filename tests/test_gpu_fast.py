@@ -35,8 +35,9 @@ CASES = {64: (16, 10, 11, 37, 9),
 
 
 @functools.lru_cache(maxsize=None)
-def _problem(Q):
-    K, H, na, nb, T = CASES[Q]
+def _problem(Q, H=None):
+    K, H0, na, nb, T = CASES[Q]
+    H = H0 if H is None else H
     cfg = synth.config("fp32", N=Q // 2, K=K, Q=Q, n_img=na, n_tgt=nb, T=T, H=H,
                        n_blobs=8, snr=0.5)
     P = synth.make_problem(cfg, seed=2000 + Q)
@@ -53,7 +54,22 @@ def _problem(Q):
 @pytest.mark.parametrize("Q", sorted(CASES))
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x3_6", "bf16"])
 def test_fast_path_matches_oracle(Q, precision):
-    cfg, P, A, B, X = _problem(Q)
+    _check_fast(Q, None, precision)
+
+
+# Ranks on either side of the operand-register limits that decide whether two
+# workgroups share a compute unit (and, at Q = 256, whether the MFMA results
+# are staged in one buffer or two): Q = 256 with 24 ranks runs two workgroups
+# per CU in FP32, BF16 and 3-product bf16x3, one with 6 products; Q = 192 and
+# Q = 128 with 32 ranks.
+@pytest.mark.parametrize("Q,H", [(256, 24), (192, 32), (128, 32)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16x3_6", "bf16"])
+def test_fast_path_matches_oracle_across_occupancy_limits(Q, H, precision):
+    _check_fast(Q, H, precision)
+
+
+def _check_fast(Q, H, precision):
+    cfg, P, A, B, X = _problem(Q, H)
     prec, products = ("bf16x3", 6) if precision == "bf16x3_6" else (precision, 3)
     plan = rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision=prec, hermitian=True, products=products)
     s2 = 4.0 / np.abs(X).max()
@@ -68,7 +84,7 @@ def test_fast_path_matches_oracle(Q, precision):
     ref_sc, ref_m, ref_t = oracle.best(X)
     err_best = np.abs(sc - ref_sc).max() / scale
     tol = TOL[precision]
-    print(f"Q={Q} {precision}: score err {err_score:.2e}, best err {err_best:.2e}, "
+    print(f"Q={Q} H={cfg.H} {precision}: score err {err_score:.2e}, best err {err_best:.2e}, "
           f"argmax exact {np.mean((m == ref_m) & (t == ref_t)):.3f}")
     assert err_score <= tol
     assert err_best <= tol

@@ -44,18 +44,39 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "_build", "liboracle_direct.so")
+CFLAGS = ["-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
 _lib = None
 
 
+def _host_tag() -> str:
+    """Short tag of the host CPU (model and feature flags): -march=native code
+    is built per host, so a library built on one machine is never loaded on
+    another whose CPU lacks an instruction it uses."""
+    import hashlib
+    import platform
+    info = platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith(("model name", "flags")):
+                    info += line
+                if line.startswith("flags"):
+                    break
+    except OSError:
+        pass
+    return hashlib.sha1(info.encode()).hexdigest()[:10]
+
+
+_SO = os.path.join(_HERE, "_build", f"liboracle_direct_{_host_tag()}.so")
+
+
 def build(force: bool = False) -> str:
-    """Compile direct.c with gcc (-O2 -fopenmp)."""
+    """Compile direct.c with gcc (CFLAGS: -O3 -march=native -fopenmp) for this host."""
     os.makedirs(os.path.dirname(_SO), exist_ok=True)
     src = os.path.join(_HERE, "direct.c")
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
         tmp = _SO + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-o", tmp, src, "-lm"])
+        subprocess.check_call(["gcc"] + CFLAGS + ["-o", tmp, src, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -193,7 +214,8 @@ def landscape(A, B, U, H: int, k, w, delta, pairs=None) -> np.ndarray:
 # --------------------------------------------------------------------------
 def best(X):
     """argmax over (t, m) of Re X per pair; ties go to the smallest t*Q + m.
-    A pair whose landscape holds a NaN gets score NaN and indices -1.
+    A pair whose landscape holds a value that is not finite (NaN or an
+    infinity) gets score NaN and indices -1.
     Returns (score, m, t) with the leading pair axes of X."""
     R = np.asarray(X).real
     lead = R.shape[:-2]
@@ -201,7 +223,7 @@ def best(X):
     flat = R.reshape(-1, T * Q)
     idx = np.argmax(flat, axis=1)
     score = flat[np.arange(flat.shape[0]), idx]
-    bad = np.isnan(flat).any(axis=1)
+    bad = ~np.isfinite(flat).all(axis=1)
     score = np.where(bad, np.nan, score)
     idx = np.where(bad, -1, idx)
     m = np.where(bad, -1, idx % Q)
@@ -218,11 +240,17 @@ def lse(X, inv_sigma2: float):
     """lse_pair[a,b] = log sum_{t,m} exp(inv_sigma2 Re X); lse_img[a] =
     log sum_b exp(lse_pair[a,b]).  Soft version of the maximum-likelihood
     alignment: the Gaussian log-likelihood of section 2.6 is, up to
-    gamma-independent terms, X / sigma^2."""
-    R = np.asarray(X).real * inv_sigma2
+    gamma-independent terms, X / sigma^2.
+    A pair whose landscape holds a value that is not finite gets NaN, and so
+    does every image with such a pair."""
+    R = np.asarray(X).real
     na, nb, T, Q = R.shape
-    lp = _logsumexp(R.reshape(na, nb, T * Q), axis=2)
-    return lp, _logsumexp(lp, axis=1)
+    R = R.reshape(na, nb, T * Q)
+    bad = ~np.isfinite(R).all(axis=2)
+    lp = _logsumexp(np.where(bad[..., None], 0.0, R) * inv_sigma2, axis=2)
+    lp = np.where(bad, np.nan, lp)
+    li = np.where(bad.any(axis=1), np.nan, _logsumexp(np.where(bad, 0.0, lp), axis=1))
+    return lp, li
 
 
 def lse_loss(A, B, U, H, k, w, delta, inv_sigma2, g):

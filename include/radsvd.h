@@ -106,6 +106,9 @@ size_t align_prepare_workspace(const radsvd_problem *prob, int n_img, int n_tgt)
  *   U_in     device [K][H] FP64 row-major, or NULL.  When given, it replaces
  *            the eigenvectors of C (columns should be orthonormal) and C is
  *            not formed; the eigenvalues reported by align_get_U are then NaN.
+ *            With U_in NULL, a NaN or infinite target sample makes C
+ *            non-finite: U and every eigenvalue are then NaN, and every pair
+ *            of the plan takes the non-finite rule of align_pairs.
  *   ws       device workspace of ws_bytes >= align_prepare_workspace(),
  *            256-byte aligned; it holds everything the plan refers to.
  *   out      receives a new plan on RADSVD_OK (free with align_plan_destroy).
@@ -129,9 +132,12 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
  *                     best_m[a][b], best_t[a][b] (int32) its location; the
  *                     maximum-likelihood rotation of section 2.7 is
  *                     gamma = 2 pi m / Q.  Ties go to the smallest t*Q + m; a
- *                     pair whose landscape has a NaN gets NaN and -1, -1.
+ *                     pair whose landscape Re X holds a value that is not
+ *                     finite (NaN or infinite) gets NaN and -1, -1.
  *   RADSVD_OUT_LSE  : lse_pair[a][b] = log sum_{t,m} exp(inv_sigma2 Re X)  (f32, inv_sigma2 > 0);
  *                     if lse_img != NULL, lse_img[a] = log sum_b exp(lse_pair[a][b]).
+ *                     A pair with a non-finite landscape value gets NaN, and
+ *                     so does lse_img of its image.
  *   RADSVD_OUT_FULL : X_full [n_img][n_tgt][T][Q] complex (plan's I/O type).
  *
  * Pointers of the modes not selected are ignored.  All outputs are device
@@ -146,7 +152,13 @@ size_t align_backward_workspace(const radsvd_plan *plan);
 
 /*
  * Backward pass of the soft-alignment loss L = sum_a grad_lse_img[a] lse_img[a]
- * (lse_img as produced by align_pairs with the same inv_sigma2): writes
+ * (lse_img as produced by align_pairs with the same inv_sigma2).  Paper
+ * section 2.6 (likelihood): under the Gaussian noise model of section 2.5
+ * the log-likelihood of a target at pose (gamma, delta) against an image is,
+ * up to terms constant in the pose, Re X / sigma^2; lse_pair is the log of
+ * its sum over poses and lse_img the log of the sum over targets (a
+ * marginal likelihood with a uniform prior), so L is a weighted sum of
+ * per-image log-likelihoods.  Writes
  *   grad_B_polar device [n_tgt][K][Q] complex (plan's I/O type):
  *                dL/dRe Bhat + i dL/dIm Bhat, every entry treated as free;
  *   grad_U       device [K][H] FP64: dL/dU with U a free matrix (the

@@ -63,6 +63,15 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
         part += A[r * ld + c] * A[r * ld + c];
     }
     const double fro = block_sum_1024(part, red);
+    // A non-finite entry (a NaN or infinite target sample reaches C through the
+    // Gram sums) leaves no eigendecomposition to compute: every eigenvalue and
+    // every entry of U is NaN, so each landscape built from U is NaN and every
+    // pair takes the NaN rule of the pair step.
+    if (!isfinite(fro)) {
+        for (int i = tid; i < K * K; i += nt) U[i] = __builtin_nan("");
+        for (int i = tid; i < K; i += nt) lam[i] = __builtin_nan("");
+        return;
+    }
     int nrounds = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         part = 0.0;
@@ -165,13 +174,17 @@ __global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, i
         }
     }
     __syncthreads();
-    // rank by descending eigenvalue (ties: lower index first)
+    // rank by descending eigenvalue (ties: lower index first); a total order
+    // even for non-finite entries, which rank last, so every rank is taken once
     for (int i = tid; i < K; i += nt) {
         const double di = sdiag[i];
+        const bool ni = isnan(di);
         int rank = 0;
         for (int j = 0; j < K; ++j) {
             const double dj = sdiag[j];
-            if (dj > di || (dj == di && j < i)) ++rank;
+            const bool nj = isnan(dj);
+            const bool before = (ni != nj) ? ni : (!ni && dj != di ? dj > di : j < i);
+            if (j != i && before) ++rank;
         }
         srank[i] = rank;
         lam[rank] = di;

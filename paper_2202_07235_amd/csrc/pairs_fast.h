@@ -747,7 +747,12 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
                 x[ra] = cadd(a, tw);                // z[n]     -> X[2n], X[2n+1]
                 x[rb] = csub(a, tw);                // z[n + L] -> X[2n + M], X[2n + M + 1]
             });
-            if constexpr (par == 0) nanX = __builtin_isnan(x[ct_pos(LH, 0)].re);
+            // z at register 0 sums every folded value (each FFT output depends on
+            // every input, and IEEE arithmetic never turns a NaN or an infinity
+            // back into a finite value), so both of its parts are finite exactly
+            // when the whole landscape of this lane pair is (barring overflow)
+            if constexpr (par == 0)
+                nanX = !__builtin_isfinite(x[ct_pos(LH, 0)].re) || !__builtin_isfinite(x[ct_pos(LH, 0)].im);
             if (do_best) {
                 sfor<0, LH / 2>([&](auto FF) {
                     constexpr int f = decltype(FF)::value;

@@ -131,7 +131,9 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
             int idx = 0x7fffffff;
             bool any = false;
             for (int m = tid; m < Q; m += nt) {
-                const float x = (float)S[fft_pos(m, pl)].re;
+                // a non-finite value counts as NaN, which wins every comparison
+                const float xs = (float)S[fft_pos(m, pl)].re;
+                const float x = isfinite(xs) ? xs : NAN;
                 const int id = t * Q + m;
                 if (!any || better(x, id, v, idx)) {
                     v = x;
@@ -172,8 +174,9 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
             float mx = -INFINITY;
             bool nan_seen = false;
             for (int m = tid; m < Q; m += nt) {
-                const float x = (float)S[fft_pos(m, pl)].re * inv_s2;
-                if (isnan(x)) nan_seen = true;
+                const float xs = (float)S[fft_pos(m, pl)].re;
+                const float x = xs * inv_s2;
+                if (!isfinite(xs)) nan_seen = true;
                 else mx = fmaxf(mx, x);
             }
             for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
@@ -183,8 +186,8 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
             for (int w = 1; w < (nt >> 6); ++w) bmx = fmaxf(bmx, rv[w]);
             float sum = 0.f;
             for (int m = tid; m < Q; m += nt) {
-                const float x = (float)S[fft_pos(m, pl)].re * inv_s2;
-                sum += expf(x - bmx);
+                const float xs = (float)S[fft_pos(m, pl)].re;
+                if (isfinite(xs)) sum += expf(xs * inv_s2 - bmx);
             }
             for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
             __syncthreads();

@@ -8,7 +8,8 @@ times, on sampled pairs the FP64 oracle evaluates one by one:
   Q=256, T=9, H=16, log-sum-exp per image checked on whole rows.
 
 The oracle gets the exact complex64 inputs the GPU received (upcast) and the
-plan's U; U itself is checked against the oracle's kernel C at 1024 targets.
+plan's U; U itself is checked against the oracle's kernel C at 1024 targets
+(K = 64) and at 4096 targets (K = 128).
 """
 import numpy as np
 import pytest
@@ -65,17 +66,7 @@ def test_fp32_workload_sampled_pairs_and_U():
         print(f"fp32 workload {precision}: rel {rel:.2e} at-argmax {rel_at:.2e} agree {ok:.3f} exact {exact:.3f}")
         assert rel <= TOL[precision] and rel_at <= TOL[precision] and ok == 1.0
     # U against the oracle's kernel C built from the same 1024 targets
-    Bh = B.cpu().to(torch.complex128).numpy()
-    Cor = oracle.kernel_C(Bh, P.w, cfg.Q)
-    Uor, lam_or = oracle.principal_vectors(Cor)
-    U, lam = plan.U_lambda()
-    U, lam = U.cpu().numpy(), lam.cpu().numpy()
-    assert np.allclose(lam, lam_or, rtol=0, atol=1e-10 * lam_or[0])
-    H = cfg.H
-    gap = (lam_or[H - 1] - lam_or[H]) / lam_or[0]
-    proj = np.linalg.norm(U[:, :H] @ U[:, :H].T - Uor[:, :H] @ Uor[:, :H].T, 2)
-    print(f"projector distance {proj:.2e} (relative eigengap at H {gap:.2e})")
-    assert proj <= 1e-9 / max(gap, 1e-6)
+    _check_U(plan, B, P.w, cfg.Q, cfg.H)
 
 
 @pytest.mark.parametrize("precision", ["bf16x3", "fp32", "bf16x3_6", "bf16"])
@@ -88,6 +79,37 @@ def test_precision_workload_sampled_pairs(precision):
     rel, rel_at, ok, exact = _sample_check(cfg, P, A, B, plan, out, tol=TOL[precision])
     print(f"precision workload {precision}: rel {rel:.2e} at-argmax {rel_at:.2e} agree {ok:.3f} exact {exact:.3f}")
     assert rel <= TOL[precision] and rel_at <= TOL[precision] and ok == 1.0
+
+
+def _check_U(plan, B, w, Q, H, n_chunk=256):
+    """The plan's eigenvalues and leading-H projector against the oracle's
+    kernel C of the same targets (the target average is taken chunk by chunk:
+    C is a mean over targets, so the chunks' kernels combine by their sizes)."""
+    nb = B.shape[0]
+    Cor = 0.0
+    for i0 in range(0, nb, n_chunk):
+        Bh = B[i0:i0 + n_chunk].cpu().to(torch.complex128).numpy()
+        Cor = Cor + oracle.kernel_C(Bh, w, Q) * (Bh.shape[0] / nb)
+    Uor, lam_or = oracle.principal_vectors(Cor)
+    U, lam = plan.U_lambda()
+    U, lam = U.cpu().numpy(), lam.cpu().numpy()
+    lam_err = np.abs(lam - lam_or).max() / lam_or[0]
+    gap = (lam_or[H - 1] - lam_or[H]) / lam_or[0]
+    proj = np.linalg.norm(U[:, :H] @ U[:, :H].T - Uor[:, :H] @ Uor[:, :H].T, 2)
+    print(f"K={len(lam)}: eigenvalue err {lam_err:.2e} of lambda_0, projector distance {proj:.2e} "
+          f"(relative eigengap at H {gap:.2e})")
+    assert lam_err <= 1e-10
+    assert proj <= 1e-9 / max(gap, 1e-6)
+
+
+def test_precision_workload_U_against_oracle_kernel():
+    """K = 128 from 4096 noisy targets at SNR 0.1 (sections 3.3-3.4: the
+    principal vectors are the leading eigenvectors of C), the configuration
+    the bench times."""
+    cfg, P, A, B = _gen("precision", seed=3003)
+    plan = rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision="bf16x3", hermitian=True, products=6)
+    torch.cuda.synchronize()
+    _check_U(plan, B, P.w, cfg.Q, cfg.H)
 
 
 def test_diff_workload_forward_lse_rows():

@@ -209,6 +209,24 @@ radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs,
                                   const radsvd_job_out *outs, void *batch_ws, size_t batch_bytes,
                                   void *stream);
 
+/*
+ * align_pairs_batched for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same launch and the same results, bitwise, with the job
+ * table and queues in a device array the library holds for the life of the
+ * process, one per GPU (256 KiB), instead of a caller workspace.  The caller
+ * still passes the plans and the outputs; the call allocates no device
+ * memory.  The array of the current device is used; it keeps the last call's
+ * contents, and the launch rewrites every field it reads (queue positions
+ * start at zero) with kernels, not memset nodes.  Calls that overlap on one
+ * GPU (other streams, or another thread) share the array and race: order
+ * them.  Errors: as align_pairs_batched, and RADSVD_ERR_UNSUPPORTED for
+ * n_jobs > RADSVD_NOALLOC_MAX_JOBS.
+ */
+#define RADSVD_NOALLOC_MAX_JOBS 2048
+radsvd_status align_pairs_batched_noalloc(const radsvd_plan *const *plans, int n_jobs,
+                                          const radsvd_job_out *outs, void *stream);
+
 /* Copy U (device [K][K] FP64, column h = eigenvector h) and the eigenvalues
  * (device [K] FP64, descending) of C into caller buffers (either may be NULL).
  * With a caller-supplied U_in only its H columns are defined. */

@@ -19,14 +19,16 @@ import torch
 __all__ = [
     "RadsvdError", "FP64", "FP32", "BF16", "BF16X3", "OUT_BEST", "OUT_LSE", "OUT_FULL",
     "align_prepare_workspace", "align_prepare", "align_pairs", "align_backward_workspace",
-    "align_pairs_backward", "align_batched_workspace", "align_pairs_batched", "align_get_U",
+    "align_pairs_backward", "align_batched_workspace", "align_pairs_batched",
+    "align_pairs_batched_noalloc", "align_get_U",
     "align_set_tile", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
-    "PRECISIONS", "RadialAlignLSE", "pairs_batched",
+    "PRECISIONS", "RadialAlignLSE", "pairs_batched", "RADSVD_NOALLOC_MAX_JOBS",
 ]
 
 FP64, FP32, BF16, BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3}
 OUT_BEST, OUT_LSE, OUT_FULL = 1, 2, 4
+RADSVD_NOALLOC_MAX_JOBS = 2048   # include/radsvd.h
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "WORKSPACE", 4: "DEVICE"}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,6 +80,8 @@ def _load():
     L.align_batched_workspace.restype = sz
     L.align_pairs_batched.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(_JobOut), vp, sz, vp]
     L.align_pairs_batched.restype = i32
+    L.align_pairs_batched_noalloc.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(_JobOut), vp]
+    L.align_pairs_batched_noalloc.restype = i32
     L.align_get_U.argtypes = [vp, vp, vp, vp]
     L.align_get_U.restype = i32
     L.align_set_tile.argtypes = [vp, i32]
@@ -175,6 +179,14 @@ def align_pairs_batched(plans, outs, batch_ws, stream=None):
     jo = (_JobOut * n)(*[_JobOut(o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr()) for o in outs])
     nbytes = batch_ws.numel() * batch_ws.element_size()
     _check(_load().align_pairs_batched(arr, n, jo, _ptr(batch_ws), nbytes, _stream(stream)))
+
+
+def align_pairs_batched_noalloc(plans, outs, stream=None):
+    """As align_pairs_batched, with the library's own device scratch (no workspace)."""
+    n = len(plans)
+    arr = (ctypes.c_void_p * n)(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
+    jo = (_JobOut * n)(*[_JobOut(o[0].data_ptr(), o[1].data_ptr(), o[2].data_ptr()) for o in outs])
+    _check(_load().align_pairs_batched_noalloc(arr, n, jo, _stream(stream)))
 
 
 def align_get_U(plan, U_dev=None, lambda_dev=None, stream=None):

@@ -314,11 +314,11 @@ size_t align_batched_workspace(int n_jobs) {
     return batched_bytes(n_jobs);
 }
 
-radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs, const radsvd_job_out *outs,
-                                  void *batch_ws, size_t batch_bytes, void *stream) {
-    g_err[0] = 0;
+}  // extern "C"
+
+namespace {
+radsvd_status validate_batch(const radsvd_plan *const *plans, int n_jobs, const radsvd_job_out *outs) {
     if (!plans || !outs) return fail(RADSVD_ERR_INVALID_ARG, "plans / outs is NULL");
-    if (n_jobs < 1 || n_jobs > 4096) return fail(RADSVD_ERR_INVALID_ARG, "n_jobs=%d outside [1, 4096]", n_jobs);
     int prec = -1;
     for (int i = 0; i < n_jobs; ++i) {
         const radsvd_plan *p = plans[i];
@@ -334,12 +334,42 @@ radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs, c
                         "plans[%d]: the batched launch needs a Hermitian FP32/BF16/bf16x3 plan with "
                         "Q in {128, 192, 256, 384, 512} (got Q=%d)", i, p->Q);
     }
+    return RADSVD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+radsvd_status align_pairs_batched(const radsvd_plan *const *plans, int n_jobs, const radsvd_job_out *outs,
+                                  void *batch_ws, size_t batch_bytes, void *stream) {
+    g_err[0] = 0;
+    if (n_jobs < 1 || n_jobs > 4096) return fail(RADSVD_ERR_INVALID_ARG, "n_jobs=%d outside [1, 4096]", n_jobs);
+    const radsvd_status st = validate_batch(plans, n_jobs, outs);
+    if (st != RADSVD_OK) return st;
     const size_t need = batched_bytes(n_jobs);
     if (!batch_ws) return fail(RADSVD_ERR_WORKSPACE, "batch workspace is NULL");
     if (!aligned(batch_ws, 256)) return fail(RADSVD_ERR_WORKSPACE, "batch workspace must be 256-byte aligned");
     if (batch_bytes < need) return fail(RADSVD_ERR_WORKSPACE, "batch workspace too small: %zu < %zu", batch_bytes, need);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     return dev_check(launch_pairs_batched(plans, n_jobs, outs, batch_ws, s), "align_pairs_batched launch");
+}
+
+static_assert(RADSVD_NOALLOC_MAX_JOBS >= 1 && RADSVD_NOALLOC_MAX_JOBS <= 4096, "no-allocation job limit");
+
+radsvd_status align_pairs_batched_noalloc(const radsvd_plan *const *plans, int n_jobs,
+                                          const radsvd_job_out *outs, void *stream) {
+    g_err[0] = 0;
+    if (n_jobs < 1) return fail(RADSVD_ERR_INVALID_ARG, "n_jobs=%d must be >= 1", n_jobs);
+    if (n_jobs > RADSVD_NOALLOC_MAX_JOBS || batched_bytes(n_jobs) > kNoAllocScratchBytes)
+        return fail(RADSVD_ERR_UNSUPPORTED, "n_jobs=%d exceeds the no-allocation limit of %d jobs", n_jobs,
+                    RADSVD_NOALLOC_MAX_JOBS);
+    const radsvd_status st = validate_batch(plans, n_jobs, outs);
+    if (st != RADSVD_OK) return st;
+    void *ws = nullptr;
+    const hipError_t e = noalloc_scratch(&ws);
+    if (e != hipSuccess) return dev_check(e, "align_pairs_batched_noalloc scratch address");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return dev_check(launch_pairs_batched(plans, n_jobs, outs, ws, s), "align_pairs_batched_noalloc launch");
 }
 
 radsvd_status align_get_U(const radsvd_plan *p, double *U_dev, double *lambda_dev, void *stream) {

@@ -3,11 +3,45 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "batched.h"
 
 namespace radsvd {
+
+// Job table and queues of align_pairs_batched_noalloc, for callers that cannot
+// allocate: one copy per GPU for the life of the process.  Host code never
+// uses this name as an address (on the host it is only a stand-in for the
+// symbol); it uses the per-device address from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static_assert(sizeof(fastk::BatchHeader) <= 256 &&
+                  256 + (RADSVD_NOALLOC_MAX_JOBS * sizeof(fastk::BatchJob) + 255) / 256 * 256 <= kNoAllocScratchBytes,
+              "the no-allocation scratch holds the header and the job table of the maximum job count");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 namespace fastk {
 

@@ -138,6 +138,10 @@ hipError_t launch_backward(const radsvd_plan *p, float inv_s2, const float *lse_
 
 // batched.hip
 size_t batched_bytes(int n_jobs);
+// the no-allocation batched launch: job table and queues in a static device
+// array of kNoAllocScratchBytes per GPU (RADSVD_NOALLOC_MAX_JOBS jobs)
+constexpr size_t kNoAllocScratchBytes = 256 * 1024;
+hipError_t noalloc_scratch(void **out);
 bool batched_supported(const radsvd_plan *p);
 hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, const radsvd_job_out *outs,
                                 void *ws, hipStream_t s);

@@ -88,6 +88,16 @@ def test_pairs_and_backward_argument_errors():
     assert lib.align_set_tile(None, 0) == 1
     assert lib.align_batched_workspace(0) == 0
     assert lib.align_pairs_batched(None, 1, None, None, 0, None) == 1
+    assert lib.align_pairs_batched_noalloc(None, 1, None, None) == 1
+    assert lib.align_pairs_batched_noalloc(None, 0, None, None) == 1
+    # the job limit of the library's own scratch is checked before anything else
+    assert lib.align_pairs_batched_noalloc(None, rs.RADSVD_NOALLOC_MAX_JOBS + 1, None, None) == 2
+    assert "no-allocation limit" in rs.radsvd_last_error()
+
+
+def test_noalloc_job_limit_matches_header():
+    src = open(os.path.join(ROOT, "include", "radsvd.h")).read()
+    assert f"#define RADSVD_NOALLOC_MAX_JOBS {rs.RADSVD_NOALLOC_MAX_JOBS}" in src
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):

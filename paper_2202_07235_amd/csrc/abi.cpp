@@ -83,6 +83,10 @@ Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
     const bool split_b = b3 && pr->products != 3;
     L.ffmt_a = pr->prec == RADSVD_FP32 ? kFragF32 : kFragBF16;
     L.ffmt_b = pr->prec == RADSVD_FP32 ? kFragF32 : (split_b ? kFragF32B : kFragBF16);
+    if (wide_plan(pr->prec, pr->products, pr->hermitian, Q)) {
+        L.ffmt_a = kFragBF16D;
+        L.ffmt_b = kFragF32P;
+    }
     L.nplanes_a = b3 ? (pr->products == 3 ? 2 : 3) : 1;
     L.nplanes_b = b3 ? (pr->products == 3 ? 2 : 1) : 1;
     L.na_pad = (n_img + kFastTA - 1) / kFastTA * kFastTA;

@@ -1,7 +1,9 @@
 // Persistent multi-job launch of the fused Hermitian pair kernel.
 //
 // Many independent alignment jobs, each with its own angle count Q, rank H,
-// translations and image/target counts, run in one launch: every job's tiles
+// translations and image/target counts, run in one launch per tile class
+// (the four-wave tile body, and the eight-wave one at Q = 384 and 512 for
+// split bf16 with six products): every job's tiles
 // (8 images x 16 targets, all translations) make up its work items, one tile
 // per item, or several consecutive ones for jobs whose tiles are cheap (so
 // that the per-item queue and call overhead stays small).  Items are
@@ -35,18 +37,24 @@ struct BatchJob {
 
 constexpr int kChunk = 128;   // consecutive items per XCD chunk
 
+// Two classes of items, each with its own persistent launch: class 0 runs the
+// four-wave tile body (256 threads), class 1 the eight-wave one of the plans
+// wide_plan() selects (512 threads).  Jobs are ordered by class, so a class's
+// items are the contiguous range [base, base + its item count).
 struct BatchHeader {
     int n_jobs;
-    int total;                  // work items
-    int count[8];               // items in each XCD's queue
-    unsigned int next[8];       // queue positions
+    int total;                  // work items of both classes
+    int base[2];                // first item of each class
+    int count[2][8];            // items in each XCD's queue, per class
+    unsigned int next[2][8];    // queue positions
 };
 
 constexpr int kTableChunk = 32;   // jobs per table-writer launch (kernel argument space)
 
 struct TableChunk {
     int first, n, n_jobs, total;
-    int count[8];
+    int base[2];
+    int count[2][8];
     BatchJob jobs[kTableChunk];
 };
 
@@ -81,35 +89,47 @@ __device__ __forceinline__ void tile_q(int hi, CArgs &a, int lin0, int cnt, unsi
     }
 }
 
-template <int KIND>
-__global__ __launch_bounds__(256, 1) void k_pairs_batched(BatchHeader *hdr, const BatchJob *__restrict__ jobs_g) {
-    extern __shared__ unsigned char smem_raw[];
-    // the item handoff uses the tile's staging memory (the tile needs all 160 KB
-    // at Q = 512); the barrier after the read keeps it from being overwritten early
+// Takes the items of class CLS from the XCD queues (its own first, then the
+// others) and runs f(job, lin0, cnt) for each; every wave of the workgroup
+// leaves together once all queues are empty.
+template <int CLS, class F>
+__device__ __forceinline__ void batch_loop(BatchHeader *hdr, CJob *jobs, unsigned char *smem_raw, F &&f) {
+    // the item handoff uses the tile's staging memory; the barrier after the
+    // read keeps it from being overwritten early
     int &s_item = *reinterpret_cast<int *>(smem_raw);
-    CJob *jobs = (CJob *)jobs_g;
     const int x0 = blockIdx.x & 7;   // workgroups are dealt to the XCDs round-robin
+    const int base = hdr->base[CLS], nj = hdr->n_jobs;
     for (int qn = 0; qn < 8; ++qn) {
       const int x = (x0 + qn) & 7;
       for (;;) {
-        const int qcount = hdr->count[x], nj = hdr->n_jobs;
+        const int qcount = hdr->count[CLS][x];
         __syncthreads();   // s_item of the previous item has been read by every thread
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&hdr->next[x], 1u);
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&hdr->next[CLS][x], 1u);
         __syncthreads();
         const int k = s_item;
         __syncthreads();
         if (k >= qcount) break;   // uniform across the workgroup: every wave leaves
-        const int item = (x + 8 * (k / kChunk)) * kChunk + k % kChunk;
+        const int item = base + (x + 8 * (k / kChunk)) * kChunk + k % kChunk;
         int lo = 0, hi = nj - 1;    // last job with item0 <= item
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (jobs[mid].item0 <= item) lo = mid;
             else hi = mid - 1;
         }
-        CArgs &a = jobs[lo].a;
-        const int qi = jobs[lo].qi, hr = jobs[lo].hi, g = jobs[lo].group;
+        const int g = jobs[lo].group;
         const int lin0 = (item - jobs[lo].item0) * g;
-        const int cnt = min(g, a.nTA * a.nTB - lin0);
+        const int cnt = min(g, jobs[lo].a.nTA * jobs[lo].a.nTB - lin0);
+        f(jobs[lo], lin0, cnt);
+      }
+    }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256, 1) void k_pairs_batched(BatchHeader *hdr, const BatchJob *__restrict__ jobs_g) {
+    extern __shared__ unsigned char smem_raw[];
+    batch_loop<0>(hdr, (CJob *)jobs_g, smem_raw, [&](CJob &J, int lin0, int cnt) {
+        CArgs &a = J.a;
+        const int qi = J.qi, hr = J.hi;
         switch (qi) {
         case 0: tile_q<128, KIND>(hr, a, lin0, cnt, smem_raw); break;
         case 1: tile_q<192, KIND>(hr, a, lin0, cnt, smem_raw); break;
@@ -117,8 +137,7 @@ __global__ __launch_bounds__(256, 1) void k_pairs_batched(BatchHeader *hdr, cons
         case 3: tile_q<384, KIND>(hr, a, lin0, cnt, smem_raw); break;
         default: tile_q<512, KIND>(hr, a, lin0, cnt, smem_raw); break;
         }
-      }
-    }
+    });
 }
 
 template <int KIND>
@@ -134,6 +153,8 @@ hipError_t launch_batched_kind(BatchHeader *hdr, const BatchJob *jobs, int grid,
     return hipGetLastError();
 }
 
+// the eight-wave items (Q = 384, 512; split bf16 with 6 products): batched_wide.hip
+hipError_t launch_batched_wide(BatchHeader *hdr, const BatchJob *jobs, int grid, hipStream_t s);
 hipError_t launch_batched_fp32(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
 hipError_t launch_batched_bf16(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
 hipError_t launch_batched_bf16x3(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);

@@ -50,9 +50,10 @@ namespace fastk {
 __global__ void k_batch_table(TableChunk c, BatchHeader *hdr, BatchJob *jobs) {
     const int i = threadIdx.x;
     if (i < c.n) jobs[c.first + i] = c.jobs[i];
-    if (c.first == 0 && i < 8) {
-        hdr->count[i] = c.count[i];
-        hdr->next[i] = 0u;
+    if (c.first == 0 && i < 16) {
+        hdr->count[i >> 3][i & 7] = c.count[i >> 3][i & 7];
+        hdr->next[i >> 3][i & 7] = 0u;
+        if (i < 2) hdr->base[i] = c.base[i];
         if (i == 0) {
             hdr->n_jobs = c.n_jobs;
             hdr->total = c.total;
@@ -97,19 +98,22 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
                                 void *ws, hipStream_t s) {
     using namespace fastk;
     const int kind = plan_kind(plans[0]);
-    // item order: decreasing cost per item (translations x angles x work per angle)
-    std::vector<int> order(n_jobs);
+    // item order: class (four-wave tiles, then eight-wave), then decreasing cost
+    // per item (translations x angles x work per angle)
+    std::vector<int> order(n_jobs), cls(n_jobs);
     std::vector<double> cost(n_jobs);
-    int max_q = 0;
+    int max_q0 = 0;
     for (int i = 0; i < n_jobs; ++i) {
         const radsvd_plan *p = plans[i];
         order[i] = i;
+        cls[i] = wide_plan(p->prec, p->products, p->herm, p->Q) ? 1 : 0;
         cost[i] = (double)p->T * p->Q * (std::log2((double)p->Q) + 0.25 * p->H8);
-        max_q = std::max(max_q, p->Q);
+        if (!cls[i]) max_q0 = std::max(max_q0, p->Q);
     }
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return cls[x] != cls[y] ? cls[x] < cls[y] : cost[x] > cost[y]; });
     std::vector<BatchJob> jobs(n_jobs);
-    int total = 0;
+    int total = 0, n_cls[2] = {0, 0};
     for (int k = 0; k < n_jobs; ++k) {
         const int i = order[k];
         const radsvd_plan *p = plans[i];
@@ -138,11 +142,15 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
         const double ref = 9.0 * 256 * (8.0 + 4.0);
         J.group = std::max(1, std::min(16, (int)std::lround(ref / cost[i])));
         J.item0 = total;
-        total += (a.nTA * a.nTB + J.group - 1) / J.group;
+        const int items = (a.nTA * a.nTB + J.group - 1) / J.group;
+        total += items;
+        n_cls[cls[i]] += items;   // class-0 jobs come first: class 1 starts at n_cls[0]
     }
-    // items of each XCD queue: chunks x, x + 8, x + 16, ... of kChunk items
-    int count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int c = 0; (long)c * kChunk < total; ++c) count[c & 7] += std::min(kChunk, total - c * kChunk);
+    const int base[2] = {0, n_cls[0]};
+    // items of each XCD queue of a class: chunks x, x + 8, x + 16, ... of kChunk items
+    int count[2][8] = {};
+    for (int q = 0; q < 2; ++q)
+        for (int c = 0; (long)c * kChunk < n_cls[q]; ++c) count[q][c & 7] += std::min(kChunk, n_cls[q] - c * kChunk);
     char *w = reinterpret_cast<char *>(ws);
     BatchHeader *hdr = reinterpret_cast<BatchHeader *>(w);
     BatchJob *djobs = reinterpret_cast<BatchJob *>(w + align_up(sizeof(BatchHeader), 256));
@@ -153,20 +161,28 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
         c.n = std::min(kTableChunk, n_jobs - first);
         c.n_jobs = n_jobs;
         c.total = total;
-        for (int x = 0; x < 8; ++x) c.count[x] = count[x];
+        for (int q = 0; q < 2; ++q) {
+            c.base[q] = base[q];
+            for (int x = 0; x < 8; ++x) c.count[q][x] = count[q][x];
+        }
         for (int k = 0; k < c.n; ++k) c.jobs[k] = jobs[first + k];
         hipLaunchKernelGGL(k_batch_table, dim3(1), dim3(kTableChunk), 0, s, c, hdr, djobs);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int grid = std::max(1, std::min(total, device_cus()));
-    const size_t shmem = (size_t)(2 * 16 * 128 + (max_q / 8) * 256) * sizeof(cx<float>);
-    switch (kind) {
-    case 0: return launch_batched_fp32(hdr, djobs, grid, shmem, s);
-    case 1: return launch_batched_bf16(hdr, djobs, grid, shmem, s);
-    case 2: return launch_batched_bf16x3(hdr, djobs, grid, shmem, s);
-    default: return launch_batched_bf16x3_6(hdr, djobs, grid, shmem, s);
+    if (n_cls[0] > 0) {
+        const int grid = std::max(1, std::min(n_cls[0], device_cus()));
+        const size_t shmem = (size_t)(2 * 16 * 128 + (max_q0 / 8) * 256) * sizeof(cx<float>);
+        switch (kind) {
+        case 0: e = launch_batched_fp32(hdr, djobs, grid, shmem, s); break;
+        case 1: e = launch_batched_bf16(hdr, djobs, grid, shmem, s); break;
+        case 2: e = launch_batched_bf16x3(hdr, djobs, grid, shmem, s); break;
+        default: e = launch_batched_bf16x3_6(hdr, djobs, grid, shmem, s); break;
+        }
+        if (e != hipSuccess) return e;
     }
+    if (n_cls[1] > 0) e = launch_batched_wide(hdr, djobs, std::max(1, std::min(n_cls[1], device_cus())), s);
+    return e;
 }
 
 }  // namespace radsvd

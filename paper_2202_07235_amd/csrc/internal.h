@@ -47,11 +47,28 @@ constexpr int kFastTB = 16;    // targets per tile  (16 MFMA columns)
 //   one 1 KB block (lane l's 4 values).
 // * FP32 plane: chunks of 16 consecutive k (v_mfma_f32_16x16x4_f32; lane l's
 //   element j feeds the chunk's MFMA j with k = 16 chunk + 4 j + l / 16).
-constexpr int kFragF32 = 0, kFragBF16 = 1, kFragF32B = 2;
+//
+// The eight-wave kernel (Q = 384, 512, split bf16 with 6 products) uses the
+// paired slot order: lane l of a full chunk holds h = 16 chunk + 4 (l / 16)
+// + 0..3, slots 0..3 for c = 0 and 4..7 for c = 1 (half chunk: h = 16 NF +
+// 2 (l / 16) + 0..1, slots 0..1 and 2..3).  A Re row and the Im row of the
+// same image then hold the same values, [ar | ai] and [-ai | ar], so the
+// image operand stores each value once (kFragBF16D): lane l keeps 8 bytes
+// (4 for the half chunk) of its "own" part, ar for even rows and ai for odd
+// rows, and receives the other part from lane l ^ 1 in registers.
+// kFragF32P holds the targets as FP32 in the paired order: per full chunk a
+// 1 KB half of br (lane l's 4 values at 16 l) and one of bi; the half chunk
+// one 1 KB block of [br h0, br h1, bi h0, bi h1].
+constexpr int kFragF32 = 0, kFragBF16 = 1, kFragF32B = 2, kFragBF16D = 3, kFragF32P = 4;
 __host__ __device__ inline int frag_plane_bytes(int fmt, int H8) {
     if (fmt == kFragBF16) return (H8 / 16) * 1024 + ((H8 % 16) ? 512 : 0);
-    if (fmt == kFragF32B) return (H8 / 16) * 2048 + ((H8 % 16) ? 1024 : 0);
+    if (fmt == kFragF32B || fmt == kFragF32P) return (H8 / 16) * 2048 + ((H8 % 16) ? 1024 : 0);
+    if (fmt == kFragBF16D) return (H8 / 16) * 512 + ((H8 % 16) ? 256 : 0);
     return (H8 / 8) * 1024;
+}
+// plans that run the eight-wave pair kernel (and use the paired layouts)
+__host__ __device__ inline bool wide_plan(int prec, int products, int hermitian, int Q) {
+    return hermitian && prec == RADSVD_BF16X3 && products == 6 && (Q == 384 || Q == 512);
 }
 // byte offset of element (row, c, h) within one plane of an operand block
 __host__ __device__ inline int frag_elem_offset(int fmt, int H8, int row, int c, int h) {

@@ -915,6 +915,8 @@ hipError_t launch_fast_fp32(const Args &a, int Q, int nwg, int H8, hipStream_t s
 hipError_t launch_fast_bf16(const Args &a, int Q, int nwg, int H8, hipStream_t s);
 hipError_t launch_fast_bf16x3(const Args &a, int Q, int nwg, int H8, hipStream_t s);
 hipError_t launch_fast_bf16x3_6(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+// eight-wave kernel of the plans wide_plan() selects (pairs_wide.hip)
+hipError_t launch_wide(const Args &a, int Q, int nwg, int H8, hipStream_t s);
 
 }  // namespace fastk
 }  // namespace radsvd

@@ -40,6 +40,7 @@ hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, floa
     a.best_t = best_t;
     a.lse_pair = lse_pair;
     const int nwg = a.nTA * a.nTB;
+    if (wide_plan(p->prec, p->products, p->herm, p->Q)) return fastk::launch_wide(a, p->Q, nwg, p->H8, s);
     if (p->prec == RADSVD_FP32) return fastk::launch_fast_fp32(a, p->Q, nwg, p->H8, s);
     if (p->prec == RADSVD_BF16) return fastk::launch_fast_bf16(a, p->Q, nwg, p->H8, s);
     if (p->products == 3) return fastk::launch_fast_bf16x3(a, p->Q, nwg, p->H8, s);

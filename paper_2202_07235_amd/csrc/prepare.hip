@@ -240,6 +240,64 @@ __device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_t
         const cx<float> v = yb[hh * Q + pos];
         return (c ? v.im : v.re) * scale;
     };
+    if (f_kind == kFragBF16D || f_kind == kFragF32P) {
+        // paired slot order: lane group g of a full chunk holds h = 16 chunk + 4 g
+        // + 0..3 (half chunk: 16 NF + 2 g + 0..1); fragment lane 16 g + row
+        const int NF = H8 / 16;
+        const int chunk = h0 / 16;
+        const bool full = chunk < NF;
+        const int nv = full ? 4 : 2;
+        for (int i = tid; i < Qc * 4; i += nt) {
+            const int q = i >> 2, g = i & 3;
+            const int hb = full ? 16 * chunk + 4 * g : 16 * NF + 2 * g;
+            const int pos = pos_tab[q];
+            char *blk = reinterpret_cast<char *>(F) + (((size_t)t * f_ntiles + tile) * f_q + q) * blockB;
+            if (f_kind == kFragF32P) {   // target column n_in: [br ..., bi ...]
+                float re[4] = {0.f, 0.f, 0.f, 0.f}, im[4] = {0.f, 0.f, 0.f, 0.f};
+                for (int e = 0; e < nv; ++e) {
+                    re[e] = val(hb + e, pos, 0);
+                    im[e] = val(hb + e, pos, 1);
+                }
+                const int ln = 16 * g + n_in;
+                if (full) {
+                    u32x4_t w0, w1;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        w0[d] = __float_as_uint(re[d]);
+                        w1[d] = __float_as_uint(im[d]);
+                    }
+                    *reinterpret_cast<u32x4_t *>(blk + chunk * 2048 + ln * 16) = w0;
+                    *reinterpret_cast<u32x4_t *>(blk + chunk * 2048 + 1024 + ln * 16) = w1;
+                } else {
+                    const u32x4_t w0 = {__float_as_uint(re[0]), __float_as_uint(re[1]), __float_as_uint(im[0]),
+                                        __float_as_uint(im[1])};
+                    *reinterpret_cast<u32x4_t *>(blk + NF * 2048 + ln * 16) = w0;
+                }
+                continue;
+            }
+            // image n_in: row 2 n_in keeps its re values, row 2 n_in + 1 its im
+            // values, each split into the three bf16 planes
+            for (int part = 0; part < 2; ++part) {
+                uint16_t pk[3][4] = {};
+                for (int e = 0; e < nv; ++e) split3_bf16(val(hb + e, pos, part), pk[0][e], pk[1][e], pk[2][e]);
+                const int ln = 16 * g + 2 * n_in + part;
+#pragma unroll
+                for (int pl_i = 0; pl_i < 3; ++pl_i) {
+                    if (pl_i >= nplanes) break;
+                    char *pb = blk + (size_t)pl_i * planeB;
+                    if (full) {
+                        const u32x2_t wv = {(unsigned)pk[pl_i][0] | ((unsigned)pk[pl_i][1] << 16),
+                                            (unsigned)pk[pl_i][2] | ((unsigned)pk[pl_i][3] << 16)};
+                        *reinterpret_cast<u32x2_t *>(pb + chunk * 512 + ln * 8) = wv;
+                    } else {
+                        *reinterpret_cast<unsigned *>(pb + NF * 512 + ln * 4) =
+                            (unsigned)pk[pl_i][0] | ((unsigned)pk[pl_i][1] << 16);
+                    }
+                }
+            }
+        }
+        return;
+    }
     if (fbf) {
         const int NF = H8 / 16;
         const int chunk = h0 / 16;

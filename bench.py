@@ -48,6 +48,8 @@ def parse():
                          "3 only the two leading terms")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of N_A and N_B (for quick local runs; 1.0 = the full workload)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (plain FP32 batch, batching, differentiation)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the same-GPU comparison runs (FP32, bf16x3 with 3 products)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB streaming kernel (x -> -x) whose HBM counters calibrate FETCH_SIZE / "
@@ -58,11 +60,22 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pairs_fast_precision_bf16x3_6_traffic.txt")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_pairs_wide_precision_bf16x3_6_traffic.txt")
 TRAFFIC_CONFIG = "bf16x3 products=6"
+TRAFFIC_KERNEL = "k_pairs_wide"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_07235_amd", "csrc", f)
-                  for f in ("pairs_fast.h", "pairs_fast.hip", "pairs_fast_bf16x3_6.hip", "common.h", "internal.h")]
+                  for f in ("pairs_wide.h", "pairs_wide.hip", "pairs_fast.h", "pairs_fast.hip", "common.h",
+                            "internal.h")]
 COPY_BYTES = 1 << 30
+
+
+def pair_kernel_name(Q, precision, products):
+    """The fused kernel align_pairs(BEST) dispatches for a Hermitian plan: the
+    eight-wave kernel for split bf16 with six products at Q = 384 and 512, the
+    four-wave one otherwise."""
+    if precision == "bf16x3" and products == 6 and Q in (384, 512):
+        return f"k_pairs_wide<Q={Q},bf16x3,6 products>"
+    return f"k_pairs_fast<Q={Q},{precision}{',%d products' % products if precision == 'bf16x3' else ''}>"
 
 
 def kernel_source_hash():
@@ -101,7 +114,7 @@ def reduce_counters(fetch_dir, write_dir):
             if r.get("Counter_Name") != name:
                 continue
             kn, v = r.get("Kernel_Name", ""), float(r["Counter_Value"])
-            if "k_pairs_fast" in kn:
+            if TRAFFIC_KERNEL in kn:
                 pair.append(v)
             elif "neg" in kn and "elementwise" in kn:
                 copy.append(v)
@@ -113,7 +126,7 @@ def reduce_counters(fetch_dir, write_dir):
     wa, nw, wc, wf = out["WRITE_SIZE"]
     traffic = fa * 1024.0 * ff + wa * 1024.0 * wf
     lines = [
-        "# HBM traffic of k_pairs_fast, precision workload (N=256 K=128 Q=512 N_A=N_B=4096 T=9 H=24)",
+        f"# HBM traffic of {TRAFFIC_KERNEL}, precision workload (N=256 K=128 Q=512 N_A=N_B=4096 T=9 H=24)",
         "# kernel_source_sha256_16: hash of the pair kernel sources with comments removed (bench.kernel_source_hash)",
         f"config: {TRAFFIC_CONFIG}",
         f"kernel_source_sha256_16: {kernel_source_hash()}",
@@ -248,6 +261,214 @@ def cpu_baseline(P, A, B, U, H, gpu_out, budget_s=12.0):
                              "argmax_exact": agree, "argmax_within_tol": near}
 
 
+def roofline(cfg, precision, products, kernel_ms):
+    """Roofline of the fused pair kernel on one launch over a workload: the
+    contraction's algorithmic flops (8 H (Q/2 + 1) per pair-translation, times
+    the split products), the half-spectrum transform's 2.5 Q log2 Q on the
+    vector unit, and the minimum operand + output bytes; the bound is the unit
+    with the largest time at its published peak."""
+    n_pairs = cfg.n_img * cfg.n_tgt
+    pair_delta = n_pairs * cfg.T
+    H, Q = cfg.H, cfg.Q
+    M1 = Q // 2 + 1
+    nprod = {"fp32": 1, "bf16": 1, "bf16x3": products}[precision]
+    flops_contract = 8.0 * H * M1 * pair_delta                # conj(a) b over h, q in [0, Q/2]
+    flops_fft = 2.5 * Q * math.log2(Q) * pair_delta           # half-spectrum inverse transform
+    t_s = kernel_ms * 1e-3
+    t_mfma = flops_contract * nprod / (PEAK_BF16_TFLOPS * 1e12) if precision != "fp32" else \
+        flops_contract / (PEAK_FP32_MATRIX_TFLOPS * 1e12)
+    t_valu = flops_fft / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
+    H8 = (H + 7) // 8 * 8
+    # operand bytes per real value (images, targets): FP32 4 B; bf16 2 B; bf16x3 with 3 products
+    # two bf16 planes (4 B); with 6 products the images' three bf16 planes (6 B) and the
+    # targets' FP32 values, split in registers (4 B)
+    bpr_a, bpr_b = {"fp32": (4, 4), "bf16": (2, 2), "bf16x3": (4, 4) if products == 3 else (6, 4)}[precision]
+    bytes_min = (cfg.n_img * bpr_a + cfg.n_tgt * cfg.T * bpr_b) * M1 * 2 * H8 + n_pairs * 12
+    t_hbm = bytes_min / (PEAK_HBM_GBS * 1e9)
+    bound = max(("mfma", t_mfma), ("alu", t_valu), ("hbm", t_hbm), key=lambda kv: kv[1])
+    if bound[0] == "alu":
+        roof = {"bound": "alu", "achieved": flops_fft / t_s / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                "unit": "TFLOP/s"}
+    elif bound[0] == "mfma":
+        pk = PEAK_BF16_TFLOPS if precision != "fp32" else PEAK_FP32_MATRIX_TFLOPS
+        roof = {"bound": "mfma", "achieved": flops_contract * nprod / t_s / 1e12, "peak": pk, "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_min / t_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = pair_kernel_name(Q, precision, products)
+    roof["kernel_ms"] = kernel_ms
+    roof["per_unit"] = {"unit": "pair-translation", "units_per_launch": pair_delta,
+                        "contraction_flops": 8 * H * M1, "fft_flops": 2.5 * Q * math.log2(Q),
+                        "products": nprod, "operand_bytes_min_total": bytes_min}
+    roof["unit_times_ms"] = {"mfma": 1e3 * t_mfma, "valu_fft": 1e3 * t_valu, "hbm": 1e3 * t_hbm}
+    return roof
+
+
+def _make_inputs(synth, torch, cfg, seed):
+    P = synth.make_problem(cfg, seed=seed, device="cuda")
+    A = P.A.to(torch.complex64).contiguous()
+    B = P.B.to(torch.complex64).contiguous()
+    P.A = P.B = None
+    return P, A, B
+
+
+def plain_workload(rs, synth, torch, steps=5):
+    """The plain FP32 batch (N 128, K 64, Q 256, 1024 x 1024 pairs, T 9, H 16),
+    one step = align_prepare + align_pairs(BEST), in FP32 and in split bf16
+    with six products, each with the pair kernel's roofline."""
+    cfg = synth.config("fp32")
+    P, A, B = _make_inputs(synth, torch, cfg, 2002)
+    out = {"workload": f"plain FP32 batch: N={cfg.N} K={cfg.K} Q={cfg.Q} N_A={cfg.n_img} N_B={cfg.n_tgt} "
+                       f"T={cfg.T} H={cfg.H}"}
+    for prec, prod in (("fp32", 3), ("bf16x3", 6)):
+        st = Step(__import__("paper_2202_07235_amd"), A, B, P, cfg.H, prec, prod)
+        wall, pms = timed(st, steps, 2)
+        st.close()
+        kms = float(sum(pms) / len(pms))
+        roof = roofline(cfg, prec, prod, kms)
+        key = prec if prec == "fp32" else f"{prec}_{prod}products"
+        out[key] = {"image_pairs_per_s": cfg.n_img * cfg.n_tgt * steps / wall, "ms_per_step": 1e3 * wall / steps,
+                    "pairs_kernel_ms": kms,
+                    "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "kernel")}}
+        print(f"[bench] plain workload {key}: {out[key]['ms_per_step']:.2f} ms/step, pairs kernel {kms:.2f} ms, "
+              f"frac {roof['frac']:.3f}", file=sys.stderr, flush=True)
+    return out
+
+
+def batching_workload(rs, synth, torch, reps=3):
+    """The batching workload (64 jobs: N in {64 .. 256}, K = N/2, Q = 2N,
+    N_A in [128, 2048], N_B in [64, 1024] log-uniform, T in {1, 9, 25}, H in
+    [8, 32]; split bf16, six products): the pair step as one launch per job
+    and as the persistent batched launch, both after the autotuner; and the
+    whole step (prepare of every job + the batched launch) replayed from a
+    HIP graph."""
+    from paper_2202_07235_amd import autotune
+    cfgs = synth.batch_configs(64, seed=4000)
+    plans = []
+    for i, cfg in enumerate(cfgs):
+        P, A, B = _make_inputs(synth, torch, cfg, 4000 + i)
+        plans.append(rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision="bf16x3", products=6))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    autotune.tune_jobs(plans)
+    tune_s = time.perf_counter() - t0
+    outs = [p.pairs("best") for p in plans]
+    bouts = [{k: torch.empty_like(v) for k, v in o.items()} for o in outs]
+    ws = torch.empty(rs.align_batched_workspace(len(plans)), dtype=torch.uint8, device="cuda")
+
+    def per_job():
+        for p, o in zip(plans, outs):
+            p.pairs("best", outputs=o)
+
+    def batched():
+        rs.pairs_batched(plans, outputs=bouts, batch_ws=ws)
+
+    times = {}
+    for name, fn in (("one_launch_per_job_ms", per_job), ("batched_ms", batched)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / reps
+    same = all(torch.equal(o[k], b[k]) for o, b in zip(outs, bouts) for k in o)
+    pairs = sum(c.n_img * c.n_tgt for c in cfgs)
+    res = {"workload": "batching: 64 jobs, N in {64,96,128,192,256}, K=N/2, Q=2N, N_A in [128,2048], "
+                       "N_B in [64,1024], T in {1,9,25}, H in [8,32], bf16x3 (6 products)",
+           "image_pairs": pairs, **times, "speedup_batched_vs_per_job": times["one_launch_per_job_ms"] / times["batched_ms"],
+           "batched_equals_per_job": same, "autotune_s": tune_s, "tuned": autotune.describe(plans)}
+    try:
+        res.update(graph_step(rs, torch, plans, outs, reps))
+    except Exception as ex:   # reported, not hidden: the key says why the graph figure is missing
+        res["graph_error"] = repr(ex)
+    print(f"[bench] batching workload: {res}", file=sys.stderr, flush=True)
+    for p in plans:
+        p.close()
+    return res
+
+
+def graph_step(rs, torch, plans, ref, reps):
+    """The whole step (prepare of every job on 4 side streams + the batched
+    pair launch), eager and replayed from a HIP graph (each replay checked
+    against the eager outputs), against prepare + pairs one job at a time."""
+    from paper_2202_07235_amd.batch import BatchStep
+    bs = BatchStep(plans)
+
+    def one_by_one():
+        for p, o in zip(plans, ref):
+            h = rs.align_prepare(p.problem, p.n_img, p.A, p.n_tgt, p.B, p.U_in, p.ws)
+            rs.align_set_tile(h, p.band)
+            rs.align_set_waves(h, p.waves)
+            rs.align_pairs(h, rs.OUT_BEST, 1.0, o["best_score"], o["best_m"], o["best_t"])
+            rs.align_plan_destroy(h)
+
+    def timed_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    per_job_ms = timed_ms(one_by_one)
+    eager_ms = timed_ms(bs.run)
+    eager = [{k: v.clone() for k, v in o.items()} for o in bs.outs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bs.run()
+    torch.cuda.synchronize()
+    graph_ms = timed_ms(g.replay)
+    for o in bs.outs:
+        o["best_score"].fill_(float("nan"))
+    g.replay()
+    torch.cuda.synchronize()
+    ok = all(torch.equal(e[k], o[k]) for e, o in zip(eager, bs.outs) for k in e)
+    ok_ref = all(torch.equal(r[k], o[k]) for r, o in zip(ref, bs.outs) for k in r)
+    del g
+    bs.close()
+    return {"step_one_job_at_a_time_ms": per_job_ms, "step_batched_eager_ms": eager_ms,
+            "step_batched_graph_ms": graph_ms, "speedup_step_graph_vs_one_job_at_a_time": per_job_ms / graph_ms,
+            "graph_replay_equals_eager": ok, "graph_equals_one_job_at_a_time": ok_ref}
+
+
+def differentiation_workload(rs, synth, torch, reps=3):
+    """The differentiation workload (N 128, K 64, Q 256, 2048 images, 256
+    templates, T 9, H 16, sigma^2 = 1): forward LSE and the backward pass with
+    respect to the templates' polar coefficients and U, FP32 plan."""
+    cfg = synth.config("diff")
+    P, A, B = _make_inputs(synth, torch, cfg, 5005)
+    plan = rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision="fp32")
+    g = torch.ones(cfg.n_img, dtype=torch.float32, device="cuda")
+    o = plan.pairs("lse", inv_sigma2=1.0)
+    plan.backward(1.0, o["lse_img"], g)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fw, bw = [], []
+    for _ in range(reps):
+        ev[0].record()
+        o = plan.pairs("lse", inv_sigma2=1.0)
+        ev[1].record()
+        plan.backward(1.0, o["lse_img"], g)
+        ev[2].record()
+        torch.cuda.synchronize()
+        fw.append(ev[0].elapsed_time(ev[1]))
+        bw.append(ev[1].elapsed_time(ev[2]))
+    res = {"workload": f"differentiation: N={cfg.N} K={cfg.K} Q={cfg.Q} N_A={cfg.n_img} N_B={cfg.n_tgt} T={cfg.T} "
+                       f"H={cfg.H}, loss = sum_a logsumexp(X / sigma^2), FP32 plan",
+           "forward_lse_ms": min(fw), "backward_ms": min(bw)}
+    print(f"[bench] differentiation workload: {res}", file=sys.stderr, flush=True)
+    plan.close()
+    return res
+
+
 def main():
     a = parse()
     if a.reduce_counters:
@@ -322,39 +543,18 @@ def main():
               file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (the fused pair kernel)
-    M1 = Q // 2 + 1
-    nprod = {"fp32": 1, "bf16": 1, "bf16x3": a.products}[a.precision]
-    flops_contract = 8.0 * H * M1 * pair_delta                # conj(a) b over h, q in [0, Q/2]
-    flops_fft = 2.5 * Q * math.log2(Q) * pair_delta           # half-spectrum inverse transform
-    t_s = pairs_avg * 1e-3
-    t_mfma = flops_contract * nprod / (PEAK_BF16_TFLOPS * 1e12) if a.precision != "fp32" else \
-        flops_contract / (PEAK_FP32_MATRIX_TFLOPS * 1e12)
-    t_valu = flops_fft / (PEAK_FP32_VECTOR_TFLOPS * 1e12)
-    H8 = (H + 7) // 8 * 8
-    # operand bytes per real value (images, targets): FP32 4 B; bf16 2 B; bf16x3 with 3 products
-    # two bf16 planes (4 B); with 6 products the images' three bf16 planes (6 B) and the
-    # targets' FP32 values, split in registers (4 B)
-    bpr_a, bpr_b = {"fp32": (4, 4), "bf16": (2, 2),
-                    "bf16x3": (4, 4) if a.products == 3 else (6, 4)}[a.precision]
-    bytes_min = (cfg.n_img * bpr_a + cfg.n_tgt * cfg.T * bpr_b) * M1 * 2 * H8 + n_pairs * 12
-    t_hbm = bytes_min / (PEAK_HBM_GBS * 1e9)
-    bound = max(("mfma", t_mfma), ("alu", t_valu), ("hbm", t_hbm), key=lambda kv: kv[1])
-    if bound[0] == "alu":
-        roof = {"bound": "alu", "achieved": flops_fft / t_s / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                "unit": "TFLOP/s"}
-    elif bound[0] == "mfma":
-        pk = PEAK_BF16_TFLOPS if a.precision != "fp32" else PEAK_FP32_MATRIX_TFLOPS
-        roof = {"bound": "mfma", "achieved": flops_contract * nprod / t_s / 1e12, "peak": pk, "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": bytes_min / t_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = traffic_from_profile() if f"{a.precision} products={a.products}" == TRAFFIC_CONFIG else None
-    roof["kernel"] = f"k_pairs_fast<Q={Q},bf16={a.precision != 'fp32'},BEST>"
-    roof["kernel_ms"] = pairs_avg
-    roof["per_unit"] = {"unit": "pair-translation", "units_per_launch": pair_delta,
-                        "contraction_flops": 8 * H * M1, "fft_flops": 2.5 * Q * math.log2(Q),
-                        "products": nprod, "operand_bytes_min_total": bytes_min}
-    roof["unit_times_ms"] = {"mfma": 1e3 * t_mfma, "valu_fft": 1e3 * t_valu, "hbm": 1e3 * t_hbm}
+    roof = roofline(cfg, a.precision, a.products, pairs_avg)
+    tr = traffic_from_profile() if f"{a.precision} products={a.products}" == TRAFFIC_CONFIG else None
+    roof = {**{k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac")}, "traffic": tr,
+            **{k: v for k, v in roof.items() if k not in ("bound", "achieved", "peak", "unit", "frac")}}
+
+    extras = {}
+    if not a.no_extras:
+        del step
+        torch.cuda.empty_cache()
+        extras["plain_fp32_workload"] = plain_workload(rs, synth, torch)
+        extras["batching_workload"] = batching_workload(rs, synth, torch)
+        extras["differentiation_workload"] = differentiation_workload(rs, synth, torch)
 
     cpu = None
     accuracy = None
@@ -381,6 +581,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy_vs_oracle": accuracy,
+        "other_workloads": extras,
         "gpu": gpu_name,
         "host": platform.node(),
     }

@@ -115,8 +115,12 @@ size_t align_prepare_workspace(const radsvd_problem *prob, int n_img, int n_tgt)
  *
  * Lifetime: ws, A_polar and B_polar must stay valid and unchanged until the
  * last call enqueued with the plan has completed (the backward pass reads the
- * polar samples).  Plans are immutable; calls on different streams may share
- * one plan.  n_img, n_tgt in [1, 2^20].
+ * polar samples).  Plans are immutable once prepared, with one exception: for
+ * plans the fused pair kernel serves (Hermitian, not FP64, Q in {64, 96, 128,
+ * 192, 256, 384, 512}) align_prepare writes only the fused kernel's operand
+ * layout, and the first align_pairs_backward call writes the generic one (its
+ * space is part of ws) on its own stream.  Apart from that first backward call,
+ * calls on different streams may share one plan.  n_img, n_tgt in [1, 2^20].
  */
 radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A_polar,
                             int n_tgt, const void *B_polar, const double *U_in,
@@ -139,6 +143,8 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
  *                     A pair with a non-finite landscape value gets NaN, and
  *                     so does lse_img of its image.
  *   RADSVD_OUT_FULL : X_full [n_img][n_tgt][T][Q] complex (plan's I/O type).
+ *                     Hermitian plans (real landscapes) write imaginary parts 0;
+ *                     the values are those the BEST and LSE epilogues see.
  *
  * Pointers of the modes not selected are ignored.  All outputs are device
  * arrays, row-major.
@@ -170,7 +176,9 @@ size_t align_backward_workspace(const radsvd_plan *plan);
  * (b, t, m) is recomputed in FP64.  Images are processed in chunks whose
  * landscape transforms take at most 4 GiB of the scratch.
  * bwd_ws: device scratch of bwd_bytes >= align_backward_workspace(plan),
- * 256-byte aligned.  Errors: RADSVD_ERR_INVALID_ARG (NULL plan or lse
+ * 256-byte aligned.  The first call with a plan the fused kernel serves also
+ * writes the plan's generic operand layout on `stream` (see align_prepare);
+ * later calls on other streams must be ordered after it.  Errors: RADSVD_ERR_INVALID_ARG (NULL plan or lse
  * pointers, inv_sigma2 not finite and > 0, misaligned outputs),
  * RADSVD_ERR_WORKSPACE (scratch missing, misaligned or too small).
  */
@@ -241,6 +249,18 @@ radsvd_status align_get_U(const radsvd_plan *plan, double *U_dev, double *lambda
  * results.  Applies to later calls with this plan.  Errors:
  * RADSVD_ERR_INVALID_ARG for a NULL plan or another value. */
 radsvd_status align_set_tile(radsvd_plan *plan, int band);
+
+/* Wave layout of the fast Hermitian path (autotuner hook): the waves resident
+ * on one compute unit, 4 (one four-wave workgroup per CU) or 8 (two of them,
+ * or, for split bf16 with 6 products at Q = 384 and 512, one eight-wave
+ * workgroup); 0 = the default, which depends on Q, the precision and the rank.
+ * Both are available at Q = 128, 192 and 256; elsewhere only the default.  The
+ * arithmetic, and so every result, is the same in both layouts: the choice
+ * changes occupancy and prefetch depth, and applies to later align_pairs and
+ * align_pairs_batched calls with this plan.  Errors: RADSVD_ERR_INVALID_ARG
+ * for a NULL plan or a value other than 0, 4, 8; RADSVD_ERR_UNSUPPORTED for a
+ * layout this plan does not have (the plan is unchanged). */
+radsvd_status align_set_waves(radsvd_plan *plan, int waves);
 
 void align_plan_destroy(radsvd_plan *plan);
 

@@ -21,7 +21,7 @@ __all__ = [
     "align_prepare_workspace", "align_prepare", "align_pairs", "align_backward_workspace",
     "align_pairs_backward", "align_batched_workspace", "align_pairs_batched",
     "align_pairs_batched_noalloc", "align_get_U",
-    "align_set_tile", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
+    "align_set_tile", "align_set_waves", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
     "PRECISIONS", "RadialAlignLSE", "pairs_batched", "RADSVD_NOALLOC_MAX_JOBS",
 ]
 
@@ -86,6 +86,8 @@ def _load():
     L.align_get_U.restype = i32
     L.align_set_tile.argtypes = [vp, i32]
     L.align_set_tile.restype = i32
+    L.align_set_waves.argtypes = [vp, i32]
+    L.align_set_waves.restype = i32
     L.align_plan_destroy.argtypes = [vp]
     L.align_plan_destroy.restype = None
     L.radsvd_last_error.argtypes = []
@@ -197,6 +199,10 @@ def align_set_tile(plan, band: int):
     _check(_load().align_set_tile(plan, int(band)))
 
 
+def align_set_waves(plan, waves: int):
+    _check(_load().align_set_waves(plan, int(waves)))
+
+
 def align_plan_destroy(plan):
     if plan:
         _load().align_plan_destroy(plan)
@@ -233,6 +239,11 @@ class Plan:
         self.handle = align_prepare(self.problem, n_img, A_polar, n_tgt, B_polar, self.U_in, self.ws, stream)
         self.device = A_polar.device
         self.band = 0
+        self.waves = 0
+
+    def close(self):
+        """Release the plan handle now (the workspace goes with the object)."""
+        self.__del__()
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -274,6 +285,12 @@ class Plan:
         """Tile order of the fast path: image tiles per XCD band (0 = default)."""
         align_set_tile(self.handle, band)
         self.band = band
+
+    def set_waves(self, waves: int):
+        """Waves per CU of the fast path: 4, 8 or 0 (default); raises
+        RadsvdError (UNSUPPORTED) where this plan has no such layout."""
+        align_set_waves(self.handle, waves)
+        self.waves = waves
 
     def backward(self, inv_sigma2: float, lse_img: torch.Tensor, grad_lse_img: torch.Tensor,
                  want_B: bool = True, want_U: bool = True, stream=None):

@@ -188,6 +188,7 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
     p->nb_pad = L.nb_pad;
     p->user_U = U_in != nullptr;
     p->band = 0;
+    p->waves = 0;
     p->ws = reinterpret_cast<char *>(ws);
     p->ws_bytes = ws_bytes;
     p->A_polar = A_polar;
@@ -264,14 +265,12 @@ radsvd_status align_pairs(const radsvd_plan *p, int flags, float inv_sigma2, flo
         return fail(RADSVD_ERR_INVALID_ARG, "BEST outputs must be 4-byte aligned");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
-    const int fast_flags = flags & (RADSVD_OUT_BEST | RADSVD_OUT_LSE);
-    if (fast_flags && fast_path_supported(p, fast_flags)) {
-        e = launch_pairs_fast(p, fast_flags, inv_sigma2, best_score, best_m, best_t, lse_pair, s);
-        if (e == hipSuccess && (flags & RADSVD_OUT_FULL))
-            e = launch_pairs_generic(p, RADSVD_OUT_FULL, inv_sigma2, nullptr, nullptr, nullptr, nullptr,
-                                     X_full, s);
+    if (fast_path_supported(p, flags)) {
+        e = launch_pairs_fast(p, flags, inv_sigma2, best_score, best_m, best_t, lse_pair, X_full, s);
     } else {
-        e = launch_pairs_generic(p, flags, inv_sigma2, best_score, best_m, best_t, lse_pair, X_full, s);
+        e = ensure_generic_layout(p, s);
+        if (e == hipSuccess)
+            e = launch_pairs_generic(p, flags, inv_sigma2, best_score, best_m, best_t, lse_pair, X_full, s);
     }
     if (e == hipSuccess && (flags & RADSVD_OUT_LSE) && lse_img)
         e = launch_lse_img(p->n_img, p->n_tgt, lse_pair, lse_img, s);
@@ -305,8 +304,9 @@ radsvd_status align_pairs_backward(const radsvd_plan *p, float inv_sigma2, const
     if (bwd_bytes < need)
         return fail(RADSVD_ERR_WORKSPACE, "backward workspace too small: %zu < %zu", bwd_bytes, need);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    return dev_check(launch_backward(p, inv_sigma2, lse_img, grad_lse_img, grad_B_polar, grad_U, bwd_ws, s),
-                     "align_pairs_backward launch");
+    hipError_t e = ensure_generic_layout(p, s);
+    if (e == hipSuccess) e = launch_backward(p, inv_sigma2, lse_img, grad_lse_img, grad_B_polar, grad_U, bwd_ws, s);
+    return dev_check(e, "align_pairs_backward launch");
 }
 
 size_t align_batched_workspace(int n_jobs) {
@@ -392,6 +392,16 @@ radsvd_status align_set_tile(radsvd_plan *p, int band) {
     if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
     if (!fast_band_ok(band)) return fail(RADSVD_ERR_INVALID_ARG, "band=%d not one of 0, 1, 2, 4, 8, 16", band);
     p->band = band;
+    return RADSVD_OK;
+}
+
+radsvd_status align_set_waves(radsvd_plan *p, int waves) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    if (waves != 0 && waves != 4 && waves != 8) return fail(RADSVD_ERR_INVALID_ARG, "waves=%d not one of 0, 4, 8", waves);
+    if (!fast_waves_ok(p, waves))
+        return fail(RADSVD_ERR_UNSUPPORTED, "waves=%d: not available for this plan (Q=%d, H8=%d)", waves, p->Q, p->H8);
+    p->waves = waves;
     return RADSVD_OK;
 }
 

@@ -2,8 +2,9 @@
 //
 // Many independent alignment jobs, each with its own angle count Q, rank H,
 // translations and image/target counts, run in one launch per tile class
-// (the four-wave tile body, and the eight-wave one at Q = 384 and 512 for
-// split bf16 with six products): every job's tiles
+// (the four-wave tile body at two workgroups per CU and at one, and the
+// eight-wave one at Q = 384 and 512 for split bf16 with six products): every
+// job's tiles
 // (8 images x 16 targets, all translations) make up its work items, one tile
 // per item, or several consecutive ones for jobs whose tiles are cheap (so
 // that the per-item queue and call overhead stays small).  Items are
@@ -37,24 +38,27 @@ struct BatchJob {
 
 constexpr int kChunk = 128;   // consecutive items per XCD chunk
 
-// Two classes of items, each with its own persistent launch: class 0 runs the
-// four-wave tile body (256 threads), class 1 the eight-wave one of the plans
-// wide_plan() selects (512 threads).  Jobs are ordered by class, so a class's
-// items are the contiguous range [base, base + its item count).
+// Three classes of items, each with its own persistent launch: class 0 runs the
+// four-wave tile body at two workgroups per CU (Q = 128, 192, 256), class 1 at
+// one, class 2 the eight-wave body of the plans wide_plan() selects (512
+// threads).  A job's class follows the occupancy its plan runs at alone.  Jobs
+// are ordered by class, so a class's items are the contiguous range
+// [base, base + its item count).
+constexpr int kBatchClasses = 3;
 struct BatchHeader {
     int n_jobs;
-    int total;                  // work items of both classes
-    int base[2];                // first item of each class
-    int count[2][8];            // items in each XCD's queue, per class
-    unsigned int next[2][8];    // queue positions
+    int total;                              // work items of all classes
+    int base[kBatchClasses];                // first item of each class
+    int count[kBatchClasses][8];            // items in each XCD's queue, per class
+    unsigned int next[kBatchClasses][8];    // queue positions
 };
 
 constexpr int kTableChunk = 32;   // jobs per table-writer launch (kernel argument space)
 
 struct TableChunk {
     int first, n, n_jobs, total;
-    int base[2];
-    int count[2][8];
+    int base[kBatchClasses];
+    int count[kBatchClasses][8];
     BatchJob jobs[kTableChunk];
 };
 
@@ -67,25 +71,25 @@ typedef const __attribute__((address_space(4))) BatchJob CJob;
 // One (Q, H8) specialisation per function: each gets the register allocation
 // of the single-job kernel, not the union of all of them.
 // tiles lin0 .. lin0 + cnt - 1 of a job, in its band order
-template <int Q, int KIND, int H8>
+template <int Q, int KIND, int H8, int WPC>
 __device__ __attribute__((noinline)) void tile_h(CArgs &a, int lin0, int cnt, unsigned char *sm) {
     const int nTA = __builtin_amdgcn_readfirstlane(a.nTA), nTB = __builtin_amdgcn_readfirstlane(a.nTB);
     const int band = __builtin_amdgcn_readfirstlane(a.band);
     for (int k = 0; k < cnt; ++k) {
         int ta, tb;
         band_tile(lin0 + k, nTA, nTB, band, ta, tb);
-        if constexpr (KIND == 0) fast_tile<Q, 0, H8 / 8, 0>(a, ta, tb, sm);
-        else fast_tile<Q, KIND, H8 / 16, (H8 % 16) ? 1 : 0>(a, ta, tb, sm);
+        if constexpr (KIND == 0) fast_tile<Q, 0, H8 / 8, 0, WPC>(a, ta, tb, sm);
+        else fast_tile<Q, KIND, H8 / 16, (H8 % 16) ? 1 : 0, WPC>(a, ta, tb, sm);
     }
 }
 
-template <int Q, int KIND>
+template <int Q, int KIND, int WPC>
 __device__ __forceinline__ void tile_q(int hi, CArgs &a, int lin0, int cnt, unsigned char *sm) {
     switch (hi) {
-    case 0: tile_h<Q, KIND, 8>(a, lin0, cnt, sm); break;
-    case 1: tile_h<Q, KIND, 16>(a, lin0, cnt, sm); break;
-    case 2: tile_h<Q, KIND, 24>(a, lin0, cnt, sm); break;
-    default: tile_h<Q, KIND, 32>(a, lin0, cnt, sm); break;
+    case 0: tile_h<Q, KIND, 8, WPC>(a, lin0, cnt, sm); break;
+    case 1: tile_h<Q, KIND, 16, WPC>(a, lin0, cnt, sm); break;
+    case 2: tile_h<Q, KIND, 24, WPC>(a, lin0, cnt, sm); break;
+    default: tile_h<Q, KIND, 32, WPC>(a, lin0, cnt, sm); break;
     }
 }
 
@@ -124,18 +128,35 @@ __device__ __forceinline__ void batch_loop(BatchHeader *hdr, CJob *jobs, unsigne
     }
 }
 
+// class 1: one workgroup per CU
 template <int KIND>
 __global__ __launch_bounds__(256, 1) void k_pairs_batched(BatchHeader *hdr, const BatchJob *__restrict__ jobs_g) {
+    extern __shared__ unsigned char smem_raw[];
+    batch_loop<1>(hdr, (CJob *)jobs_g, smem_raw, [&](CJob &J, int lin0, int cnt) {
+        CArgs &a = J.a;
+        const int qi = J.qi, hr = J.hi;
+        switch (qi) {
+        case 0: tile_q<128, KIND, 1>(hr, a, lin0, cnt, smem_raw); break;
+        case 1: tile_q<192, KIND, 1>(hr, a, lin0, cnt, smem_raw); break;
+        case 2: tile_q<256, KIND, 1>(hr, a, lin0, cnt, smem_raw); break;
+        case 3: tile_q<384, KIND, 1>(hr, a, lin0, cnt, smem_raw); break;
+        default: tile_q<512, KIND, 1>(hr, a, lin0, cnt, smem_raw); break;
+        }
+    });
+}
+
+// class 0: two workgroups per CU (the host puts only Q = 128, 192, 256 here)
+template <int KIND>
+__global__ __launch_bounds__(256, 2) void k_pairs_batched2(BatchHeader *hdr, const BatchJob *__restrict__ jobs_g) {
     extern __shared__ unsigned char smem_raw[];
     batch_loop<0>(hdr, (CJob *)jobs_g, smem_raw, [&](CJob &J, int lin0, int cnt) {
         CArgs &a = J.a;
         const int qi = J.qi, hr = J.hi;
         switch (qi) {
-        case 0: tile_q<128, KIND>(hr, a, lin0, cnt, smem_raw); break;
-        case 1: tile_q<192, KIND>(hr, a, lin0, cnt, smem_raw); break;
-        case 2: tile_q<256, KIND>(hr, a, lin0, cnt, smem_raw); break;
-        case 3: tile_q<384, KIND>(hr, a, lin0, cnt, smem_raw); break;
-        default: tile_q<512, KIND>(hr, a, lin0, cnt, smem_raw); break;
+        case 0: tile_q<128, KIND, 2>(hr, a, lin0, cnt, smem_raw); break;
+        case 1: tile_q<192, KIND, 2>(hr, a, lin0, cnt, smem_raw); break;
+        case 2: tile_q<256, KIND, 2>(hr, a, lin0, cnt, smem_raw); break;
+        default: break;
         }
     });
 }
@@ -153,6 +174,19 @@ hipError_t launch_batched_kind(BatchHeader *hdr, const BatchJob *jobs, int grid,
     return hipGetLastError();
 }
 
+template <int KIND>
+hipError_t launch_batched2_kind(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s) {
+    static size_t attr_bytes = 0;
+    if (shmem > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_pairs_batched2<KIND>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+        attr_bytes = shmem;
+    }
+    hipLaunchKernelGGL(k_pairs_batched2<KIND>, dim3(grid), dim3(256), shmem, s, hdr, jobs);
+    return hipGetLastError();
+}
+
 // the eight-wave items (Q = 384, 512; split bf16 with 6 products): batched_wide.hip
 hipError_t launch_batched_wide(BatchHeader *hdr, const BatchJob *jobs, int grid, hipStream_t s);
 hipError_t launch_batched_fp32(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
@@ -160,6 +194,12 @@ hipError_t launch_batched_bf16(BatchHeader *hdr, const BatchJob *jobs, int grid,
 hipError_t launch_batched_bf16x3(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
 hipError_t launch_batched_bf16x3_6(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem,
                                    hipStream_t s);
+// class 0 (pairs_fast_occ_*.hip)
+hipError_t launch_batched2_fp32(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
+hipError_t launch_batched2_bf16(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
+hipError_t launch_batched2_bf16x3(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s);
+hipError_t launch_batched2_bf16x3_6(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem,
+                                    hipStream_t s);
 
 }  // namespace fastk
 }  // namespace radsvd

@@ -50,10 +50,10 @@ namespace fastk {
 __global__ void k_batch_table(TableChunk c, BatchHeader *hdr, BatchJob *jobs) {
     const int i = threadIdx.x;
     if (i < c.n) jobs[c.first + i] = c.jobs[i];
-    if (c.first == 0 && i < 16) {
+    if (c.first == 0 && i < 8 * kBatchClasses) {
         hdr->count[i >> 3][i & 7] = c.count[i >> 3][i & 7];
         hdr->next[i >> 3][i & 7] = 0u;
-        if (i < 2) hdr->base[i] = c.base[i];
+        if (i < kBatchClasses) hdr->base[i] = c.base[i];
         if (i == 0) {
             hdr->n_jobs = c.n_jobs;
             hdr->total = c.total;
@@ -98,22 +98,27 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
                                 void *ws, hipStream_t s) {
     using namespace fastk;
     const int kind = plan_kind(plans[0]);
-    // item order: class (four-wave tiles, then eight-wave), then decreasing cost
-    // per item (translations x angles x work per angle)
+    // item order: class (four-wave tiles at two workgroups per CU, at one, then
+    // eight-wave), then decreasing cost per item (translations x angles x work
+    // per angle)
     std::vector<int> order(n_jobs), cls(n_jobs);
     std::vector<double> cost(n_jobs);
-    int max_q0 = 0;
+    size_t lds[2] = {0, 0};   // LDS per workgroup of classes 0 and 1
     for (int i = 0; i < n_jobs; ++i) {
         const radsvd_plan *p = plans[i];
         order[i] = i;
-        cls[i] = wide_plan(p->prec, p->products, p->herm, p->Q) ? 1 : 0;
+        cls[i] = wide_plan(p->prec, p->products, p->herm, p->Q) ? 2 : (fast_plan_wpc(p) == 2 ? 0 : 1);
         cost[i] = (double)p->T * p->Q * (std::log2((double)p->Q) + 0.25 * p->H8);
-        if (!cls[i]) max_q0 = std::max(max_q0, p->Q);
+        if (cls[i] < 2) {
+            // staging buffers (one at Q = 256 with two workgroups per CU) + parked Z values
+            const int nstage = (cls[i] == 0 && p->Q == 256) ? 1 : 2;
+            lds[cls[i]] = std::max(lds[cls[i]], (size_t)(nstage * 16 * 128 + (p->Q / 8) * 256) * sizeof(cx<float>));
+        }
     }
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return cls[x] != cls[y] ? cls[x] < cls[y] : cost[x] > cost[y]; });
     std::vector<BatchJob> jobs(n_jobs);
-    int total = 0, n_cls[2] = {0, 0};
+    int total = 0, n_cls[kBatchClasses] = {0, 0, 0};
     for (int k = 0; k < n_jobs; ++k) {
         const int i = order[k];
         const radsvd_plan *p = plans[i];
@@ -144,12 +149,12 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
         J.item0 = total;
         const int items = (a.nTA * a.nTB + J.group - 1) / J.group;
         total += items;
-        n_cls[cls[i]] += items;   // class-0 jobs come first: class 1 starts at n_cls[0]
+        n_cls[cls[i]] += items;   // jobs are in class order: class c starts after the items of classes < c
     }
-    const int base[2] = {0, n_cls[0]};
+    const int base[kBatchClasses] = {0, n_cls[0], n_cls[0] + n_cls[1]};
     // items of each XCD queue of a class: chunks x, x + 8, x + 16, ... of kChunk items
-    int count[2][8] = {};
-    for (int q = 0; q < 2; ++q)
+    int count[kBatchClasses][8] = {};
+    for (int q = 0; q < kBatchClasses; ++q)
         for (int c = 0; (long)c * kChunk < n_cls[q]; ++c) count[q][c & 7] += std::min(kChunk, n_cls[q] - c * kChunk);
     char *w = reinterpret_cast<char *>(ws);
     BatchHeader *hdr = reinterpret_cast<BatchHeader *>(w);
@@ -161,7 +166,7 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
         c.n = std::min(kTableChunk, n_jobs - first);
         c.n_jobs = n_jobs;
         c.total = total;
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < kBatchClasses; ++q) {
             c.base[q] = base[q];
             for (int x = 0; x < 8; ++x) c.count[q][x] = count[q][x];
         }
@@ -170,18 +175,28 @@ hipError_t launch_pairs_batched(const radsvd_plan *const *plans, int n_jobs, con
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (n_cls[0] > 0) {
-        const int grid = std::max(1, std::min(n_cls[0], device_cus()));
-        const size_t shmem = (size_t)(2 * 16 * 128 + (max_q0 / 8) * 256) * sizeof(cx<float>);
+    const int cus = device_cus();
+    if (n_cls[0] > 0) {   // two workgroups per CU
+        const int grid = std::max(1, std::min(n_cls[0], 2 * cus));
         switch (kind) {
-        case 0: e = launch_batched_fp32(hdr, djobs, grid, shmem, s); break;
-        case 1: e = launch_batched_bf16(hdr, djobs, grid, shmem, s); break;
-        case 2: e = launch_batched_bf16x3(hdr, djobs, grid, shmem, s); break;
-        default: e = launch_batched_bf16x3_6(hdr, djobs, grid, shmem, s); break;
+        case 0: e = launch_batched2_fp32(hdr, djobs, grid, lds[0], s); break;
+        case 1: e = launch_batched2_bf16(hdr, djobs, grid, lds[0], s); break;
+        case 2: e = launch_batched2_bf16x3(hdr, djobs, grid, lds[0], s); break;
+        default: e = launch_batched2_bf16x3_6(hdr, djobs, grid, lds[0], s); break;
         }
         if (e != hipSuccess) return e;
     }
-    if (n_cls[1] > 0) e = launch_batched_wide(hdr, djobs, std::max(1, std::min(n_cls[1], device_cus())), s);
+    if (n_cls[1] > 0) {
+        const int grid = std::max(1, std::min(n_cls[1], cus));
+        switch (kind) {
+        case 0: e = launch_batched_fp32(hdr, djobs, grid, lds[1], s); break;
+        case 1: e = launch_batched_bf16(hdr, djobs, grid, lds[1], s); break;
+        case 2: e = launch_batched_bf16x3(hdr, djobs, grid, lds[1], s); break;
+        default: e = launch_batched_bf16x3_6(hdr, djobs, grid, lds[1], s); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    if (n_cls[2] > 0) e = launch_batched_wide(hdr, djobs, std::max(1, std::min(n_cls[2], cus)), s);
     return e;
 }
 

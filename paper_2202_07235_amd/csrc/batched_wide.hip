@@ -1,4 +1,4 @@
-// Persistent launch of the eight-wave items of a batch (class 1: Q = 384 and
+// Persistent launch of the eight-wave items of a batch (class 2: Q = 384 and
 // 512, split bf16 with six products), one tile body per (Q, H8).
 #include "batched.h"
 #include "pairs_wide.h"
@@ -30,7 +30,7 @@ __device__ __forceinline__ void wide_tile_q(int hi, CArgs &a, int lin0, int cnt,
 __global__ __launch_bounds__(512, 1) void k_pairs_batched_wide(BatchHeader *hdr, const BatchJob *__restrict__ jobs_g) {
     extern __shared__ unsigned char smem_raw[];
     int tables_q = 0;   // angle count whose twiddle table is in LDS
-    batch_loop<1>(hdr, (CJob *)jobs_g, smem_raw, [&](CJob &J, int lin0, int cnt) {
+    batch_loop<2>(hdr, (CJob *)jobs_g, smem_raw, [&](CJob &J, int lin0, int cnt) {
         CArgs &a = J.a;
         const int hr = J.hi;
         if (J.qi == 3) {

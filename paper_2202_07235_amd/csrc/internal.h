@@ -102,6 +102,7 @@ struct radsvd_plan {
     int na_pad, nb_pad;   // counts padded to the fast tile sizes
     int user_U;
     int band;    // image tiles per XCD band of the fast path's tile order (0 = default)
+    int waves;   // waves per CU of the fast path (0 = default; 4 or 8, align_set_waves)
     void *stream_hint;
     char *ws;
     size_t ws_bytes;
@@ -117,6 +118,10 @@ struct radsvd_plan {
     double *gram_part;                // [nsplit][K][K]
     void *eig_log;                    // Jacobi rotation log
     int gram_nsplit;
+    // generic operands: written by align_prepare where the fused path cannot
+    // serve the plan, else on first need (the backward pass) by
+    // ensure_generic_layout; g_ready says whether they hold the plan's values
+    mutable int g_ready;
     void *Ag;                         // [n_img][Qc][H] cx<R>        generic operands
     void *Bg;                         // [n_tgt][T][Qc][H] cx<R>
     void *Af;                         // fast operands (tile-major planes)
@@ -143,9 +148,15 @@ hipError_t launch_pairs_generic(const radsvd_plan *p, int flags, float inv_s2, f
 // pairs_fast.hip
 bool fast_path_supported(const radsvd_plan *p, int flags);
 bool fast_band_ok(int band);
+// writes the generic operand layout if it is not written yet (on stream s)
+hipError_t ensure_generic_layout(const radsvd_plan *p, hipStream_t s);
+// workgroups per CU the four-wave fused kernel runs this plan at (1 or 2)
+int fast_plan_wpc(const radsvd_plan *p);
+// whether align_set_waves may give this plan `waves` waves per CU (0, 4, 8)
+bool fast_waves_ok(const radsvd_plan *p, int waves);
 constexpr int kDefaultBand = 8;
 hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, float *best_score,
-                             int32_t *best_m, int32_t *best_t, float *lse_pair, hipStream_t s);
+                             int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full, hipStream_t s);
 // lse.hip
 hipError_t launch_lse_img(int n_img, int n_tgt, const float *lse_pair, float *lse_img, hipStream_t s);
 // backward.hip

@@ -228,6 +228,7 @@ struct Args {
     float *best_score;
     int32_t *best_m, *best_t;
     float *lse_pair;
+    cx<float> *X_full;         // FULL output [n_img][n_tgt][T][Q] (real landscape, imaginary parts 0)
 };
 
 // tile index of workgroup `wg`: workgroups are dealt round-robin to the 8
@@ -329,17 +330,42 @@ __device__ __forceinline__ void split3_frag4(const u32x4 &r, u32x2 (&pl)[3]) {
     }
 }
 
-// Staging buffers for the MFMA results: two (round parity) unless a single one
-// lets a second workgroup fit in the LDS (Q = 256: 16 + 64 KB).
-template <int Q, int KIND, int NF, int HF>
-constexpr int fast_nstage() {
-    return (Q == 256 && frag_regs<KIND, NF, HF>() <= 24) ? 1 : 2;
+// Workgroups per CU by default (see k_pairs_fast): two where the LDS holds two
+// and one job's operand registers leave room for a second wave per SIMD
+// without spills (fr: frag_regs of the instantiation).
+__host__ __device__ constexpr int fast_wpc_rule(int Q, int fr) {
+    return (Q <= 128 || (Q <= 192 && fr <= 30) || (Q == 256 && fr <= 24)) ? 2 : 1;
 }
-// Workgroups per CU (see k_pairs_fast).
 template <int Q, int KIND, int NF, int HF>
 constexpr int fast_wg_per_cu() {
-    return (Q <= 128 || (Q <= 192 && frag_regs<KIND, NF, HF>() <= 30) || fast_nstage<Q, KIND, NF, HF>() == 1) ? 2 : 1;
+    return fast_wpc_rule(Q, frag_regs<KIND, NF, HF>());
 }
+// Staging buffers for the MFMA results: two (round parity) unless a single one
+// lets a second workgroup fit in the LDS (Q = 256: 16 + 64 KB).
+template <int Q, int WPC>
+constexpr int fast_nstage() {
+    static_assert(WPC == 1 || (WPC == 2 && Q <= 256), "two workgroups per CU fit the LDS up to Q = 256");
+    return (Q == 256 && WPC == 2) ? 1 : 2;
+}
+// LDS bytes of one workgroup
+template <int Q, int WPC>
+constexpr size_t fast_lds_bytes() {
+    return (size_t)(fast_nstage<Q, WPC>() * 16 * 128 + (Q / 8) * 256) * sizeof(cx<float>);
+}
+// the rule at run time (kind: 0 FP32, 1 BF16, 2 split bf16 with 3 products, 3 with 6)
+inline int fast_default_wpc(int kind, int Q, int H8) {
+    const int NF = kind == 0 ? H8 / 8 : H8 / 16, HF = kind == 0 ? 0 : ((H8 % 16) ? 1 : 0);
+    int fr;
+    switch (kind) {
+    case 0: fr = 2 * Prec<0>::NPL * (4 * NF + 2 * HF); break;
+    case 1: fr = 2 * Prec<1>::NPL * (4 * NF + 2 * HF); break;
+    case 2: fr = 2 * Prec<2>::NPL * (4 * NF + 2 * HF); break;
+    default: fr = Prec<3>::NPL * (4 * NF + 2 * HF) + 8 * NF + 4 * HF; break;
+    }
+    return fast_wpc_rule(Q, fr);
+}
+// angle counts with both occupancies compiled (the other one for the tuner)
+__host__ __device__ constexpr bool fast_alt_q(int Q) { return Q == 128 || Q == 192 || Q == 256; }
 
 // One tile (ta, tb) for all translations.  Q angles; KIND contraction
 // precision; NF, HF operand chunks per plane (FP32: NF = H8 / 8 chunks of 16
@@ -347,7 +373,9 @@ constexpr int fast_wg_per_cu() {
 // of 8).  Called by all 256 threads of a workgroup; smem_raw holds
 // (2 * 16 * 128 + Q / 8 * 256) complex FP32 values (160 KB at Q = 512).
 // Begins and ends at a barrier.
-template <int Q, int KIND, int NF, int HF, class ArgsT>
+// FULL: the landscape is also written out (RADSVD_OUT_FULL; a separate
+// instantiation, so that the BEST/LSE kernels keep their register allocation).
+template <int Q, int KIND, int NF, int HF, int WPC, bool FULL = false, class ArgsT>
 __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_in, unsigned char *smem_raw) {
     constexpr int M = Q / 2;
     constexpr int L = M / 2;          // Z values per lane
@@ -358,7 +386,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     static_assert(M % 16 == 0, "Q must be a multiple of 32");
 
     // staging of MFMA results, double-buffered by round parity: [NSTAGE][16][128]
-    constexpr int NSTAGE = fast_nstage<Q, KIND, NF, HF>();
+    constexpr int NSTAGE = fast_nstage<Q, WPC>();
     cx<float> *stage = reinterpret_cast<cx<float> *>(smem_raw);
     cx<float> *upper = stage + NSTAGE * 16 * 128;                 // [LH][256]
 
@@ -384,6 +412,7 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     const char *Af = uniform_ptr(args.Af), *Bf = uniform_ptr(args.Bf);
     const bool do_best = flags & RADSVD_OUT_BEST;
     const bool do_lse = flags & RADSVD_OUT_LSE;
+    const bool do_full = FULL && (flags & RADSVD_OUT_FULL);
 
     // ---- MFMA operands: fragment-ordered blocks, one per (tile, q) ----
     // Lane l reads bytes [16 l, 16 l + 16) of each full chunk and [8 l, 8 l + 8)
@@ -625,8 +654,11 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
     // its hi terms), so the wave does not wait for the MFMA chain; the prefetch
     // depth leaves room for the split's registers
     constexpr bool PIPE_PUT = F32B;
-    constexpr int D = PIPE_PUT ? (FRAG_REGS <= 24 ? 4 : (FRAG_REGS <= 32 ? 3 : 2))
-                               : (FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 48 ? 3 : 2));
+    // (two workgroups per CU where the default is one: 256 registers per lane,
+    // so at most two jobs ahead)
+    constexpr int D0 = PIPE_PUT ? (FRAG_REGS <= 24 ? 4 : (FRAG_REGS <= 32 ? 3 : 2))
+                                : (FRAG_REGS <= 24 ? 5 : (FRAG_REGS <= 48 ? 3 : 2));
+    constexpr int D = (WPC == 2 && fast_wg_per_cu<Q, KIND, NF, HF>() == 1 && D0 > 2) ? 2 : D0;
     constexpr int NJ = 4 * NRP;
     FragT fr[D + 1];
 
@@ -753,6 +785,22 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
             // when the whole landscape of this lane pair is (barring overflow)
             if constexpr (par == 0)
                 nanX = !__builtin_isfinite(x[ct_pos(LH, 0)].re) || !__builtin_isfinite(x[ct_pos(LH, 0)].im);
+            if constexpr (FULL) {
+                if (do_full && ta * 8 + pa < args.n_img && tb * 16 + pb < args.n_tgt) {
+                    // this lane's part of its pair's landscape row: X[2 n] = Re z[n], X[2 n + 1] = Im z[n]
+                    cx<float> *xo = args.X_full +
+                                    (((size_t)(ta * 8 + pa) * args.n_tgt + (tb * 16 + pb)) * (size_t)nT + t) * Q + e * (Q / 4);
+                    sfor<0, LH / 2>([&](auto FF) {
+                        constexpr int m0 = 4 * decltype(FF)::value + 2 * par;
+                        const cx<float> zl = x[ct_pos(LH, decltype(FF)::value)];
+                        const cx<float> zh = x[ct_pos(LH, decltype(FF)::value + LH / 2)];
+                        xo[m0] = cx<float>{zl.re, 0.f};
+                        xo[m0 + 1] = cx<float>{zl.im, 0.f};
+                        xo[m0 + M] = cx<float>{zh.re, 0.f};
+                        xo[m0 + M + 1] = cx<float>{zh.im, 0.f};
+                    });
+                }
+            }
             if (do_best) {
                 sfor<0, LH / 2>([&](auto FF) {
                     constexpr int f = decltype(FF)::value;
@@ -849,63 +897,90 @@ __device__ __forceinline__ void fast_tile(const ArgsT &args, int ta_in, int tb_i
 // ms).  With more operand registers per job (Q = 192 beyond 30, Q = 256 beyond
 // 24) the spills cost more than the second wave gains (Q = 192, H = 32: 78.3
 // -> 87.8 ms; Q = 256, H = 24, 6 products: 88.5 -> 99.0 ms); beyond Q = 256
-// the LDS holds one workgroup.
+// the LDS holds one workgroup.  That rule is the default; at Q = 128, 192 and
+// 256 the other occupancy is compiled as well (two workgroups per CU where the
+// rule says one then prefetch at most two jobs ahead), and a plan may ask for
+// either (align_set_waves), which is what the tile tuner times.
 
-template <int Q, int KIND, int NF, int HF>
-__global__ __launch_bounds__(256, (fast_wg_per_cu<Q, KIND, NF, HF>())) void k_pairs_fast(Args args) {
+// WPC workgroups per CU
+template <int Q, int KIND, int NF, int HF, int WPC, bool FULL>
+__global__ __launch_bounds__(256, WPC) void k_pairs_fast(Args args) {
     extern __shared__ unsigned char smem_raw[];
     int ta, tb;
     tile_of(blockIdx.x, gridDim.x, args.nTA, args.nTB, args.band, ta, tb);
-    fast_tile<Q, KIND, NF, HF>(args, ta, tb, smem_raw);
+    fast_tile<Q, KIND, NF, HF, WPC, FULL>(args, ta, tb, smem_raw);
 }
 
-template <int Q, int KIND, int NF, int HF>
+template <int Q, int KIND, int NF, int HF, int WPC, bool FULL>
 static hipError_t launch_v(const Args &a, int nwg, hipStream_t s) {
-    constexpr int LH = Q / 8;
-    const size_t shmem = (size_t)(fast_nstage<Q, KIND, NF, HF>() * 16 * 128 + LH * 256) * sizeof(cx<float>);
+    constexpr size_t shmem = fast_lds_bytes<Q, WPC>();
     static bool attr_done = false;
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_pairs_fast<Q, KIND, NF, HF>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_pairs_fast<Q, KIND, NF, HF, WPC, FULL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    hipLaunchKernelGGL((k_pairs_fast<Q, KIND, NF, HF>), dim3(nwg), dim3(256), shmem, s, a);
+    hipLaunchKernelGGL((k_pairs_fast<Q, KIND, NF, HF, WPC, FULL>), dim3(nwg), dim3(256), shmem, s, a);
     return hipGetLastError();
 }
 
+// ALT: the occupancy other than the default (only where fast_alt_q)
+template <int Q, int KIND, int NF, int HF, bool ALT, bool FULL>
+static hipError_t launch_o(const Args &a, int nwg, hipStream_t s) {
+    constexpr int d = fast_wg_per_cu<Q, KIND, NF, HF>();
+    if constexpr (ALT) {
+        if constexpr (fast_alt_q(Q)) return launch_v<Q, KIND, NF, HF, 3 - d, FULL>(a, nwg, s);
+        else return hipErrorNotSupported;
+    } else {
+        return launch_v<Q, KIND, NF, HF, d, FULL>(a, nwg, s);
+    }
+}
+
 // operand chunk geometry of rank H8 (8, 16, 24 or 32)
-template <int Q, int KIND>
+template <int Q, int KIND, bool ALT, bool FULL>
 static hipError_t launch_h(const Args &a, int nwg, int H8, hipStream_t s) {
     if constexpr (KIND == 0) {
         switch (H8) {
-        case 8: return launch_v<Q, 0, 1, 0>(a, nwg, s);
-        case 16: return launch_v<Q, 0, 2, 0>(a, nwg, s);
-        case 24: return launch_v<Q, 0, 3, 0>(a, nwg, s);
-        case 32: return launch_v<Q, 0, 4, 0>(a, nwg, s);
+        case 8: return launch_o<Q, 0, 1, 0, ALT, FULL>(a, nwg, s);
+        case 16: return launch_o<Q, 0, 2, 0, ALT, FULL>(a, nwg, s);
+        case 24: return launch_o<Q, 0, 3, 0, ALT, FULL>(a, nwg, s);
+        case 32: return launch_o<Q, 0, 4, 0, ALT, FULL>(a, nwg, s);
         default: return hipErrorNotSupported;
         }
     } else {
         switch (H8) {
-        case 8: return launch_v<Q, KIND, 0, 1>(a, nwg, s);
-        case 16: return launch_v<Q, KIND, 1, 0>(a, nwg, s);
-        case 24: return launch_v<Q, KIND, 1, 1>(a, nwg, s);
-        case 32: return launch_v<Q, KIND, 2, 0>(a, nwg, s);
+        case 8: return launch_o<Q, KIND, 0, 1, ALT, FULL>(a, nwg, s);
+        case 16: return launch_o<Q, KIND, 1, 0, ALT, FULL>(a, nwg, s);
+        case 24: return launch_o<Q, KIND, 1, 1, ALT, FULL>(a, nwg, s);
+        case 32: return launch_o<Q, KIND, 2, 0, ALT, FULL>(a, nwg, s);
         default: return hipErrorNotSupported;
         }
     }
 }
 
-template <int KIND>
+// FULL: the instantiations that also write the landscape (default occupancy)
+template <int KIND, bool FULL = false>
 static hipError_t launch_kind(const Args &a, int Q, int nwg, int H8, hipStream_t s) {
     switch (Q) {
-    case 64: return launch_h<64, KIND>(a, nwg, H8, s);
-    case 96: return launch_h<96, KIND>(a, nwg, H8, s);
-    case 128: return launch_h<128, KIND>(a, nwg, H8, s);
-    case 192: return launch_h<192, KIND>(a, nwg, H8, s);
-    case 256: return launch_h<256, KIND>(a, nwg, H8, s);
-    case 384: return launch_h<384, KIND>(a, nwg, H8, s);
-    case 512: return launch_h<512, KIND>(a, nwg, H8, s);
+    case 64: return launch_h<64, KIND, false, FULL>(a, nwg, H8, s);
+    case 96: return launch_h<96, KIND, false, FULL>(a, nwg, H8, s);
+    case 128: return launch_h<128, KIND, false, FULL>(a, nwg, H8, s);
+    case 192: return launch_h<192, KIND, false, FULL>(a, nwg, H8, s);
+    case 256: return launch_h<256, KIND, false, FULL>(a, nwg, H8, s);
+    case 384: return launch_h<384, KIND, false, FULL>(a, nwg, H8, s);
+    case 512: return launch_h<512, KIND, false, FULL>(a, nwg, H8, s);
+    default: return hipErrorNotSupported;
+    }
+}
+
+// the other occupancy (Q = 128, 192, 256)
+template <int KIND>
+static hipError_t launch_kind_alt(const Args &a, int Q, int nwg, int H8, hipStream_t s) {
+    switch (Q) {
+    case 128: return launch_h<128, KIND, true, false>(a, nwg, H8, s);
+    case 192: return launch_h<192, KIND, true, false>(a, nwg, H8, s);
+    case 256: return launch_h<256, KIND, true, false>(a, nwg, H8, s);
     default: return hipErrorNotSupported;
     }
 }
@@ -915,6 +990,16 @@ hipError_t launch_fast_fp32(const Args &a, int Q, int nwg, int H8, hipStream_t s
 hipError_t launch_fast_bf16(const Args &a, int Q, int nwg, int H8, hipStream_t s);
 hipError_t launch_fast_bf16x3(const Args &a, int Q, int nwg, int H8, hipStream_t s);
 hipError_t launch_fast_bf16x3_6(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+// with the FULL output (pairs_fast_full_*.hip)
+hipError_t launch_fast_full_fp32(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_full_bf16(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_full_bf16x3(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_full_bf16x3_6(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+// the occupancy other than the default, Q = 128, 192, 256 (pairs_fast_occ_*.hip)
+hipError_t launch_fast_alt_fp32(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_alt_bf16(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_alt_bf16x3(const Args &a, int Q, int nwg, int H8, hipStream_t s);
+hipError_t launch_fast_alt_bf16x3_6(const Args &a, int Q, int nwg, int H8, hipStream_t s);
 // eight-wave kernel of the plans wide_plan() selects (pairs_wide.hip)
 hipError_t launch_wide(const Args &a, int Q, int nwg, int H8, hipStream_t s);
 

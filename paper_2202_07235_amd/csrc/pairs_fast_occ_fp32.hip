@@ -1,0 +1,17 @@
+// The fused Hermitian pair kernel at the occupancy other than its default
+// (Q = 128, 192, 256), single-job and batched: FP32 operands.
+#include "batched.h"
+
+namespace radsvd {
+namespace fastk {
+
+hipError_t launch_fast_alt_fp32(const Args &a, int Q, int nwg, int H8, hipStream_t s) {
+    return launch_kind_alt<0>(a, Q, nwg, H8, s);
+}
+
+hipError_t launch_batched2_fp32(BatchHeader *hdr, const BatchJob *jobs, int grid, size_t shmem, hipStream_t s) {
+    return launch_batched2_kind<0>(hdr, jobs, grid, shmem, s);
+}
+
+}  // namespace fastk
+}  // namespace radsvd

@@ -420,6 +420,7 @@ __device__ __forceinline__ void wide_tile(const ArgsT &args, int ta_in, int tb_i
         });
         constexpr int F4 = LO / 2;   // butterflies per lane of a cross-lane step in one pass
         const int moff = LO * u + L4 * e;   // z index offset of this lane
+        const bool do_full = flags & RADSVD_OUT_FULL;
         float bv[2][2], br[2][2];    // [pass][z index below / above M/2]: best of max(re, im), its re
         int bi[2][2];                //                                 landscape index of that pair
         float lse_mx = -INFINITY, lse_sum = 0.f;
@@ -460,6 +461,20 @@ __device__ __forceinline__ void wide_tile(const ArgsT &args, int ta_in, int tb_i
             if constexpr (par == 0) {
                 const cx<float> z0 = x[ct_pos(LO, 0)];
                 bad = (!__builtin_isfinite(z0.re) || !__builtin_isfinite(z0.im)) ? 1 : 0;
+            }
+            if (do_full && ta * 8 + w < args.n_img && tb * 16 + p < args.n_tgt) {
+                // this lane's part of its pair's landscape row: X[2 n] = Re z[n], X[2 n + 1] = Im z[n]
+                cx<float> *xo = args.X_full +
+                                (((size_t)(ta * 8 + w) * args.n_tgt + (tb * 16 + p)) * (size_t)nT + t) * Q + 2 * moff;
+                sfor<0, F4>([&](auto FF) {
+                    constexpr int m0 = 4 * decltype(FF)::value + 2 * par;
+                    const cx<float> za = x[ct_pos(LO, decltype(FF)::value)];
+                    const cx<float> zb = x[ct_pos(LO, decltype(FF)::value + F4)];
+                    xo[m0] = cx<float>{za.re, 0.f};
+                    xo[m0 + 1] = cx<float>{za.im, 0.f};
+                    xo[m0 + M] = cx<float>{zb.re, 0.f};
+                    xo[m0 + M + 1] = cx<float>{zb.im, 0.f};
+                });
             }
             if (do_best) {
                 // a (re at 2 m, im at 2 m + 1) pair replaces the winner only when

@@ -392,7 +392,7 @@ __device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_t
 // CU.  Workgroups loop over rings; each XCD runs one contiguous range of rings,
 // so the T translations of an item share its samples in one L2.
 template <int NG, bool PHASE, bool TWO>
-__global__ __launch_bounds__(256) void k_rings_mfma(
+__global__ __launch_bounds__(256, 2) void k_rings_mfma(
     const cx<float> *__restrict__ X, int n_real, int T, const cx<float> *__restrict__ phase,
     const float *__restrict__ Ueta, int K, int Q, int H, int Qc, cx<float> *__restrict__ G,
     void *__restrict__ F, int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
@@ -622,6 +622,7 @@ static hipError_t rings_side(radsvd_plan *p, const void *X, int n_real, int n_pa
 hipError_t launch_principal_rings(radsvd_plan *p, hipStream_t s) {
     hipError_t e;
     if (p->prec == RADSVD_FP64) {
+        p->g_ready = 1;
         e = rings_side<double, 16>(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, nullptr,
                                    kFastTA, 1, s);
         if (e != hipSuccess) return e;
@@ -642,9 +643,29 @@ hipError_t launch_principal_rings(radsvd_plan *p, hipStream_t s) {
                                p->Bf_bytes / 16);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    e = rings_side_mfma(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, p->Af, kFastTA, 1, s);
+    // Plans the fused kernel serves for every output (BEST, LSE, FULL) get only
+    // the fast layout here; their generic one is written when the backward pass
+    // first needs it.
+    const bool generic = !fast_path_supported(p, RADSVD_OUT_BEST | RADSVD_OUT_LSE | RADSVD_OUT_FULL);
+    p->g_ready = generic ? 1 : 0;
+    e = rings_side_mfma(p, p->A_polar, p->n_img, p->na_pad, 1, false, generic ? p->Ag : nullptr, p->Af, kFastTA,
+                        1, s);
     if (e != hipSuccess) return e;
-    return rings_side_mfma(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, p->Bf, kFastTB, 0, s);
+    return rings_side_mfma(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, generic ? p->Bg : nullptr, p->Bf,
+                           kFastTB, 0, s);
+}
+
+hipError_t ensure_generic_layout(const radsvd_plan *cp, hipStream_t s) {
+    if (cp->g_ready) return hipSuccess;
+    radsvd_plan *p = const_cast<radsvd_plan *>(cp);   // reads only; the workspace is the plan's
+    hipError_t e = rings_side_mfma(p, p->A_polar, p->n_img, p->na_pad, 1, false, p->Ag, nullptr, kFastTA, 1, s);
+    if (e == hipSuccess)
+        e = rings_side_mfma(p, p->B_polar, p->n_tgt, p->nb_pad, p->T, true, p->Bg, nullptr, kFastTB, 0, s);
+    if (e != hipSuccess) return e;
+    // under stream capture the writes exist only in the graph: write again next time
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusNone) cp->g_ready = 1;
+    return hipSuccess;
 }
 
 }  // namespace radsvd

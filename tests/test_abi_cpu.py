@@ -86,6 +86,8 @@ def test_pairs_and_backward_argument_errors():
     assert lib.align_pairs_backward(None, 1.0, None, None, None, None, None, 0, None) == 1
     assert lib.align_get_U(None, None, None, None) == 1
     assert lib.align_set_tile(None, 0) == 1
+    assert lib.align_set_waves(None, 0) == 1
+    assert lib.align_set_waves(None, 8) == 1
     assert lib.align_batched_workspace(0) == 0
     assert lib.align_pairs_batched(None, 1, None, None, 0, None) == 1
     assert lib.align_pairs_batched_noalloc(None, 1, None, None) == 1

@@ -6,9 +6,15 @@ the tile-order autotuner.
   FP32, bf16x3 (3 and 6 products) and BF16.
 * Parity of the batched outputs with the FP64 oracle on sampled pairs.
 * Graph capture: replays with eager work in between, every replay checked.
+* Wave layouts (align_set_waves): 4 and 8 waves per CU give bitwise the
+  outputs of the default, alone and in a batch that mixes layouts (the
+  batched launch runs each class of items at its own occupancy); layouts a
+  plan does not have are refused and leave it unchanged.
 * The batching workload (64 jobs: N in {64..256}, K = N/2, Q = 2N, N_A in
   [128, 2048], N_B in [64, 1024], T in {1, 9, 25}, H in [8, 32]) with
-  autotuned bands: equal to one launch per job, and timed against it.
+  autotuned layouts and bands: equal to one launch per job, and timed
+  against it; the whole step (prepare of every job + the batched launch)
+  captured in a HIP graph, every replay equal to the eager step.
 """
 import numpy as np
 import pytest
@@ -18,6 +24,7 @@ import oracle
 import paper_2202_07235_amd as rs
 import synth
 from paper_2202_07235_amd import autotune
+from paper_2202_07235_amd.batch import BatchStep
 from tests._parity import argmax_agrees, host_inputs
 
 pytestmark = pytest.mark.gpu
@@ -124,8 +131,8 @@ def test_batching_workload_autotuned_vs_one_launch_per_job():
         P.A = P.B = None
         plans.append(rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision="bf16x3", products=6))
     torch.cuda.synchronize()
-    bands = autotune.tune_jobs(plans)
-    print("autotuned bands:", dict(zip(*np.unique(bands, return_counts=True))))
+    autotune.tune_jobs(plans)
+    print("autotuned:", autotune.describe(plans))
     ref = [p.pairs("best") for p in plans]
     outs = rs.pairs_batched(plans)
     torch.cuda.synchronize()
@@ -154,3 +161,86 @@ def test_batching_workload_autotuned_vs_one_launch_per_job():
         times[name] = e0.elapsed_time(e1) / 3
     pairs = sum(c.n_img * c.n_tgt for c in cfgs)
     print({k: f"{v:.2f} ms ({pairs / v * 1e3:.3e} pairs/s)" for k, v in times.items()})
+
+
+#              Q    K   H  n_img n_tgt T
+LAYOUT_JOBS = [(128, 32, 24, 30, 40, 4),
+               (192, 48, 32, 17, 33, 9),
+               (256, 64, 16, 24, 20, 9),
+               (256, 64, 24, 9, 35, 4)]
+
+
+@pytest.mark.parametrize("precision,products", [("fp32", 3), ("bf16x3", 6), ("bf16", 3), ("bf16x3", 3)])
+def test_wave_layouts_give_the_same_outputs(precision, products):
+    jobs = _plans(precision, products, jobs=LAYOUT_JOBS, seed=1100)
+    plans = [p for _, _, p in jobs]
+    ref = [p.pairs("best+lse", inv_sigma2=0.3) for p in plans]
+    for w in (4, 8):
+        for p, r in zip(plans, ref):
+            p.set_waves(w)
+            o = p.pairs("best+lse", inv_sigma2=0.3)
+            for k in r:
+                assert torch.equal(r[k], o[k]), (w, p.Q, p.H, k)
+    # a batch mixing both layouts: equal to the per-job outputs
+    for i, p in enumerate(plans):
+        p.set_waves((4, 8)[i % 2])
+    outs = rs.pairs_batched(plans)
+    torch.cuda.synchronize()
+    for r, o in zip(ref, outs):
+        for k in ("best_score", "best_m", "best_t"):
+            assert torch.equal(r[k], o[k])
+
+
+def test_wave_layouts_refused_where_absent():
+    jobs = _plans("bf16x3", 6, jobs=[(512, 128, 24, 9, 17, 1), (64, 16, 8, 9, 17, 1)], seed=1200)
+    (_, _, wide), (_, _, small) = jobs
+    ref = wide.pairs("best")
+    with pytest.raises(rs.RadsvdError, match="UNSUPPORTED"):
+        wide.set_waves(4)           # operands in the eight-wave layout
+    wide.set_waves(8)
+    assert all(torch.equal(ref[k], v) for k, v in wide.pairs("best").items())
+    with pytest.raises(rs.RadsvdError, match="UNSUPPORTED"):
+        small.set_waves(4)          # Q = 64: only the default (two workgroups per CU)
+    with pytest.raises(rs.RadsvdError, match="INVALID_ARG"):
+        small.set_waves(6)
+    small.set_waves(8)
+    p384 = _plans("fp32", 3, jobs=[(384, 96, 16, 9, 17, 1)], seed=1300)[0][2]
+    with pytest.raises(rs.RadsvdError, match="UNSUPPORTED"):
+        p384.set_waves(8)           # Q = 384 four-wave: the LDS holds one workgroup
+    p384.set_waves(4)
+
+
+def test_batching_workload_step_replays_from_a_graph():
+    cfgs = synth.batch_configs(64, seed=4000)
+    plans = []
+    for i, cfg in enumerate(cfgs):
+        P = synth.make_problem(cfg, seed=4000 + i, device="cuda")
+        A = P.A.to(torch.complex64).contiguous()
+        B = P.B.to(torch.complex64).contiguous()
+        P.A = P.B = None
+        plans.append(rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision="bf16x3", products=6))
+        plans[-1].set_waves((0, 4, 8)[i % 3] if cfg.Q in (128, 192, 256) else 0)
+    ref = [p.pairs("best") for p in plans]
+    bs = BatchStep(plans)
+    bs.run()
+    torch.cuda.synchronize()
+    for i, (r, o) in enumerate(zip(ref, bs.outs)):
+        assert all(torch.equal(r[k], o[k]) for k in r), f"eager step, job {i}"
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bs.run()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in bs.outs:   # eager work between replays
+            o["best_score"].fill_(float("nan"))
+            o["best_m"].fill_(-7)
+        plans[rep].pairs("best")
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (r, o) in enumerate(zip(ref, bs.outs)):
+            assert all(torch.equal(r[k], o[k]) for k in r), f"replay {rep}, job {i}"
+    del g
+    bs.close()

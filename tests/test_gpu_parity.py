@@ -67,8 +67,9 @@ def test_tiny_fp64_full_landscape_and_U():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "bf16"])
-def test_generic_hermitian_paths(precision):
-    # ragged counts (not multiples of the tiles), 9 translations, radix-3 Q
+def test_hermitian_paths_full_output(precision):
+    # ragged counts (not multiples of the tiles), 9 translations, radix-3 Q; the
+    # fused kernel writes FULL beside BEST and LSE
     cfg = synth.config("fp32", N=48, K=24, Q=96, n_img=5, n_tgt=7, T=9, H=10)
     P, plan, A_h, B_h, Xor, Uh, lam, o, s2 = _run(cfg, 1002, precision)
     X = o["X"].cpu().numpy()
@@ -82,6 +83,29 @@ def test_generic_hermitian_paths(precision):
     assert np.all(np.abs(sc - ref) <= 2 * e * np.abs(Xor).max())
     lp, li = oracle.lse(Xor, s2)
     assert np.allclose(o["lse_pair"].cpu().numpy(), lp, rtol=0, atol=max(1e-4, 8 * e * 4))
+
+
+@pytest.mark.parametrize("Q,precision,products", [(512, "bf16x3", 6), (384, "bf16x3", 6), (256, "fp32", 3),
+                                                  (128, "bf16x3", 3)])
+def test_fused_full_output_is_the_landscape_best_and_lse_see(Q, precision, products):
+    na, nb, T = 11, 19, 4
+    cfg = synth.config("fp32", N=Q // 2, K=Q // 4, Q=Q, n_img=na, n_tgt=nb, T=T, H=20, n_blobs=8, snr=0.5)
+    P, plan, A_h, B_h, Xor, Uh, lam, o, s2 = _run(cfg, 1010, precision, products=products)
+    X = o["X"].cpu().numpy()
+    assert (X.imag == 0).all()
+    scale = np.abs(Xor).reshape(na, nb, -1).max(axis=-1)
+    err = (np.abs(X - Xor).reshape(na, nb, -1).max(axis=-1) / scale).max()
+    print(f"Q={Q} {precision}: FULL rel err (per-pair scale) {err:.3e}")
+    assert err <= TOL[precision]
+    # BEST is the first maximum of the FULL values, LSE their log-sum-exp
+    Xr = X.real.reshape(na, nb, -1)
+    idx = o["best_t"].cpu().numpy() * Q + o["best_m"].cpu().numpy()
+    assert np.array_equal(Xr.argmax(axis=-1), idx)
+    assert np.array_equal(Xr.max(axis=-1), o["best_score"].cpu().numpy())
+    x64 = s2 * Xr.astype(np.float64)
+    mx = x64.max(axis=-1, keepdims=True)
+    lse = (mx[..., 0] + np.log(np.exp(x64 - mx).sum(axis=-1)))
+    assert np.allclose(o["lse_pair"].cpu().numpy(), lse, rtol=0, atol=2e-5 * np.abs(lse).max())
 
 
 def test_non_hermitian_fp32_full():

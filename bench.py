@@ -54,6 +54,14 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB streaming kernel (x -> -x) whose HBM counters calibrate FETCH_SIZE / "
                          "WRITE_SIZE of the pair kernel")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="summarise rocprofv3 --pmc runs (any counters) of the pair kernel at the precision "
+                         "workload into the counter profile text and exit (needs --kernel-ms)")
+    ap.add_argument("--summarize-kernel-stats", metavar="CSV",
+                    help="summarise a rocprofv3 --kernel-trace --stats kernel_stats.csv of bench.py runs "
+                         "(library kernels only) and exit")
+    ap.add_argument("--kernel-ms", type=float, default=None,
+                    help="the pair kernel's duration (from a kernel-trace run), for the derived rates")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "`bench.py --copy-probe` into the traffic profile text and exit")
@@ -136,6 +144,76 @@ def reduce_counters(fetch_dir, write_dir):
         f"copy kernel (1 GiB read + 1 GiB write) WRITE_SIZE: {wc:.6g} KiB -> scale {wf:.4f}",
         f"traffic_bytes_per_launch: {traffic:.6g}",
     ]
+    return "\n".join(lines)
+
+
+def summarize_counters(dirs, kernel_ms):
+    """Per-dispatch averages of every counter of the pair kernel in the given
+    rocprofv3 --pmc output folders, with the rates they imply on MI355X (256
+    CUs x 4 SIMDs at 2.4 GHz; one wave64 VALU instruction issues over 4
+    cycles)."""
+    import collections
+    acc = collections.defaultdict(list)
+    for d in dirs:
+        for r in _counter_rows(d):
+            if TRAFFIC_KERNEL in r.get("Kernel_Name", ""):
+                acc[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    if not acc:
+        raise SystemExit(f"no {TRAFFIC_KERNEL} dispatches in {dirs}")
+    v = {k: sum(x) / len(x) for k, x in acc.items()}
+    n_tiles = (4096 // 8) * (4096 // 16)
+    waves, T = n_tiles * 8, 9
+    simd_cycles = 1024 * 2.4e9 * kernel_ms * 1e-3
+    lines = [f"# SQ/TCC counters of {TRAFFIC_KERNEL}, precision workload (N=256 K=128 Q=512 N_A=N_B=4096 "
+             f"T=9 H=24), bf16x3 with 6 products",
+             "# kernel_source_sha256_16: hash of the pair kernel sources with comments removed "
+             "(bench.kernel_source_hash)",
+             f"config: {TRAFFIC_CONFIG}",
+             f"kernel_source_sha256_16: {kernel_source_hash()}",
+             f"kernel_ms (kernel-trace run): {kernel_ms:.2f}",
+             f"waves per dispatch: {waves} ({n_tiles} workgroups x 8), translations: {T}",
+             "", "counter (average per dispatch)"]
+    for k in sorted(v):
+        lines.append(f"  {k:28s} {v[k]:.6g}  ({len(acc[k])} dispatches)")
+    lines += ["", "derived"]
+
+    def have(*ks):
+        return all(k in v for k in ks)
+    if have("SQ_VALU_MFMA_BUSY_CYCLES"):
+        lines.append(f"  MFMA busy, fraction of SIMD cycles: {v['SQ_VALU_MFMA_BUSY_CYCLES'] / simd_cycles:.3f}")
+    if have("SQ_INSTS_VALU"):
+        lines.append(f"  VALU issue, fraction of SIMD cycles (4 cycles each): {4 * v['SQ_INSTS_VALU'] / simd_cycles:.3f}")
+        lines.append(f"  VALU instructions per wave and translation: {v['SQ_INSTS_VALU'] / waves / T:.0f}")
+    if have("SQ_INSTS_MFMA"):
+        lines.append(f"  MFMA instructions per wave and translation: {v['SQ_INSTS_MFMA'] / waves / T:.0f}")
+    if have("SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES"):
+        lines.append(f"  SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES: {v['SQ_ACTIVE_INST_VALU'] / v['SQ_WAVE_CYCLES']:.3f}")
+    if have("SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"):
+        lines.append(f"  SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES: {v['SQ_WAIT_INST_ANY'] / v['SQ_WAVE_CYCLES']:.3f}")
+    if have("SQ_LDS_BANK_CONFLICT", "SQ_ACTIVE_INST_LDS"):
+        lines.append(f"  SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS: "
+                     f"{v['SQ_LDS_BANK_CONFLICT'] / v['SQ_ACTIVE_INST_LDS']:.3f}")
+    if have("TCC_HIT_sum", "TCC_MISS_sum"):
+        lines.append(f"  L2 hit rate: {v['TCC_HIT_sum'] / (v['TCC_HIT_sum'] + v['TCC_MISS_sum']):.3f}")
+    if have("TA_BUSY_avr", "GRBM_GUI_ACTIVE"):
+        lines.append(f"  TA busy (TA_BUSY_avr / (GRBM_GUI_ACTIVE / 8 XCDs)): "
+                     f"{v['TA_BUSY_avr'] / (v['GRBM_GUI_ACTIVE'] / 8):.3f}")
+    return "\n".join(lines)
+
+
+def summarize_kernel_stats(path):
+    """Library kernels of a rocprofv3 kernel_stats.csv: calls, average, min and
+    max duration (ms), sorted by total time."""
+    import csv
+    with open(path) as fh:
+        rows = [r for r in csv.DictReader(fh) if "radsvd::" in r["Name"]]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"{'kernel':72s} {'calls':>5s} {'avg ms':>9s} {'min ms':>9s} {'max ms':>9s}"]
+    for r in rows:
+        name = r["Name"].replace("void ", "").replace("radsvd::", "")
+        name = name[:name.index("(")] if "(" in name else name
+        lines.append(f"{name[:72]:72s} {int(r['Calls']):5d} {float(r['AverageNs']) / 1e6:9.3f} "
+                     f"{float(r['MinNs']) / 1e6:9.3f} {float(r['MaxNs']) / 1e6:9.3f}")
     return "\n".join(lines)
 
 
@@ -473,6 +551,14 @@ def main():
     a = parse()
     if a.reduce_counters:
         print(reduce_counters(*a.reduce_counters))
+        return 0
+    if a.summarize_kernel_stats:
+        print(summarize_kernel_stats(a.summarize_kernel_stats))
+        return 0
+    if a.summarize_counters:
+        if a.kernel_ms is None:
+            raise SystemExit("--summarize-counters needs --kernel-ms")
+        print(summarize_counters(a.summarize_counters, a.kernel_ms))
         return 0
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the library has no multi-GPU "

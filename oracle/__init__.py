@@ -14,6 +14,11 @@ alignment of images and volumes", arXiv 2202.07235):
                           weights sqrt(w_r) of the kernel's defining integral;
                           evaluated in psi-space by the 1-D Plancherel
                           identity, no FFT.
+* ``kernel_C_translated`` -- the kernel of the translation- and rotation-averaged
+                          objective of the discussion (section 5), for an
+                          isotropic Gaussian prior on the translations: the
+                          closed form with the factors E+ and E- (modified
+                          Bessel functions of order -1/2 and +1/2).
 * ``principal_vectors`` -- U = eigenvectors of C by descending eigenvalue
                           (section 3.3: the maximisers of the Rayleigh quotient).
 * ``principal_rings``  -- [u_h^T Ahat](psi_j) = sum_r U[r,h] eta_r Ahat(k_r, psi_j),
@@ -148,6 +153,53 @@ def kernel_C(B, w, Q: int) -> np.ndarray:
     s = B.sum(axis=2)                                 # [nb][K]
     G0 = np.conj(s).T @ s                             # sum_b conj(sum_j B_r)(sum_j B_r')
     C = (G - G0 / Q).real * np.outer(e, e) / nb
+    return 0.5 * (C + C.T)
+
+
+def translation_factors(k, sigma_delta: float):
+    """The factors of the translation-averaged kernel (section 5, the closed
+    form for an isotropic Gaussian translation prior of standard deviation
+    sigma_delta), as the paper writes them:
+      E+(k_r, k_r') = exp(-sigma^2 (k_r^2 + k_r'^2) / 2) * exp(k_r k_r' sigma^2),
+      E-(k_r)       = kt sqrt(pi/2) exp(-kt^2) (I_{-1/2}(kt^2) - I_{+1/2}(kt^2)),  kt = k_r sigma / 2,
+    with I_nu the modified Bessel function of the first kind.  The two
+    exponentials of E+ are taken as one (no overflow for large k sigma), and
+    exp(-x) I_nu(x) is scipy's exponentially scaled ``ive``.  E-(0) = 1 (the
+    limit kt -> 0).  Returns (E+ [K][K], E- [K])."""
+    import scipy.special
+    k = np.asarray(k, dtype=np.float64)
+    s2 = float(sigma_delta) ** 2
+    Ep = np.exp(-0.5 * s2 * (k[:, None] ** 2 + k[None, :] ** 2) + s2 * np.outer(k, k))
+    kt = k * float(sigma_delta) / 2.0
+    x = kt * kt
+    Em = np.ones_like(k)
+    nz = kt > 0
+    Em[nz] = kt[nz] * math.sqrt(math.pi / 2.0) * (scipy.special.ive(-0.5, x[nz]) - scipy.special.ive(0.5, x[nz]))
+    return Ep, Em
+
+
+def kernel_C_translated(B, w, Q: int, k, sigma_delta: float) -> np.ndarray:
+    """Target-averaged kernel of the translation- and rotation-averaged
+    objective (section 5): for each target, the sum over pairs of poses
+    (rotation on the grid, translation from an isotropic Gaussian of standard
+    deviation sigma_delta) of sum_j |[u^T T_d R_g B](psi_j) - [u^T T_d' R_g' B](psi_j)|^2
+    is quadratic in u.  Its kernel has the closed form of the paper's
+    equation for the translated template cost, with the sums over the
+    volume's spherical-harmonic coefficients read, for a set of image
+    targets, as each target's sums over the angular frequencies q:
+      C = eta_r eta_r' Re[ E+(k_r, k_r') sum_q conj(bq_r) bq_r'  -  E-(k_r) E-(k_r') conj(bq0_r) bq0_r' ] / N_B,
+    bq the unitary angular DFT of the ring (bq0 its q = 0 term).  By the 1-D
+    Plancherel identity the q-sum is the psi-sum and bq0 = (ring sum) / sqrt(Q),
+    as in kernel_C.  sigma_delta = 0 gives kernel_C (E+ = E- = 1)."""
+    B = _c128(B)
+    nb, K, _ = B.shape
+    e = eta(w, Q)
+    Ep, Em = translation_factors(k, sigma_delta)
+    Bm = B.transpose(1, 0, 2).reshape(K, nb * Q)
+    G = np.conj(Bm) @ Bm.T                            # sum_{b,j} conj(B_r) B_r'
+    s = B.sum(axis=2)                                 # [nb][K]
+    G0 = np.conj(s).T @ s                             # sum_b conj(sum_j B_r)(sum_j B_r')
+    C = (Ep * G - np.outer(Em, Em) * G0 / Q).real * np.outer(e, e) / nb
     return 0.5 * (C + C.T)
 
 

@@ -221,6 +221,75 @@ def test_kernel_C_is_the_rotation_averaged_objective():
         assert abs(tot - 2 * Q * Q * (u @ C @ u)) <= 1e-11 * tot
 
 
+def _gauss_hermite_2d(sigma, n):
+    """Nodes and weights (summing to 1) of an n x n Gauss-Hermite rule for
+    the isotropic Gaussian of standard deviation sigma on R^2."""
+    x, wt = np.polynomial.hermite.hermgauss(n)
+    d1 = math.sqrt(2.0) * sigma * x
+    w1 = wt / math.sqrt(math.pi)
+    D = np.array([(a, b) for a in d1 for b in d1])
+    W = np.outer(w1, w1).reshape(-1)
+    return D, W
+
+
+def test_translated_kernel_is_the_translation_and_rotation_averaged_objective():
+    """Section 5: the sum over pairs of poses (grid rotations g, g'; Gaussian
+    translations d, d') of sum_j |[u^T T_d R_g B](psi_j) - [u^T T_d' R_g' B](psi_j)|^2
+    is 2 Q^2 u^T C u.  Brute force: every pose pair, translations by a 10 x 10
+    Gauss-Hermite rule (exact to ~1e-15 here: k sigma <= 1)."""
+    cfg = synth.config("fp32", N=32, K=8, Q=16, n_img=1, n_tgt=1, T=1)
+    P = synth.make_problem(cfg, seed=9)
+    B = P.B.numpy()[0]
+    Q, K = cfg.Q, cfg.K
+    sigma = 1.0 / float(np.max(P.k))
+    e = oracle.eta(P.w, Q)
+    D, W = _gauss_hermite_2d(sigma, 10)
+    psi = 2 * math.pi * np.arange(Q) / Q
+    C = oracle.kernel_C_translated(P.B, P.w, Q, P.k, sigma)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        u = rng.standard_normal(K)
+        u /= np.linalg.norm(u)
+        # y[(m, i)][j] = sum_r u_r eta_r exp(-i k_r d_i.n(psi_j)) B[r, j - m]
+        ys, ws = [], []
+        for m in range(Q):
+            Bm = np.roll(B, m, axis=-1)
+            for d, wd in zip(D, W):
+                ph = np.exp(-1j * P.k[:, None] * (d[0] * np.cos(psi) + d[1] * np.sin(psi))[None, :])
+                ys.append((u * e) @ (ph * Bm))
+                ws.append(wd)
+        Y, Wv = np.array(ys), np.array(ws)
+        tot = 0.0
+        for i in range(0, len(Y), 200):   # every pair of poses, weighted
+            dif = Y[i:i + 200, None, :] - Y[None, :, :]
+            tot += float(np.einsum("a,b,abj->", Wv[i:i + 200], Wv, np.abs(dif) ** 2))
+        assert abs(tot - 2 * Q * Q * (u @ C @ u)) <= 1e-11 * tot, (tot, 2 * Q * Q * (u @ C @ u))
+
+
+def test_translated_kernel_factors_and_limits():
+    k = np.linspace(0.05, 40.0, 97)
+    for sigma in (0.0, 0.013, 0.1, 0.7):
+        Ep, Em = oracle.translation_factors(k, sigma)
+        # I_{+-1/2} are elementary: E- reduces to exp(-sigma^2 k^2 / 2), E+ to exp(-sigma^2 (k - k')^2 / 2)
+        ref = np.exp(-0.5 * (sigma * k) ** 2)
+        big = ref > 1e-6
+        assert np.allclose(Em[big], ref[big], rtol=1e-9, atol=0)
+        assert np.all(np.abs(Em - ref) <= 1e-12)
+        assert np.allclose(Ep, np.exp(-0.5 * sigma ** 2 * (k[:, None] - k[None, :]) ** 2), rtol=1e-12, atol=0)
+    cfg = synth.config("fp32", N=32, K=16, Q=64, n_img=1, n_tgt=9, T=1)
+    P = synth.make_problem(cfg, seed=12)
+    C0 = oracle.kernel_C(P.B, P.w, cfg.Q)
+    assert _rel(oracle.kernel_C_translated(P.B, P.w, cfg.Q, P.k, 0.0), C0) <= 1e-14
+    for sigma in (0.02, 0.2):
+        C = oracle.kernel_C_translated(P.B, P.w, cfg.Q, P.k, sigma)
+        assert np.allclose(C, C.T, rtol=0, atol=0)
+        # a variance over poses: positive semidefinite
+        assert np.linalg.eigvalsh(C).min() >= -1e-12 * np.abs(C).max()
+        # a grid rotation of every target leaves it unchanged
+        Cr = oracle.kernel_C_translated(np.roll(P.B.numpy(), 5, axis=-1), P.w, cfg.Q, P.k, sigma)
+        assert _rel(Cr, C) <= 1e-13
+
+
 def test_principal_vectors_are_sorted_orthonormal_eigenvectors():
     cfg = synth.config("fp32", N=32, K=16, Q=64, n_img=1, n_tgt=12, T=1)
     P = synth.make_problem(cfg, seed=10)

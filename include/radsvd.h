@@ -85,6 +85,10 @@ typedef struct {
                             /*    then uses only the frequencies q in [0, Q/2]          */
     int products;           /* RADSVD_BF16X3 only: 3 (hi*hi + hi*mid + mid*hi) or 6     */
                             /* (+ mid*mid + hi*lo + lo*hi); ignored otherwise            */
+    double sigma_delta;     /* >= 0: standard deviation of an isotropic Gaussian prior on */
+                            /* the images' translations, same unit as delta.  0: kernel C */
+                            /* of section 3.4 (rotations only); > 0: the translation- and */
+                            /* rotation-averaged kernel of section 5 (see align_prepare)  */
 } radsvd_problem;
 
 typedef struct radsvd_plan radsvd_plan;   /* opaque host-side metadata */
@@ -96,7 +100,14 @@ size_t align_prepare_workspace(const radsvd_problem *prob, int n_img, int n_tgt)
 /*
  * Precompute (paper section 3.5, operation-count items 1-3): the kernel C
  * of the targets at delta = 0 (section 3.4, q = 0 excluded, ring weights
- * sqrt(w_r w_r')), its FP64 eigendecomposition (descending eigenvalues, each
+ * sqrt(w_r w_r')), or with sigma_delta > 0 the kernel of the objective
+ * averaged over grid rotations and Gaussian translations (section 5):
+ *   C = eta_r eta_r' Re[ E+(k_r,k_r') sum_q conj(bq_r) bq_r'
+ *                        - E-(k_r) E-(k_r') conj(bq0_r) bq0_r' ] / N_B,
+ *   E+ = exp(-sigma^2 (k_r - k_r')^2 / 2), E- = exp(-sigma^2 k_r^2 / 2)
+ * (the paper's E- with Bessel I of order -1/2 and +1/2 is this exponential),
+ * bq the unitary angular spectrum of a target ring and bq0 its q = 0 term,
+ * its FP64 eigendecomposition (descending eigenvalues, each
  * eigenvector's largest-magnitude entry positive), and the principal rings of
  * every image and of every target at every translation, transformed to
  * angular frequency.

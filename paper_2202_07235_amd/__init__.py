@@ -46,7 +46,7 @@ class _Problem(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("Q", ctypes.c_int), ("H", ctypes.c_int), ("T", ctypes.c_int),
                 ("k", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double)),
                 ("delta", ctypes.POINTER(ctypes.c_double)), ("prec", ctypes.c_int),
-                ("hermitian", ctypes.c_int), ("products", ctypes.c_int)]
+                ("hermitian", ctypes.c_int), ("products", ctypes.c_int), ("sigma_delta", ctypes.c_double)]
 
 
 class _JobOut(ctypes.Structure):
@@ -119,7 +119,7 @@ def _stream(stream):
     return ctypes.c_void_p(int(stream))
 
 
-def make_problem(K, Q, H, T, k, w, delta, prec, hermitian, products=3):
+def make_problem(K, Q, H, T, k, w, delta, prec, hermitian, products=3, sigma_delta=0.0):
     """Build the C problem struct; the returned tuple keeps the host arrays
     alive (pass element 0 to the ABI)."""
     k = np.ascontiguousarray(k, dtype=np.float64)
@@ -128,7 +128,7 @@ def make_problem(K, Q, H, T, k, w, delta, prec, hermitian, products=3):
     dp = ctypes.POINTER(ctypes.c_double)
     pr = _Problem(K, Q, H, T, k.ctypes.data_as(dp), w.ctypes.data_as(dp),
                   d.ctypes.data_as(dp) if d is not None else ctypes.cast(None, dp),
-                  int(prec), int(hermitian), int(products))
+                  int(prec), int(hermitian), int(products), float(sigma_delta))
     return pr, (k, w, d)
 
 
@@ -217,7 +217,7 @@ class Plan:
 
     def __init__(self, A_polar: torch.Tensor, B_polar: torch.Tensor, k, w, delta, H: int,
                  precision: str = "fp32", hermitian: bool = True, products: int = 3,
-                 U: torch.Tensor | None = None, stream=None):
+                 U: torch.Tensor | None = None, stream=None, sigma_delta: float = 0.0):
         prec = PRECISIONS[precision]
         want = torch.complex128 if prec == FP64 else torch.complex64
         for name, X in (("A_polar", A_polar), ("B_polar", B_polar)):
@@ -231,7 +231,8 @@ class Plan:
         self.n_img, self.n_tgt = n_img, n_tgt
         self.precision, self.prec, self.hermitian = precision, prec, hermitian
         self.products = products
-        self.problem, self._keep = make_problem(K, Q, H, T, k, w, delta, prec, hermitian, products)
+        self.sigma_delta = float(sigma_delta)
+        self.problem, self._keep = make_problem(K, Q, H, T, k, w, delta, prec, hermitian, products, sigma_delta)
         nbytes = align_prepare_workspace(self.problem, n_img, n_tgt)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=A_polar.device)
         self.A, self.B = A_polar, B_polar

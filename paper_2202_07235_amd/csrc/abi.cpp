@@ -57,11 +57,13 @@ radsvd_status validate_problem(const radsvd_problem *pr) {
         return fail(RADSVD_ERR_INVALID_ARG, "hermitian must be 0 or 1");
     if (pr->prec == RADSVD_BF16X3 && pr->products != 3 && pr->products != 6)
         return fail(RADSVD_ERR_INVALID_ARG, "products=%d must be 3 or 6 for BF16X3", pr->products);
+    if (!(pr->sigma_delta >= 0.0) || !isfinite(pr->sigma_delta))
+        return fail(RADSVD_ERR_INVALID_ARG, "sigma_delta must be finite and >= 0");
     return RADSVD_OK;
 }
 
 struct Layout {
-    size_t off_k, off_eta, off_delta, off_phase, off_C, off_U, off_lam, off_ueta, off_rsum, off_gram,
+    size_t off_k, off_eta, off_delta, off_phase, off_C, off_U, off_lam, off_ueta, off_rsum, off_gram, off_g0,
         off_Ag, off_Bg, off_Af, off_Bf, off_log, total;
     size_t Af_bytes, Bf_bytes;
     int nsplit, H8, nplanes_a, nplanes_b, ffmt_a, ffmt_b, na_pad, nb_pad, Qc;
@@ -114,6 +116,7 @@ Layout make_layout(const radsvd_problem *pr, int n_img, int n_tgt) {
     L.off_rsum = take((size_t)n_tgt * K * 16);
     (void)KP;
     L.off_gram = take((size_t)ns * K * K * 8);
+    L.off_g0 = take((size_t)K * K * 8);
     L.off_log = take(eig_log_bytes(K));
     L.off_Ag = take((size_t)n_img * L.Qc * H * CX);
     L.off_Bg = take((size_t)n_tgt * T * L.Qc * H * CX);
@@ -175,6 +178,7 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
     p->prec = prob->prec;
     p->herm = prob->hermitian;
     p->products = prob->prec == RADSVD_BF16X3 ? prob->products : 0;
+    p->sigma_delta = prob->sigma_delta;
     p->n_img = n_img;
     p->n_tgt = n_tgt;
     p->M = prob->Q / 2;
@@ -204,6 +208,7 @@ radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A
     p->Ueta = w + L.off_ueta;
     p->ringsum = reinterpret_cast<double *>(w + L.off_rsum);
     p->gram_part = reinterpret_cast<double *>(w + L.off_gram);
+    p->ring_gram = reinterpret_cast<double *>(w + L.off_g0);
     p->gram_nsplit = L.nsplit;
     p->eig_log = w + L.off_log;
     p->Ag = w + L.off_Ag;

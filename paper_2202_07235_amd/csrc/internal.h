@@ -116,6 +116,8 @@ struct radsvd_plan {
     void *Ueta;                       // [K][H] R : U[r][h] * eta_r
     double *ringsum;                  // [n_tgt][K] complex FP64
     double *gram_part;                // [nsplit][K][K]
+    double *ring_gram;                // [K][K] sum_b Re conj(S_b,r) S_b,r' (translation-averaged kernel only)
+    double sigma_delta;               // Gaussian translation prior of kernel C (0: none)
     void *eig_log;                    // Jacobi rotation log
     int gram_nsplit;
     // generic operands: written by align_prepare where the fused path cannot

@@ -10,6 +10,15 @@
 // dropped (principal vectors are unchanged).  Everything accumulates in FP64.
 // The Gram sum is split over target ranges; partial Gram matrices are reduced
 // in a fixed order (deterministic).
+//
+// With a Gaussian translation prior (sigma > 0, the translation- and
+// rotation-averaged objective of section 5) the two terms are weighted
+// apart: E+(k_r, k_r') = exp(-sigma^2 (k_r - k_r')^2 / 2) on the full sum and
+// E-(k_r) E-(k_r'), E-(k) = exp(-sigma^2 k^2 / 2), on the q = 0 term.  (The
+// paper writes E- with the modified Bessel functions of order -1/2 and +1/2;
+// both are elementary, sqrt(2 / (pi x)) cosh x and sinh x, and the product
+// reduces to this exponential.)  Written as E+ times the q != 0 Gram plus
+// (E+ - E- E-) times the q = 0 Gram, so sigma = 0 keeps the plain kernel.
 #include "common.h"
 #include "internal.h"
 
@@ -176,8 +185,34 @@ __global__ __launch_bounds__(256) void k_gram_partial(const cx<R> *__restrict__ 
     }
 }
 
-__global__ void k_C_finalize(const double *__restrict__ P, int nsplit, int n_tgt, int K,
-                             const double *__restrict__ eta, double *__restrict__ C) {
+// G0[r][c] = sum_b Re conj(S[b][r]) S[b][c] (the targets' q = 0 terms times Q),
+// for r <= c; 16 x 16 entries per workgroup, 64 targets per LDS chunk
+__global__ __launch_bounds__(256) void k_ring_gram(const double *__restrict__ S, int n_tgt, int K,
+                                                   double *__restrict__ G0) {
+    __shared__ double sr[64][16][2], sc[64][16][2];
+    const int r0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+    if (r0 > c0 + 15) return;   // below the diagonal (uniform per workgroup)
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    double acc = 0.0;
+    for (int b0 = 0; b0 < n_tgt; b0 += 64) {
+        for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+            const int bb = i >> 4, j = i & 15, b = b0 + bb;
+            const bool okr = b < n_tgt && r0 + j < K, okc = b < n_tgt && c0 + j < K;
+            sr[bb][j][0] = okr ? S[2 * ((size_t)b * K + r0 + j)] : 0.0;
+            sr[bb][j][1] = okr ? S[2 * ((size_t)b * K + r0 + j) + 1] : 0.0;
+            sc[bb][j][0] = okc ? S[2 * ((size_t)b * K + c0 + j)] : 0.0;
+            sc[bb][j][1] = okc ? S[2 * ((size_t)b * K + c0 + j) + 1] : 0.0;
+        }
+        __syncthreads();
+        for (int bb = 0; bb < 64; ++bb) acc += sr[bb][tr][0] * sc[bb][tc][0] + sr[bb][tr][1] * sc[bb][tc][1];
+        __syncthreads();
+    }
+    if (r0 + tr < K && c0 + tc < K) G0[(size_t)(r0 + tr) * K + c0 + tc] = acc;
+}
+
+__global__ void k_C_finalize(const double *__restrict__ P, int nsplit, int n_tgt, int K, int Q,
+                             const double *__restrict__ eta, const double *__restrict__ kr, double sigma,
+                             const double *__restrict__ G0, double *__restrict__ C) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= K * K) return;
     const int r = i / K, c = i - r * K;
@@ -185,6 +220,12 @@ __global__ void k_C_finalize(const double *__restrict__ P, int nsplit, int n_tgt
     const int a = r < c ? r : c, bb = r < c ? c : r;
     double g = 0.0;
     for (int s = 0; s < nsplit; ++s) g += P[((size_t)s * K + a) * K + bb];
+    if (sigma > 0.0) {
+        const double s2 = sigma * sigma, d = kr[a] - kr[bb];
+        const double ep = exp(-0.5 * s2 * d * d);
+        const double em2 = exp(-0.5 * s2 * (kr[a] * kr[a] + kr[bb] * kr[bb]));
+        g = ep * g + (ep - em2) * G0[(size_t)a * K + bb] / (double)Q;
+    }
     C[i] = eta[a] * eta[bb] * g / (double)n_tgt;
 }
 
@@ -207,8 +248,11 @@ hipError_t launch_kernel_C(radsvd_plan *p, hipStream_t s) {
         hipLaunchKernelGGL(k_gram_partial<float>, dim3(nreg, nsplit), dim3(256), 0, s, B,
                            p->ringsum, nb, K, Q, bps, p->gram_part);
     }
-    hipLaunchKernelGGL(k_C_finalize, dim3((K * K + 255) / 256), dim3(256), 0, s, p->gram_part, nsplit, nb, K,
-                       p->d_eta, p->C);
+    if (p->sigma_delta > 0.0)
+        hipLaunchKernelGGL(k_ring_gram, dim3((K + 15) / 16, (K + 15) / 16), dim3(256), 0, s, p->ringsum, nb, K,
+                           p->ring_gram);
+    hipLaunchKernelGGL(k_C_finalize, dim3((K * K + 255) / 256), dim3(256), 0, s, p->gram_part, nsplit, nb, K, Q,
+                       p->d_eta, p->d_k, p->sigma_delta, p->ring_gram, p->C);
     return hipGetLastError();
 }
 

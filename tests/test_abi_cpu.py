@@ -34,7 +34,7 @@ def _prob(**kw):
     w = kw.get("w", np.ones(K))
     delta = kw.get("delta", np.zeros((T, 2)))
     return rs.make_problem(K, Q, H, T, k, w, delta, kw.get("prec", rs.FP32), kw.get("herm", 1),
-                           kw.get("products", 3))
+                           kw.get("products", 3), kw.get("sigma_delta", 0.0))
 
 
 @pytest.mark.parametrize("bad", [
@@ -42,6 +42,7 @@ def _prob(**kw):
     dict(K=64, H=33), dict(T=0), dict(T=65), dict(prec=7), dict(herm=2),
     dict(prec=rs.BF16X3, products=4), dict(k=np.r_[np.linspace(0.5, 16, 15), -1.0]),
     dict(w=np.r_[np.ones(15), 0.0]), dict(T=2, delta=np.array([[0.0, np.nan], [0, 0]])),
+    dict(sigma_delta=-0.1), dict(sigma_delta=float("nan")), dict(sigma_delta=float("inf")),
 ])
 def test_invalid_problem_rejected(bad):
     pr, keep = _prob(**bad)

@@ -108,6 +108,32 @@ def test_fused_full_output_is_the_landscape_best_and_lse_see(Q, precision, produ
     assert np.allclose(o["lse_pair"].cpu().numpy(), lse, rtol=0, atol=2e-5 * np.abs(lse).max())
 
 
+@pytest.mark.parametrize("precision,K,sigma", [("fp64", 16, 0.05), ("fp32", 64, 0.02), ("bf16x3", 64, 0.05)])
+def test_translated_kernel_U_against_oracle(precision, K, sigma):
+    """Kernel C of the translation-averaged objective (section 5): the library's
+    C eigenvalues and principal subspace against the oracle's closed form."""
+    Q = 4 * K
+    cfg = synth.config("fp32", N=2 * K, K=K, Q=Q, n_img=5, n_tgt=150, T=1, H=min(K, 12), n_blobs=8, snr=0.5)
+    P = synth.make_problem(cfg, 1020)
+    A, B = to_device(P, precision)
+    plan = rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision=precision, sigma_delta=sigma)
+    U, lam = plan.U_lambda()
+    U, lam = U.cpu().numpy(), lam.cpu().numpy()
+    A_h, B_h = host_inputs(A, B)
+    Cor = oracle.kernel_C_translated(B_h, P.w, Q, P.k, sigma)
+    Uor, lam_or = oracle.principal_vectors(Cor)
+    assert np.allclose(lam, lam_or, rtol=0, atol=1e-12 * lam_or[0])
+    # the rank-H principal subspace (gap-weighted)
+    H = cfg.H
+    gap = (lam_or[H - 1] - lam_or[H]) / lam_or[0]
+    proj = np.abs(U[:, :H] @ U[:, :H].T - Uor[:, :H] @ Uor[:, :H].T).max()
+    print(f"{precision} K={K} sigma={sigma}: gap {gap:.2e}, projector {proj:.2e}")
+    assert proj <= 1e-9 / max(gap, 1e-6)
+    # and it differs from the rotation-only kernel's
+    C0 = oracle.kernel_C(B_h, P.w, Q)
+    assert np.abs(Cor - C0).max() > 1e-3 * np.abs(C0).max()
+
+
 def test_non_hermitian_fp32_full():
     P = synth.make_problem(synth.config("tiny", n_img=3, n_tgt=4, H=9), 1003)
     delta = np.array([[0, 0], [0.01, 0], [0, -0.02], [0.03, 0.01]])

@@ -30,6 +30,11 @@ alignment of images and volumes", arXiv 2202.07235):
                           (section 2.4 / section 3.3 steps 1-2).  At H = K it
                           is the full polar quadrature of <Ahat, R_gamma T_delta Bhat>
                           (prefactor (2 pi)^-2 dropped, as the paper does).
+* ``landscape_offgrid`` -- X at rotations gamma off the polar grid: the target
+                          ring rotated by the phase exp(-i q gamma) on its
+                          Fourier-Bessel coefficients (section 2.2, rotation by
+                          any gamma), band-limited to |q| <= Q/2, then the
+                          direct psi-space sum.
 * ``best`` / ``lse``   -- maximum-likelihood alignment argmax_gamma X (section
                           2.7) and the soft-alignment log-sum-exp score.
 * ``lse_grad``         -- gradient of sum_a g_a lse_img[a] with respect to the
@@ -264,6 +269,36 @@ def landscape(A, B, U, H: int, k, w, delta, pairs=None) -> np.ndarray:
 # --------------------------------------------------------------------------
 # decisions (section 2.7) and the soft-alignment score
 # --------------------------------------------------------------------------
+def rotate_ring(R, gamma):
+    """A ring of Q samples rotated by any angle gamma (section 2.2): its
+    Fourier-Bessel coefficients (the DFT over psi, divided by Q) times
+    exp(-i q gamma), summed back at the grid angles.  The band is |q| <= Q/2
+    with the q = Q/2 term split evenly between +Q/2 and -Q/2 (its cosine), so
+    that grid rotations shift the samples exactly.  R [..., Q]."""
+    R = _c128(R)
+    Q = R.shape[-1]
+    c = np.fft.fft(R, axis=-1) / Q
+    q = np.arange(Q)
+    qs = np.where(q < Q // 2, q, q - Q).astype(np.float64)    # symmetric representatives
+    psi = 2.0 * math.pi * np.arange(Q) / Q
+    E = np.exp(1j * qs[:, None] * (psi[None, :] - gamma))       # [q][j]
+    if Q % 2 == 0:
+        E[Q // 2] = np.cos((Q // 2) * (psi - gamma))
+    return c @ E
+
+
+def landscape_offgrid(Ar, Br, gammas) -> np.ndarray:
+    """X(gamma) = sum_h sum_j conj(Ar[h](psi_j)) [R_gamma Br[h]](psi_j) for the
+    principal rings of one image (Ar [H][Q]) and one translated target (Br
+    [H][Q]) at any rotations gamma (rotate_ring; the direct psi-space sum of
+    ``landscape`` at gamma = 2 pi m / Q)."""
+    Ar, Br = _c128(Ar), _c128(Br)
+    out = np.empty(len(gammas), dtype=np.complex128)
+    for i, g in enumerate(gammas):
+        out[i] = np.sum(np.conj(Ar) * rotate_ring(Br, float(g)))
+    return out
+
+
 def best(X):
     """argmax over (t, m) of Re X per pair; ties go to the smallest t*Q + m.
     A pair whose landscape holds a value that is not finite (NaN or an

@@ -401,3 +401,64 @@ def test_lse_gradient_matches_central_differences():
         Um[r, h] -= 1e-4
         fd = (f(B, Up) - f(B, Um)) / 2e-4
         assert abs(fd - gU[r, h]) <= 1e-8 * np.abs(gU).max()
+
+
+# --------------------------------------------------------------------------
+# rotations off the grid (section 2.2)
+# --------------------------------------------------------------------------
+def test_offgrid_landscape_on_the_grid_is_the_landscape():
+    cfg = synth.config("fp32", N=32, K=16, Q=48, n_img=2, n_tgt=3, T=4, H=6)
+    P = synth.make_problem(cfg, seed=21)
+    U, _ = oracle.principal_vectors(oracle.kernel_C(P.B, P.w, cfg.Q))
+    Ar = oracle.principal_rings(P.A, U, cfg.H, P.w, cfg.Q)
+    Br = oracle.principal_rings(P.B, U, cfg.H, P.w, cfg.Q, k=P.k, delta=P.delta)
+    X = oracle.landscape_rings(Ar, Br)
+    g = 2 * math.pi * np.arange(cfg.Q) / cfg.Q
+    for a, b, t in [(0, 0, 0), (1, 2, 3), (0, 1, 2)]:
+        Xo = oracle.landscape_offgrid(Ar[a], Br[b, t], g)
+        assert _rel(Xo, X[a, b, t]) <= 1e-13
+
+
+def test_offgrid_landscape_peaks_at_the_true_rotation():
+    """A target ring that is the image ring rotated by gamma0 (exactly, as a
+    band-limited trigonometric polynomial): rotating it back, X(-gamma0) =
+    sum |Ar|^2, the Cauchy-Schwarz maximum, and X is smaller at every other
+    angle tried."""
+    rng = np.random.default_rng(4)
+    Q, H = 32, 5
+    psi = 2 * math.pi * np.arange(Q) / Q
+    # rings with |q| < Q/2 and no Nyquist term
+    qs = np.r_[np.arange(0, Q // 2), np.arange(-Q // 2 + 1, 0)]
+    coef = rng.standard_normal((H, Q - 1)) + 1j * rng.standard_normal((H, Q - 1))
+    ring = lambda g: (coef[:, :, None] * np.exp(1j * qs[None, :, None] * (psi[None, None, :] - g))).sum(1)
+    g0 = 2 * math.pi * 7.37 / Q
+    Ar, Br = ring(0.0), ring(g0)
+    assert _rel(oracle.rotate_ring(Ar, g0), Br) <= 1e-13
+    gs = -g0 + np.linspace(-0.3, 0.3, 61)
+    X = oracle.landscape_offgrid(Ar, Br, gs)
+    peak = np.sum(np.abs(Ar) ** 2)
+    assert abs(X[30] - peak) <= 1e-12 * peak
+    assert np.all(X.real[np.arange(61) != 30] < peak * (1 - 1e-6))
+
+
+def test_offgrid_landscape_shift_and_reality():
+    """Rotating the target by a grid angle shifts the off-grid landscape by
+    that angle; Hermitian rings give a real landscape at every angle."""
+    cfg = synth.config("fp32", N=32, K=16, Q=64, n_img=1, n_tgt=1, T=1, H=8)
+    P = synth.make_problem(cfg, seed=22)
+    U, _ = oracle.principal_vectors(oracle.kernel_C(P.B, P.w, cfg.Q))
+    Ar = oracle.principal_rings(P.A, U, cfg.H, P.w, cfg.Q)[0]
+    Br = oracle.principal_rings(P.B, U, cfg.H, P.w, cfg.Q)[0]
+    gs = np.array([0.013, 0.9, 2.71, 5.5])
+    X = oracle.landscape_offgrid(Ar, Br, gs)
+    Xs = oracle.landscape_offgrid(Ar, np.roll(Br, 3, axis=-1), gs - 2 * math.pi * 3 / cfg.Q)
+    assert _rel(Xs, X) <= 1e-12
+    assert np.abs(X.imag).max() <= 1e-12 * np.abs(X).max()
+    # real rings with a strong q = Q/2 term: the band-limited rotation keeps them
+    # real (the Nyquist term enters as a cosine), so X is real at any angle
+    rng = np.random.default_rng(23)
+    Ar = rng.standard_normal((3, 16))
+    Br = rng.standard_normal((3, 16)) + 5.0 * (-1.0) ** np.arange(16)[None, :]
+    Xr = oracle.landscape_offgrid(Ar, Br, np.array([0.05, 0.77, 3.3]))
+    assert np.abs(Xr.imag).max() <= 1e-12 * np.abs(Xr).max()
+    assert np.abs(oracle.rotate_ring(Br, 0.4).imag).max() <= 1e-12 * np.abs(Br).max()

@@ -129,9 +129,9 @@ size_t align_prepare_workspace(const radsvd_problem *prob, int n_img, int n_tgt)
  * polar samples).  Plans are immutable once prepared, with one exception: for
  * plans the fused pair kernel serves (Hermitian, not FP64, Q in {64, 96, 128,
  * 192, 256, 384, 512}) align_prepare writes only the fused kernel's operand
- * layout, and the first align_pairs_backward call writes the generic one (its
- * space is part of ws) on its own stream.  Apart from that first backward call,
- * calls on different streams may share one plan.  n_img, n_tgt in [1, 2^20].
+ * layout, and the first align_pairs_backward or align_refine_rotation call
+ * writes the generic one (its space is part of ws) on its own stream.  Apart
+ * from that first call, calls on different streams may share one plan.  n_img, n_tgt in [1, 2^20].
  */
 radsvd_status align_prepare(const radsvd_problem *prob, int n_img, const void *A_polar,
                             int n_tgt, const void *B_polar, const double *U_in,
@@ -164,6 +164,32 @@ radsvd_status align_pairs(const radsvd_plan *plan, int out_flags, float inv_sigm
                           float *best_score, int32_t *best_m, int32_t *best_t,
                           float *lse_pair, float *lse_img, void *X_full, void *stream);
 
+/*
+ * Rotations off the grid (section 2.2: rotating a ring by any gamma multiplies
+ * its Fourier-Bessel coefficients by exp(-i q gamma); section 2.4: zero-padding
+ * the frequency array before the transform over q gives a finer gamma grid).
+ * For every pair (a, b) whose BEST output is (best_m, best_t), the landscape at
+ * translation best_t is evaluated at the rotations
+ *   gamma_j = 2 pi (R best_m + j) / (R Q),  j = -R+1 .. R-1,
+ * i.e. the length-R*Q zero-padded transform within one grid step of the grid
+ * maximum, with the frequencies in the band |q| <= Q/2 and the q = Q/2 term
+ * taken as a cosine (so j = 0 reproduces the grid landscape).  Writes
+ *   fine_score [n_img][n_tgt] f32: the largest Re X(gamma_j);
+ *   fine_m     [n_img][n_tgt] int32: (R best_m + j) mod (R Q) of that maximum,
+ *              gamma = 2 pi fine_m / (R Q); ties go to the smallest j.
+ * best_m, best_t: device [n_img][n_tgt] int32, a BEST output of align_pairs with
+ * this plan; a pair with best_m < 0 (non-finite landscape), or whose landscape
+ * is not finite at a candidate rotation, gets NaN and -1.  The sums run in the
+ * plan's I/O precision (FP64 for RADSVD_FP64, else FP32) on the plan's
+ * principal rings in the generic layout, whatever the plan's contraction
+ * precision (so j = 0 may differ from best_score by that precision's error);
+ * the first call with a plan the fused kernel serves writes that layout (see
+ * align_prepare).  R in [1, 64].  Errors: RADSVD_ERR_INVALID_ARG (NULL or
+ * misaligned arrays, R outside [1, 64]).
+ */
+radsvd_status align_refine_rotation(const radsvd_plan *plan, const int32_t *best_m, const int32_t *best_t, int R,
+                                    float *fine_score, int32_t *fine_m, void *stream);
+
 /* Bytes of device scratch align_pairs_backward needs for this plan. */
 size_t align_backward_workspace(const radsvd_plan *plan);
 
@@ -188,7 +214,8 @@ size_t align_backward_workspace(const radsvd_plan *plan);
  * landscape transforms take at most 4 GiB of the scratch.
  * bwd_ws: device scratch of bwd_bytes >= align_backward_workspace(plan),
  * 256-byte aligned.  The first call with a plan the fused kernel serves also
- * writes the plan's generic operand layout on `stream` (see align_prepare);
+ * writes the plan's generic operand layout on `stream` (see align_prepare; so
+ * does the first align_refine_rotation call);
  * later calls on other streams must be ordered after it.  Errors: RADSVD_ERR_INVALID_ARG (NULL plan or lse
  * pointers, inv_sigma2 not finite and > 0, misaligned outputs),
  * RADSVD_ERR_WORKSPACE (scratch missing, misaligned or too small).

@@ -21,7 +21,7 @@ __all__ = [
     "align_prepare_workspace", "align_prepare", "align_pairs", "align_backward_workspace",
     "align_pairs_backward", "align_batched_workspace", "align_pairs_batched",
     "align_pairs_batched_noalloc", "align_get_U",
-    "align_set_tile", "align_set_waves", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
+    "align_set_tile", "align_set_waves", "align_refine_rotation", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
     "PRECISIONS", "RadialAlignLSE", "pairs_batched", "RADSVD_NOALLOC_MAX_JOBS",
 ]
 
@@ -86,6 +86,8 @@ def _load():
     L.align_get_U.restype = i32
     L.align_set_tile.argtypes = [vp, i32]
     L.align_set_tile.restype = i32
+    L.align_refine_rotation.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.align_refine_rotation.restype = i32
     L.align_set_waves.argtypes = [vp, i32]
     L.align_set_waves.restype = i32
     L.align_plan_destroy.argtypes = [vp]
@@ -199,6 +201,11 @@ def align_set_tile(plan, band: int):
     _check(_load().align_set_tile(plan, int(band)))
 
 
+def align_refine_rotation(plan, best_m, best_t, R: int, fine_score, fine_m, stream=None):
+    _check(_load().align_refine_rotation(plan, _ptr(best_m), _ptr(best_t), int(R), _ptr(fine_score), _ptr(fine_m),
+                                         _stream(stream)))
+
+
 def align_set_waves(plan, waves: int):
     _check(_load().align_set_waves(plan, int(waves)))
 
@@ -286,6 +293,15 @@ class Plan:
         """Tile order of the fast path: image tiles per XCD band (0 = default)."""
         align_set_tile(self.handle, band)
         self.band = band
+
+    def refine_rotation(self, best: dict, R: int, stream=None) -> dict:
+        """Best rotation on the R-times finer grid around each pair's grid
+        maximum (``align_refine_rotation``); ``best`` holds best_m and best_t
+        of a BEST output.  Returns fine_score, fine_m and gamma (radians)."""
+        fs = torch.empty((self.n_img, self.n_tgt), dtype=torch.float32, device=self.device)
+        fm = torch.empty((self.n_img, self.n_tgt), dtype=torch.int32, device=self.device)
+        align_refine_rotation(self.handle, best["best_m"], best["best_t"], R, fs, fm, stream)
+        return {"fine_score": fs, "fine_m": fm, "gamma": fm.to(torch.float64) * (2.0 * np.pi / (R * self.Q))}
 
     def set_waves(self, waves: int):
         """Waves per CU of the fast path: 4, 8 or 0 (default); raises

@@ -400,6 +400,21 @@ radsvd_status align_set_tile(radsvd_plan *p, int band) {
     return RADSVD_OK;
 }
 
+radsvd_status align_refine_rotation(const radsvd_plan *p, const int32_t *best_m, const int32_t *best_t, int R,
+                                    float *fine_score, int32_t *fine_m, void *stream) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    if (!best_m || !best_t || !fine_score || !fine_m)
+        return fail(RADSVD_ERR_INVALID_ARG, "best_m, best_t, fine_score and fine_m must be non-NULL");
+    if (!aligned(best_m, 4) || !aligned(best_t, 4) || !aligned(fine_score, 4) || !aligned(fine_m, 4))
+        return fail(RADSVD_ERR_INVALID_ARG, "arrays must be 4-byte aligned");
+    if (R < 1 || R > kMaxRefine) return fail(RADSVD_ERR_INVALID_ARG, "R=%d outside [1, %d]", R, kMaxRefine);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = ensure_generic_layout(p, s);
+    if (e == hipSuccess) e = launch_refine_rotation(p, best_m, best_t, R, fine_score, fine_m, s);
+    return dev_check(e, "align_refine_rotation launch");
+}
+
 radsvd_status align_set_waves(radsvd_plan *p, int waves) {
     g_err[0] = 0;
     if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");

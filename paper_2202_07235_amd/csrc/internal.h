@@ -10,6 +10,7 @@ namespace radsvd {
 
 constexpr int kMaxK = 128;
 constexpr int kMaxQ = 512;
+constexpr int kMaxRefine = 64;   // largest refinement factor of align_refine_rotation
 constexpr int kMaxH = 32;
 constexpr int kMaxT = 64;
 constexpr int kEigMaxSweeps = 40;
@@ -159,6 +160,9 @@ bool fast_waves_ok(const radsvd_plan *p, int waves);
 constexpr int kDefaultBand = 8;
 hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, float *best_score,
                              int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full, hipStream_t s);
+// refine.hip
+hipError_t launch_refine_rotation(const radsvd_plan *p, const int32_t *best_m, const int32_t *best_t, int Rf,
+                                  float *fine_score, int32_t *fine_m, hipStream_t s);
 // lse.hip
 hipError_t launch_lse_img(int n_img, int n_tgt, const float *lse_pair, float *lse_img, hipStream_t s);
 // backward.hip

@@ -88,6 +88,7 @@ def test_pairs_and_backward_argument_errors():
     assert lib.align_get_U(None, None, None, None) == 1
     assert lib.align_set_tile(None, 0) == 1
     assert lib.align_set_waves(None, 0) == 1
+    assert lib.align_refine_rotation(None, None, None, 4, None, None, None) == 1
     assert lib.align_set_waves(None, 8) == 1
     assert lib.align_batched_workspace(0) == 0
     assert lib.align_pairs_batched(None, 1, None, None, 0, None) == 1

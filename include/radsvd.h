@@ -190,6 +190,46 @@ radsvd_status align_pairs(const radsvd_plan *plan, int out_flags, float inv_sigm
 radsvd_status align_refine_rotation(const radsvd_plan *plan, const int32_t *best_m, const int32_t *best_t, int R,
                                     float *fine_score, int32_t *fine_m, void *stream);
 
+/*
+ * align_pairs for a list of pairs (principal-mode marching, section 5: the
+ * candidates that a low-rank pass selects are evaluated again at a higher
+ * rank).  pairs: device [n][2] int32 (image, target) of this plan; outputs as
+ * in align_pairs but indexed by list position: best_score, best_m, best_t,
+ * lse_pair [n], X_full [n][T][Q].  An entry outside the plan's counts gets
+ * NaN and -1.  Runs the per-pair kernel in the plan's precision on the
+ * generic operand layout (written on the first such call, see align_prepare).
+ * Errors: RADSVD_ERR_INVALID_ARG (n < 1, NULL or misaligned arrays, flags as
+ * in align_pairs).
+ */
+radsvd_status align_pairs_list(const radsvd_plan *plan, int out_flags, float inv_sigma2, int n, const int32_t *pairs,
+                               float *best_score, int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full,
+                               void *stream);
+
+/*
+ * The k best targets of every image by a score (marching, section 5):
+ * cand[a][c], c < k, the target of the c-th largest score[a][.] (device
+ * [n_img][n_tgt] f32, e.g. best_score of a low-rank align_pairs), ties to the
+ * smaller target; NaN scores are never taken and slots beyond the finite ones
+ * get -1.  k in [1, 1024].  Errors: RADSVD_ERR_INVALID_ARG.
+ */
+radsvd_status align_top_targets(int n_img, int n_tgt, const float *score, int k, int32_t *cand, void *stream);
+
+/*
+ * Landscape quality (section 3.5) of an approximate landscape X_est against a
+ * reference X_ref (e.g. low rank against full rank), both device
+ * [n_pairs][len] complex (FP64 if fp64 = 1, else FP32; FULL outputs with
+ * len = T * Q), on their real parts:
+ *   f [n_pairs] f32: the fraction of the pair's X_ref values that are <= X_ref
+ *       at the argmax of X_est (first maximum), NaN if a value is not finite;
+ *   pair_stats [n_pairs][6] FP64: per pair sum (e - r)^2, sum r^2, sum e, sum r,
+ *       sum e^2, sum e r (output, also the reduction's input);
+ *   summary [3] FP64: relative Frobenius error ||X_est - X_ref|| / ||X_ref||,
+ *       correlation over the whole array, mean f (sums in a fixed order).
+ * Errors: RADSVD_ERR_INVALID_ARG (sizes < 1, NULL or misaligned arrays).
+ */
+radsvd_status align_landscape_metrics(long long n_pairs, int len, const void *X_est, const void *X_ref, int fp64,
+                                      float *f, double *pair_stats, double *summary, void *stream);
+
 /* Bytes of device scratch align_pairs_backward needs for this plan. */
 size_t align_backward_workspace(const radsvd_plan *plan);
 

@@ -35,6 +35,12 @@ alignment of images and volumes", arXiv 2202.07235):
                           Fourier-Bessel coefficients (section 2.2, rotation by
                           any gamma), band-limited to |q| <= Q/2, then the
                           direct psi-space sum.
+* ``landscape_metrics`` -- the quality measures of section 3.5: relative
+                          error in the Frobenius norm and correlation over the
+                          whole array, and per pair the true percentile f of
+                          the approximate alignment.
+* ``top_targets``      -- the candidates of principal-mode marching (section 5):
+                          the k best-scoring targets of each image.
 * ``best`` / ``lse``   -- maximum-likelihood alignment argmax_gamma X (section
                           2.7) and the soft-alignment log-sum-exp score.
 * ``lse_grad``         -- gradient of sum_a g_a lse_img[a] with respect to the
@@ -296,6 +302,44 @@ def landscape_offgrid(Ar, Br, gammas) -> np.ndarray:
     out = np.empty(len(gammas), dtype=np.complex128)
     for i, g in enumerate(gammas):
         out[i] = np.sum(np.conj(Ar) * rotate_ring(Br, float(g)))
+    return out
+
+
+def landscape_metrics(X_est, X_ref):
+    """Section 3.5, on the real parts of two landscapes of the same shape
+    [n_pairs][...]: the relative error in the Frobenius norm over the whole
+    array, the correlation over the whole array, and per pair the fraction f
+    of the true inner products X_ref that are <= X_ref at the approximate
+    optimum argmax X_est (the first maximum; NaN if a value is not finite).
+    Returns (rel_fro, corr, f [n_pairs])."""
+    E = np.asarray(X_est).real.astype(np.float64)
+    Rr = np.asarray(X_ref).real.astype(np.float64)
+    n = E.shape[0]
+    E2, R2 = E.reshape(n, -1), Rr.reshape(n, -1)
+    rel = math.sqrt(float(np.sum((E2 - R2) ** 2)) / float(np.sum(R2 ** 2)))
+    e, r = E2.ravel(), R2.ravel()
+    de, dr = e - e.mean(), r - r.mean()
+    corr = float(np.sum(de * dr) / math.sqrt(float(np.sum(de * de)) * float(np.sum(dr * dr))))
+    f = np.empty(n)
+    for p in range(n):
+        if not (np.isfinite(E2[p]).all() and np.isfinite(R2[p]).all()):
+            f[p] = np.nan
+            continue
+        i = int(np.argmax(E2[p]))          # first maximum
+        f[p] = np.count_nonzero(R2[p] <= R2[p, i]) / R2.shape[1]
+    return rel, corr, f
+
+
+def top_targets(score, k: int):
+    """The k best targets of each image (candidates of principal-mode
+    marching, section 5): targets by decreasing score, ties to the smaller
+    target, NaN never taken; -1 pads the slots beyond the finite scores."""
+    S = np.asarray(score, dtype=np.float64)
+    out = -np.ones((S.shape[0], k), dtype=np.int64)
+    for a in range(S.shape[0]):
+        ok = [b for b in range(S.shape[1]) if not math.isnan(S[a, b])]
+        ok.sort(key=lambda b: (-S[a, b], b))
+        out[a, :min(k, len(ok))] = ok[:k]
     return out
 
 

@@ -21,7 +21,8 @@ __all__ = [
     "align_prepare_workspace", "align_prepare", "align_pairs", "align_backward_workspace",
     "align_pairs_backward", "align_batched_workspace", "align_pairs_batched",
     "align_pairs_batched_noalloc", "align_get_U",
-    "align_set_tile", "align_set_waves", "align_refine_rotation", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
+    "align_set_tile", "align_set_waves", "align_refine_rotation", "align_pairs_list", "align_top_targets",
+    "align_landscape_metrics", "align_plan_destroy", "radsvd_last_error", "library_path", "Plan",
     "PRECISIONS", "RadialAlignLSE", "pairs_batched", "RADSVD_NOALLOC_MAX_JOBS",
 ]
 
@@ -86,6 +87,12 @@ def _load():
     L.align_get_U.restype = i32
     L.align_set_tile.argtypes = [vp, i32]
     L.align_set_tile.restype = i32
+    L.align_pairs_list.argtypes = [vp, i32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
+    L.align_pairs_list.restype = i32
+    L.align_top_targets.argtypes = [i32, i32, vp, i32, vp, vp]
+    L.align_top_targets.restype = i32
+    L.align_landscape_metrics.argtypes = [ctypes.c_longlong, i32, vp, vp, i32, vp, vp, vp, vp]
+    L.align_landscape_metrics.restype = i32
     L.align_refine_rotation.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     L.align_refine_rotation.restype = i32
     L.align_set_waves.argtypes = [vp, i32]
@@ -201,6 +208,26 @@ def align_set_tile(plan, band: int):
     _check(_load().align_set_tile(plan, int(band)))
 
 
+def align_pairs_list(plan, out_flags, inv_sigma2, pairs, best_score=None, best_m=None, best_t=None,
+                     lse_pair=None, X_full=None, stream=None):
+    _check(_load().align_pairs_list(plan, out_flags, float(inv_sigma2), int(pairs.shape[0]), _ptr(pairs),
+                                    _ptr(best_score), _ptr(best_m), _ptr(best_t), _ptr(lse_pair), _ptr(X_full),
+                                    _stream(stream)))
+
+
+def align_top_targets(score, k: int, cand, stream=None):
+    _check(_load().align_top_targets(int(score.shape[0]), int(score.shape[1]), _ptr(score), int(k), _ptr(cand),
+                                     _stream(stream)))
+
+
+def align_landscape_metrics(X_est, X_ref, f, pair_stats, summary, stream=None):
+    """X_est, X_ref: device [n_pairs, ...] complex64 or complex128 of equal shape."""
+    n = int(X_est.shape[0])
+    _check(_load().align_landscape_metrics(n, int(X_est.numel() // n), _ptr(X_est), _ptr(X_ref),
+                                           int(X_est.dtype == torch.complex128), _ptr(f), _ptr(pair_stats),
+                                           _ptr(summary), _stream(stream)))
+
+
 def align_refine_rotation(plan, best_m, best_t, R: int, fine_score, fine_m, stream=None):
     _check(_load().align_refine_rotation(plan, _ptr(best_m), _ptr(best_t), int(R), _ptr(fine_score), _ptr(fine_m),
                                          _stream(stream)))
@@ -293,6 +320,27 @@ class Plan:
         """Tile order of the fast path: image tiles per XCD band (0 = default)."""
         align_set_tile(self.handle, band)
         self.band = band
+
+    def pairs_list(self, pairs: torch.Tensor, out: str = "best", inv_sigma2: float = 1.0, stream=None) -> dict:
+        """align_pairs for the listed (image, target) pairs, pairs: device
+        [n][2] int32; outputs indexed by list position."""
+        flags = 0
+        for tok in out.split("+"):
+            flags |= {"best": OUT_BEST, "lse": OUT_LSE, "full": OUT_FULL}[tok]
+        n, dev = int(pairs.shape[0]), self.device
+        o = {}
+        if flags & OUT_BEST:
+            o["best_score"] = torch.empty(n, dtype=torch.float32, device=dev)
+            o["best_m"] = torch.empty(n, dtype=torch.int32, device=dev)
+            o["best_t"] = torch.empty(n, dtype=torch.int32, device=dev)
+        if flags & OUT_LSE:
+            o["lse_pair"] = torch.empty(n, dtype=torch.float32, device=dev)
+        if flags & OUT_FULL:
+            dt = torch.complex128 if self.prec == FP64 else torch.complex64
+            o["X"] = torch.empty((n, self.T, self.Q), dtype=dt, device=dev)
+        align_pairs_list(self.handle, flags, inv_sigma2, pairs.contiguous(), o.get("best_score"), o.get("best_m"),
+                         o.get("best_t"), o.get("lse_pair"), o.get("X"), stream)
+        return o
 
     def refine_rotation(self, best: dict, R: int, stream=None) -> dict:
         """Best rotation on the R-times finer grid around each pair's grid

@@ -400,6 +400,51 @@ radsvd_status align_set_tile(radsvd_plan *p, int band) {
     return RADSVD_OK;
 }
 
+radsvd_status align_pairs_list(const radsvd_plan *p, int flags, float inv_sigma2, int n, const int32_t *pairs,
+                               float *best_score, int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full,
+                               void *stream) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    if (n < 1) return fail(RADSVD_ERR_INVALID_ARG, "n=%d must be >= 1", n);
+    if (!pairs || !aligned(pairs, 4)) return fail(RADSVD_ERR_INVALID_ARG, "pairs must be non-NULL and 4-byte aligned");
+    if (flags <= 0 || (flags & ~7)) return fail(RADSVD_ERR_INVALID_ARG, "out_flags=%d invalid", flags);
+    if ((flags & RADSVD_OUT_BEST) && (!best_score || !best_m || !best_t))
+        return fail(RADSVD_ERR_INVALID_ARG, "BEST output pointers must be non-NULL");
+    if ((flags & RADSVD_OUT_LSE) && (!lse_pair || !(inv_sigma2 > 0.f && isfinite(inv_sigma2))))
+        return fail(RADSVD_ERR_INVALID_ARG, "LSE needs lse_pair and a finite inv_sigma2 > 0");
+    if ((flags & RADSVD_OUT_FULL) && !X_full) return fail(RADSVD_ERR_INVALID_ARG, "FULL output X_full must be non-NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = ensure_generic_layout(p, s);
+    if (e == hipSuccess) e = launch_pairs_list(p, flags, inv_sigma2, n, pairs, best_score, best_m, best_t, lse_pair,
+                                               X_full, s);
+    return dev_check(e, "align_pairs_list launch");
+}
+
+radsvd_status align_top_targets(int n_img, int n_tgt, const float *score, int k, int32_t *cand, void *stream) {
+    g_err[0] = 0;
+    if (n_img < 1 || n_tgt < 1) return fail(RADSVD_ERR_INVALID_ARG, "n_img=%d, n_tgt=%d must be >= 1", n_img, n_tgt);
+    if (k < 1 || k > kMaxTopK) return fail(RADSVD_ERR_INVALID_ARG, "k=%d outside [1, %d]", k, kMaxTopK);
+    if (!score || !cand || !aligned(score, 4) || !aligned(cand, 4))
+        return fail(RADSVD_ERR_INVALID_ARG, "score and cand must be non-NULL and 4-byte aligned");
+    return dev_check(launch_top_targets(n_img, n_tgt, score, k, cand, reinterpret_cast<hipStream_t>(stream)),
+                     "align_top_targets launch");
+}
+
+radsvd_status align_landscape_metrics(long long n_pairs, int len, const void *X_est, const void *X_ref, int fp64,
+                                      float *f, double *pair_stats, double *summary, void *stream) {
+    g_err[0] = 0;
+    if (n_pairs < 1 || len < 1) return fail(RADSVD_ERR_INVALID_ARG, "n_pairs and len must be >= 1");
+    if (fp64 != 0 && fp64 != 1) return fail(RADSVD_ERR_INVALID_ARG, "fp64 must be 0 or 1");
+    if (!X_est || !X_ref || !f || !pair_stats || !summary)
+        return fail(RADSVD_ERR_INVALID_ARG, "arrays must be non-NULL");
+    const size_t al = fp64 ? 16 : 8;
+    if (!aligned(X_est, al) || !aligned(X_ref, al) || !aligned(f, 4) || !aligned(pair_stats, 8) || !aligned(summary, 8))
+        return fail(RADSVD_ERR_INVALID_ARG, "misaligned array");
+    return dev_check(launch_landscape_metrics(n_pairs, len, X_est, X_ref, fp64, f, pair_stats, summary,
+                                              reinterpret_cast<hipStream_t>(stream)),
+                     "align_landscape_metrics launch");
+}
+
 radsvd_status align_refine_rotation(const radsvd_plan *p, const int32_t *best_m, const int32_t *best_t, int R,
                                     float *fine_score, int32_t *fine_m, void *stream) {
     g_err[0] = 0;

@@ -160,6 +160,15 @@ bool fast_waves_ok(const radsvd_plan *p, int waves);
 constexpr int kDefaultBand = 8;
 hipError_t launch_pairs_fast(const radsvd_plan *p, int flags, float inv_s2, float *best_score,
                              int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full, hipStream_t s);
+// pairs_generic.hip, list mode: pairs [n][2] (image, target); outputs at list positions
+hipError_t launch_pairs_list(const radsvd_plan *p, int flags, float inv_s2, int n, const int32_t *pairs,
+                             float *best_score, int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full,
+                             hipStream_t s);
+// march.hip
+hipError_t launch_top_targets(int n_img, int n_tgt, const float *score, int k, int32_t *cand, hipStream_t s);
+hipError_t launch_landscape_metrics(long long n_pairs, int len, const void *X_est, const void *X_ref, int fp64,
+                                    float *f, double *stats, double *summary, hipStream_t s);
+constexpr int kMaxTopK = 1024;   // candidates per image of align_top_targets
 // refine.hip
 hipError_t launch_refine_rotation(const radsvd_plan *p, const int32_t *best_m, const int32_t *best_t, int Rf,
                                   float *fine_score, int32_t *fine_m, hipStream_t s);

@@ -61,15 +61,29 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
     const cx<R> *__restrict__ Ag, const cx<R> *__restrict__ Bg, int n_img, int n_tgt, int T, int H,
     int Q, int Qc, int herm, int products, int flags, float inv_s2, float *__restrict__ best_score,
     int32_t *__restrict__ best_m, int32_t *__restrict__ best_t, float *__restrict__ lse_pair,
-    cx<R> *__restrict__ Xfull) {
+    cx<R> *__restrict__ Xfull, const int32_t *__restrict__ plist) {
     extern __shared__ unsigned char smem_raw[];
     cx<R> *tw = reinterpret_cast<cx<R> *>(smem_raw);
     cx<R> *S = tw + Q;
     __shared__ float rv[4];
     __shared__ int ri[4];
     __shared__ float rs[4];
-    const int b = blockIdx.x, a = blockIdx.y;
+    // grid mode: pair (blockIdx.y, blockIdx.x), outputs [n_img][n_tgt]; list mode:
+    // pair plist[2 i], plist[2 i + 1], outputs at list position i
+    const size_t o = plist ? (size_t)blockIdx.x : (size_t)blockIdx.y * n_tgt + blockIdx.x;
+    const int a = plist ? plist[2 * o] : (int)blockIdx.y, b = plist ? plist[2 * o + 1] : (int)blockIdx.x;
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (a < 0 || a >= n_img || b < 0 || b >= n_tgt) {   // a list entry outside the plan (uniform per workgroup)
+        if (tid == 0) {
+            if (flags & RADSVD_OUT_BEST) {
+                best_score[o] = NAN;
+                best_m[o] = -1;
+                best_t[o] = -1;
+            }
+            if (flags & RADSVD_OUT_LSE) lse_pair[o] = NAN;
+        }
+        return;
+    }
     const int lane = tid & 63, wid = tid >> 6;
     for (int i = tid; i < Q; i += nt) {
         double s, c;
@@ -122,7 +136,7 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
         lds_fft_dif(S, 1, Q, pl, tw);
         // epilogue
         if (flags & RADSVD_OUT_FULL) {
-            cx<R> *Xo = Xfull + (((size_t)a * n_tgt + b) * T + t) * Q;
+            cx<R> *Xo = Xfull + (o * T + t) * Q;
             for (int m = tid; m < Q; m += nt) Xo[m] = S[fft_pos(m, pl)];
         }
         if (flags & RADSVD_OUT_BEST) {
@@ -209,7 +223,6 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
         }
     }
     if (tid == 0) {
-        const size_t o = (size_t)a * n_tgt + b;
         if (flags & RADSVD_OUT_BEST) {
             if (isnan(best_v)) {
                 best_score[o] = NAN;
@@ -227,33 +240,49 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
 
 template <typename R, int PREC>
 static void launch_g(const radsvd_plan *p, int flags, float inv_s2, float *bs, int32_t *bm,
-                     int32_t *bt, float *lp, void *Xf, hipStream_t s) {
+                     int32_t *bt, float *lp, void *Xf, int n_list, const int32_t *plist, hipStream_t s) {
     const size_t shmem = 2 * (size_t)p->Q * sizeof(cx<R>);
-    hipLaunchKernelGGL((k_pairs_generic<R, PREC>), dim3(p->n_tgt, p->n_img), dim3(256), shmem, s,
+    const dim3 grid = plist ? dim3(n_list) : dim3(p->n_tgt, p->n_img);
+    hipLaunchKernelGGL((k_pairs_generic<R, PREC>), grid, dim3(256), shmem, s,
                        reinterpret_cast<const cx<R> *>(p->Ag), reinterpret_cast<const cx<R> *>(p->Bg),
                        p->n_img, p->n_tgt, p->T, p->H, p->Q, p->Qc, p->herm, p->products, flags, inv_s2,
-                       bs, bm, bt, lp, reinterpret_cast<cx<R> *>(Xf));
+                       bs, bm, bt, lp, reinterpret_cast<cx<R> *>(Xf), plist);
+}
+
+static hipError_t launch_generic_any(const radsvd_plan *p, int flags, float inv_s2, float *best_score,
+                                     int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full, int n_list,
+                                     const int32_t *plist, hipStream_t s) {
+    switch (p->prec) {
+    case RADSVD_FP64:
+        launch_g<double, RADSVD_FP64>(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, n_list,
+                                      plist, s);
+        break;
+    case RADSVD_FP32:
+        launch_g<float, RADSVD_FP32>(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, n_list,
+                                     plist, s);
+        break;
+    case RADSVD_BF16:
+        launch_g<float, RADSVD_BF16>(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, n_list,
+                                     plist, s);
+        break;
+    default:
+        launch_g<float, RADSVD_BF16X3>(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, n_list,
+                                       plist, s);
+        break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_pairs_generic(const radsvd_plan *p, int flags, float inv_s2, float *best_score,
                                 int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full,
                                 hipStream_t s) {
-    switch (p->prec) {
-    case RADSVD_FP64:
-        launch_g<double, RADSVD_FP64>(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, s);
-        break;
-    case RADSVD_FP32:
-        launch_g<float, RADSVD_FP32>(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, s);
-        break;
-    case RADSVD_BF16:
-        launch_g<float, RADSVD_BF16>(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, s);
-        break;
-    default:
-        launch_g<float, RADSVD_BF16X3>(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full,
-                                       s);
-        break;
-    }
-    return hipGetLastError();
+    return launch_generic_any(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, 0, nullptr, s);
+}
+
+hipError_t launch_pairs_list(const radsvd_plan *p, int flags, float inv_s2, int n, const int32_t *pairs,
+                             float *best_score, int32_t *best_m, int32_t *best_t, float *lse_pair, void *X_full,
+                             hipStream_t s) {
+    return launch_generic_any(p, flags, inv_s2, best_score, best_m, best_t, lse_pair, X_full, n, pairs, s);
 }
 
 }  // namespace radsvd

@@ -89,6 +89,10 @@ def test_pairs_and_backward_argument_errors():
     assert lib.align_set_tile(None, 0) == 1
     assert lib.align_set_waves(None, 0) == 1
     assert lib.align_refine_rotation(None, None, None, 4, None, None, None) == 1
+    assert lib.align_pairs_list(None, 1, 1.0, 1, None, None, None, None, None, None, None) == 1
+    assert lib.align_top_targets(1, 1, None, 1, None, None) == 1
+    assert lib.align_top_targets(4, 4, None, 0, None, None) == 1
+    assert lib.align_landscape_metrics(0, 1, None, None, 0, None, None, None, None) == 1
     assert lib.align_set_waves(None, 8) == 1
     assert lib.align_batched_workspace(0) == 0
     assert lib.align_pairs_batched(None, 1, None, None, 0, None) == 1

@@ -462,3 +462,42 @@ def test_offgrid_landscape_shift_and_reality():
     Xr = oracle.landscape_offgrid(Ar, Br, np.array([0.05, 0.77, 3.3]))
     assert np.abs(Xr.imag).max() <= 1e-12 * np.abs(Xr).max()
     assert np.abs(oracle.rotate_ring(Br, 0.4).imag).max() <= 1e-12 * np.abs(Br).max()
+
+
+# --------------------------------------------------------------------------
+# landscape quality measures (section 3.5) and marching candidates (section 5)
+# --------------------------------------------------------------------------
+def test_landscape_metrics_against_library_routines():
+    import scipy.stats
+    rng = np.random.default_rng(31)
+    R = rng.standard_normal((7, 4, 32))
+    E = R + 0.3 * rng.standard_normal(R.shape)
+    rel, corr, f = oracle.landscape_metrics(E, R)
+    assert abs(rel - np.linalg.norm(E - R) / np.linalg.norm(R)) <= 1e-14
+    assert abs(corr - np.corrcoef(E.ravel(), R.ravel())[0, 1]) <= 1e-13
+    for p in range(7):
+        i = np.argmax(E[p].ravel())
+        want = scipy.stats.percentileofscore(R[p].ravel(), R[p].ravel()[i], kind="weak") / 100.0
+        assert abs(f[p] - want) <= 1e-15
+    # exact landscapes: no error, correlation 1, every optimum at the top
+    rel, corr, f = oracle.landscape_metrics(R, R)
+    assert rel == 0.0 and abs(corr - 1.0) <= 1e-14 and np.all(f == 1.0)
+    # an affine image of the truth: correlated perfectly, same optima
+    rel, corr, f = oracle.landscape_metrics(2.5 * R - 1.0, R)
+    assert abs(corr - 1.0) <= 1e-14 and np.all(f == 1.0) and rel > 1.0
+    # a reversed landscape picks the worst alignment: f = 1 / len
+    rel, corr, f = oracle.landscape_metrics(-R, R)
+    assert abs(corr + 1.0) <= 1e-14 and np.allclose(f, 1.0 / 128)
+    E[3, 1, 5] = np.nan
+    assert np.isnan(oracle.landscape_metrics(E, R)[2][3])
+
+
+def test_top_targets_order_ties_and_nan():
+    S = np.array([[0.5, 2.0, 2.0, np.nan, -1.0],
+                  [np.nan, np.nan, 1.0, np.nan, np.nan]])
+    c = oracle.top_targets(S, 4)
+    assert c.tolist() == [[1, 2, 0, 4], [2, -1, -1, -1]]
+    rng = np.random.default_rng(2)
+    S = rng.standard_normal((5, 40))
+    c = oracle.top_targets(S, 7)
+    assert np.array_equal(c, np.argsort(-S, axis=1, kind="stable")[:, :7])

@@ -210,7 +210,7 @@ def summarize_kernel_stats(path):
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = [f"{'kernel':72s} {'calls':>5s} {'avg ms':>9s} {'min ms':>9s} {'max ms':>9s}"]
     for r in rows:
-        name = r["Name"].replace("void ", "").replace("radsvd::", "")
+        name = r["Name"].replace("void ", "").replace("(anonymous namespace)::", "").replace("radsvd::", "")
         name = name[:name.index("(")] if "(" in name else name
         lines.append(f"{name[:72]:72s} {int(r['Calls']):5d} {float(r['AverageNs']) / 1e6:9.3f} "
                      f"{float(r['MinNs']) / 1e6:9.3f} {float(r['MaxNs']) / 1e6:9.3f}")

@@ -70,7 +70,7 @@ BwdLayout bwd_layout(const radsvd_plan *p) {
         return o;
     };
     L.off_phat = take(ch * per_img);                        // [chunk][Qs][NBT]
-    L.off_sum = take(ch * nb * sizeof(double));             // [chunk][nb]
+    L.off_sum = take(ch * NBT * sizeof(double));            // [chunk][nb] or [chunk][NBT]
     L.off_kappa = take(ch * sizeof(double));                // [chunk]
     L.off_gBt = take(NBT * Qs * H * sizeof(cx<double>));    // [NBT][Qs][H]
     L.off_gAt = take(na * Qs * H * sizeof(cx<double>));     // [na][Qs][H]
@@ -88,18 +88,19 @@ __device__ __forceinline__ cx<double> up(const cx<R> &v) {
     return cx<double>{(double)v.re, (double)v.im};
 }
 
-// re + i im += sum_h conj(x[h]) y[h] over one rank row; the loads of eight
-// ranks are issued together so that a row costs H/8 memory round trips
+// re + i im += sum_h conj(x[h st]) y[h st] over the ranks of one frequency
+// (generic layout [item][h][q]: rank stride st = Qs); the loads of eight ranks
+// are issued together so that a row costs H/8 memory round trips
 template <typename R>
-__device__ __forceinline__ void conj_dot(const cx<R> *__restrict__ x, const cx<R> *__restrict__ y, int H,
+__device__ __forceinline__ void conj_dot(const cx<R> *__restrict__ x, const cx<R> *__restrict__ y, int H, int st,
                                          double &re, double &im) {
     int h = 0;
     for (; h + 8 <= H; h += 8) {
         cx<R> xv[8], yv[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            xv[k] = x[h + k];
-            yv[k] = y[h + k];
+            xv[k] = x[(size_t)(h + k) * st];
+            yv[k] = y[(size_t)(h + k) * st];
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -109,7 +110,7 @@ __device__ __forceinline__ void conj_dot(const cx<R> *__restrict__ x, const cx<R
         }
     }
     for (; h < H; ++h) {
-        const cx<double> u = up(x[h]), v = up(y[h]);
+        const cx<double> u = up(x[(size_t)h * st]), v = up(y[(size_t)h * st]);
         re += u.re * v.re + u.im * v.im;
         im += u.re * v.im - u.im * v.re;
     }
@@ -188,8 +189,8 @@ __global__ __launch_bounds__(256) void k_bwd_phat(const cx<R> *__restrict__ Ag, 
                 for (int i = tid; i < nr * Qs; i += nt) {
                     const int rr = i / Qs, q = i - rr * Qs;
                     double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
-                    conj_dot(Aq + (size_t)q * H, Bt + ((size_t)(2 * rr) * Qs + q) * H, H, er, ei);
-                    if (2 * rr + 1 < tg) conj_dot(Aq + (size_t)q * H, Bt + ((size_t)(2 * rr + 1) * Qs + q) * H, H, orr, oi);
+                    conj_dot(Aq + q, Bt + (size_t)(2 * rr) * H * Qs + q, H, Qs, er, ei);
+                    if (2 * rr + 1 < tg) conj_dot(Aq + q, Bt + (size_t)(2 * rr + 1) * H * Qs + q, H, Qs, orr, oi);
                     if (q == 0 || q == M) ei = oi = 0.0;   // the real endpoints of a Hermitian spectrum
                     cx<double> *Z = X + (size_t)rr * Q;
                     Z[q] = cx<double>{er - oi, ei + orr};
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(256) void k_bwd_phat(const cx<R> *__restrict__ Ag, 
                 for (int i = tid; i < tg * Qs; i += nt) {
                     const int tt = i / Qs, q = i - tt * Qs;
                     double re = 0.0, im = 0.0;
-                    conj_dot(Aq + (size_t)q * H, Bt + ((size_t)tt * Qs + q) * H, H, re, im);
+                    conj_dot(Aq + q, Bt + (size_t)tt * H * Qs + q, H, Qs, re, im);
                     X[(size_t)tt * Q + q] = cx<double>{re, im};
                 }
             }
@@ -242,14 +243,171 @@ __global__ __launch_bounds__(256) void k_bwd_phat(const cx<R> *__restrict__ Ag, 
     }
 }
 
+
+// ---- the P-hat step for Hermitian inputs and Q a power of two (64 .. 512) ----
+//
+// One wavefront per row of two landscape columns c0 = 2 r, c1 = 2 r + 1 of one
+// image (columns are (target, translation) pairs): Z = S_e + i S_o (the two
+// columns' spectra, extended by S[Q-q] = conj S[q]) is transformed to
+// X_e + i X_o, Pt = exp(s X - c_a) is formed for both, Y = Pt_e + i Pt_o is
+// transformed back, and the two columns' Phat are unpacked from it (the same
+// algebra as k_bwd_phat).  The transforms run in the wave's own LDS rows with
+// no workgroup barrier: a decimation-in-frequency FFT (one radix-2 stage first
+// when log2 Q is odd, then radix-4 stages), whose output order is the
+// digit reversal below.  Each column's sum of Pt goes to psum[image][column].
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// position of frequency k in the output of wave_fft_dif<Q>
+template <int Q>
+__device__ __forceinline__ int wfft_pos(int k) {
+    constexpr int LOG = __builtin_ctz(Q);
+    constexpr int ND = LOG / 2;   // radix-4 digits
+    const int r2 = (LOG & 1) ? (k & 1) : 0;
+    int x = (LOG & 1) ? (k >> 1) : k, rev = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        rev = (rev << 2) | (x & 3);
+        x >>= 2;
+    }
+    return (LOG & 1) ? r2 * (Q / 2) + rev : rev;
+}
+// inverse of wfft_pos
+template <int Q>
+__device__ __forceinline__ int wfft_freq(int p) {
+    constexpr int LOG = __builtin_ctz(Q);
+    constexpr int ND = LOG / 2;
+    const int blk = (LOG & 1) ? p / (Q / 2) : 0;
+    int x = (LOG & 1) ? p % (Q / 2) : p, rev = 0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        rev = (rev << 2) | (x & 3);
+        x >>= 2;
+    }
+    return (LOG & 1) ? 2 * rev + blk : rev;
+}
+
+// in place: buf[wfft_pos<Q>(k)] = sum_j buf[j] W_Q^{jk}, W_Q = exp(-2 pi i / Q); tw[k] = W_Q^k
+template <int Q>
+__device__ __forceinline__ void wave_fft_dif(cx<double> *buf, const cx<double> *tw, int lane) {
+    constexpr int LOG = __builtin_ctz(Q);
+    int L = Q;
+    if constexpr (LOG & 1) {
+        for (int i = lane; i < Q / 2; i += 64) {
+            const cx<double> a = buf[i], b = buf[i + Q / 2];
+            buf[i] = cadd(a, b);
+            buf[i + Q / 2] = cmul(csub(a, b), tw[i]);
+        }
+        L = Q / 2;
+        wave_sync();
+    }
+    for (; L >= 4; L /= 4) {
+        const int qL = L / 4, stride = Q / L;
+        for (int u = lane; u < Q / 4; u += 64) {
+            const int blk = u / qL, i = u - blk * qL, base = blk * L + i;
+            const cx<double> x0 = buf[base], x1 = buf[base + qL], x2 = buf[base + 2 * qL], x3 = buf[base + 3 * qL];
+            const cx<double> t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3);
+            const cx<double> d = csub(x1, x3), t3 = {d.im, -d.re};   // -i (x1 - x3)
+            buf[base] = cadd(t0, t2);
+            buf[base + qL] = cmul(cadd(t1, t3), tw[i * stride]);
+            buf[base + 2 * qL] = cmul(csub(t0, t2), tw[2 * i * stride]);
+            buf[base + 3 * qL] = cmul(csub(t1, t3), tw[3 * i * stride]);
+        }
+        wave_sync();
+    }
+}
+
+template <typename R, int Q>
+__global__ __launch_bounds__(256) void k_bwd_phat_wave(const cx<R> *__restrict__ Ag, const cx<R> *__restrict__ Bg,
+                                                       int a0, int NBT, int rows_per_wg, int H, double s2,
+                                                       const float *__restrict__ lse_img,
+                                                       cx<double> *__restrict__ Phat, double *__restrict__ psum) {
+    constexpr int M = Q / 2, Qs = M + 1;
+    constexpr int KQ = (Qs + 63) / 64;   // spectrum entries per lane
+    __shared__ cx<double> tw[Q];
+    __shared__ cx<double> wbuf[4][2][Q];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int i = tid; i < Q; i += blockDim.x) {
+        double sn, cs;
+        sincospi(-2.0 * (double)i / (double)Q, &sn, &cs);
+        tw[i] = cx<double>{cs, sn};
+    }
+    __syncthreads();
+    const int al = blockIdx.y, a = a0 + al;
+    const double ca = (double)lse_img[a];
+    const cx<R> *Aq = Ag + (size_t)a * Qs * H;
+    cx<double> *b1 = wbuf[w][0], *b2 = wbuf[w][1];
+    const int n_rows = (NBT + 1) / 2;
+    const int r_begin = blockIdx.x * rows_per_wg, r_end = min(n_rows, r_begin + rows_per_wg);
+    for (int r = r_begin + w; r < r_end; r += 4) {
+        const int c0 = 2 * r, c1 = 2 * r + 1;
+        const bool two = c1 < NBT;
+        // spectra of the two columns at q = lane + 64 k, q <= M
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int q = lane + 64 * k;
+            if (q > M) continue;
+            double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
+            conj_dot(Aq + q, Bg + (size_t)c0 * H * Qs + q, H, Qs, er, ei);
+            if (two) conj_dot(Aq + q, Bg + (size_t)c1 * H * Qs + q, H, Qs, orr, oi);
+            if (q == 0 || q == M) ei = oi = 0.0;   // the real endpoints of a Hermitian spectrum
+            b1[q] = cx<double>{er - oi, ei + orr};
+            if (q > 0 && q < M) b1[Q - q] = cx<double>{er + oi, orr - ei};
+        }
+        wave_sync();
+        wave_fft_dif<Q>(b1, tw, lane);   // b1[pos(m)] = X_e[m] + i X_o[m]
+        double se = 0.0, so = 0.0;
+        for (int p = lane; p < Q; p += 64) {
+            const cx<double> x = b1[p];
+            const double pe = exp(s2 * x.re - ca);
+            const double po = two ? exp(s2 * x.im - ca) : 0.0;
+            se += pe;
+            so += po;
+            b2[wfft_freq<Q>(p)] = cx<double>{pe, po};   // natural order for the second transform
+        }
+        wave_sync();
+        wave_fft_dif<Q>(b2, tw, lane);   // b2[pos(q)] = sum_m Y[m] W^{qm}
+        cx<double> *out = Phat + (size_t)al * Qs * NBT;
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int q = lane + 64 * k;
+            if (q > M) continue;
+            const cx<double> y = b2[wfft_pos<Q>(q)], z = b2[wfft_pos<Q>(q == 0 ? 0 : Q - q)];
+            // Phat = conj of each column's transform
+            out[(size_t)q * NBT + c0] = cx<double>{0.5 * (y.re + z.re), -0.5 * (y.im - z.im)};
+            if (two) out[(size_t)q * NBT + c1] = cx<double>{0.5 * (y.im + z.im), -0.5 * (z.re - y.re)};
+        }
+        se = wave_sum(se);
+        so = wave_sum(so);
+        if (lane == 0) {
+            psum[(size_t)al * NBT + c0] = se;
+            if (two) psum[(size_t)al * NBT + c1] = so;
+        }
+        wave_sync();   // b1, b2 are rewritten by the next row
+    }
+}
+
 // kappa[a] = g[a] s / sum_{b,t,m} Pt  (= g[a] s exp(c_a - lse_img[a]), exact lse)
-__global__ void k_bwd_kappa(const double *__restrict__ psum, const float *__restrict__ glse, int a0, int na_chunk,
-                            int n_tgt, double s2, double *__restrict__ kappa) {
-    const int al = blockIdx.x * blockDim.x + threadIdx.x;
-    if (al >= na_chunk) return;
-    double sacc = 0.0;
-    for (int b = 0; b < n_tgt; ++b) sacc += psum[(size_t)al * n_tgt + b];
-    kappa[al] = (double)glse[a0 + al] * s2 / sacc;
+// (psum: per image, n_cols partial sums; one workgroup per image, each thread
+// a contiguous range, the ranges added in thread order: a fixed order)
+__global__ __launch_bounds__(256) void k_bwd_kappa(const double *__restrict__ psum, const float *__restrict__ glse,
+                                                   int a0, int n_cols, double s2, double *__restrict__ kappa) {
+    __shared__ double part[256];
+    const int al = blockIdx.x, tid = threadIdx.x;
+    const int per = (n_cols + 255) / 256, c0 = min(n_cols, per * tid), c1 = min(n_cols, c0 + per);
+    double acc = 0.0;
+    for (int c = c0; c < c1; ++c) acc += psum[(size_t)al * n_cols + c];
+    part[tid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double sacc = 0.0;
+        for (int x = 0; x < 256; ++x) sacc += part[x];
+        kappa[al] = (double)glse[a0 + al] * s2 / sacc;
+    }
 }
 
 // g_bt[bt][q][h] (+)= sum_{a in chunk} at[a][q][h] Phat[a][q][bt]; one workgroup
@@ -276,7 +434,7 @@ __global__ __launch_bounds__(256) void k_bwd_gBt(const cx<R> *__restrict__ Ag, c
         for (int e = tid; e < 16 * H; e += 256) {
             const int aa = e / H, h = e - aa * H;
             cx<double> v = {0.0, 0.0};
-            if (c0 + aa < na_chunk) v = up(Ag[((size_t)(a0 + c0 + aa) * Qs + q) * H + h]);
+            if (c0 + aa < na_chunk) v = up(Ag[((size_t)(a0 + c0 + aa) * H + h) * Qs + q]);
             sA[aa][h] = v;
         }
         __syncthreads();
@@ -338,7 +496,7 @@ __global__ __launch_bounds__(256) void k_bwd_gAt(const cx<R> *__restrict__ Bg, c
             cx<double> v = {0.0, 0.0};
             if (e < 16 * H) {
                 const int bb = e / H, h = e - bb * H;
-                if (c0 + bb < c_end) v = up(Bg[((size_t)(c0 + bb) * Qs + q) * H + h]);
+                if (c0 + bb < c_end) v = up(Bg[((size_t)(c0 + bb) * H + h) * Qs + q]);
             }
             rb[k] = v;
         }
@@ -546,14 +704,33 @@ hipError_t run_backward(const radsvd_plan *p, float inv_s2, const float *lse_img
                                            (int)sh_phat);
         if (e != hipSuccess) return e;
     }
+    // the wave-per-row P-hat kernel: Hermitian inputs, Q a power of two
+    const bool wave_path = p->herm && Q >= 64 && Q <= 512 && (Q & (Q - 1)) == 0;
     for (int a0 = 0; a0 < na; a0 += L.chunk) {
         const int ca = min(L.chunk, na - a0);
-        // targets per workgroup: amortise the set-up while keeping ~4k workgroups
-        const int nbw = max(1, min(16, (int)(((size_t)ca * nb) / 4096)));
-        hipLaunchKernelGGL(k_bwd_phat<R>, dim3((nb + nbw - 1) / nbw, ca), dim3(256), sh_phat, s, Ag, Bg, a0, nb, nbw,
-                           T, TG, H, Q, Qs, p->herm, (double)inv_s2, lse_img, Phat, psum);
-        hipLaunchKernelGGL(k_bwd_kappa, dim3((ca + 255) / 256), dim3(256), 0, s, psum, glse, a0, ca, nb,
-                           (double)inv_s2, kappa);
+        int n_cols;
+        if (wave_path) {
+            const int n_rows = (NBT + 1) / 2, rpw = 16;
+            const dim3 grid((n_rows + rpw - 1) / rpw, ca);
+            switch (Q) {
+            case 64: hipLaunchKernelGGL((k_bwd_phat_wave<R, 64>), grid, dim3(256), 0, s, Ag, Bg, a0, NBT, rpw, H,
+                                        (double)inv_s2, lse_img, Phat, psum); break;
+            case 128: hipLaunchKernelGGL((k_bwd_phat_wave<R, 128>), grid, dim3(256), 0, s, Ag, Bg, a0, NBT, rpw, H,
+                                         (double)inv_s2, lse_img, Phat, psum); break;
+            case 256: hipLaunchKernelGGL((k_bwd_phat_wave<R, 256>), grid, dim3(256), 0, s, Ag, Bg, a0, NBT, rpw, H,
+                                         (double)inv_s2, lse_img, Phat, psum); break;
+            default: hipLaunchKernelGGL((k_bwd_phat_wave<R, 512>), grid, dim3(256), 0, s, Ag, Bg, a0, NBT, rpw, H,
+                                        (double)inv_s2, lse_img, Phat, psum); break;
+            }
+            n_cols = NBT;
+        } else {
+            // targets per workgroup: amortise the set-up while keeping ~4k workgroups
+            const int nbw = max(1, min(16, (int)(((size_t)ca * nb) / 4096)));
+            hipLaunchKernelGGL(k_bwd_phat<R>, dim3((nb + nbw - 1) / nbw, ca), dim3(256), sh_phat, s, Ag, Bg, a0, nb,
+                               nbw, T, TG, H, Q, Qs, p->herm, (double)inv_s2, lse_img, Phat, psum);
+            n_cols = nb;
+        }
+        hipLaunchKernelGGL(k_bwd_kappa, dim3(ca), dim3(256), 0, s, psum, glse, a0, n_cols, (double)inv_s2, kappa);
         hipLaunchKernelGGL(k_bwd_gBt<R>, dim3((NBT + 63) / 64, Qs), dim3(256), 0, s, Ag, Phat, kappa, a0, ca, NBT,
                            Qs, H, a0 > 0 ? 1 : 0, gBt);
         if (want_U) {

@@ -125,8 +125,8 @@ struct radsvd_plan {
     // serve the plan, else on first need (the backward pass) by
     // ensure_generic_layout; g_ready says whether they hold the plan's values
     mutable int g_ready;
-    void *Ag;                         // [n_img][Qc][H] cx<R>        generic operands
-    void *Bg;                         // [n_tgt][T][Qc][H] cx<R>
+    void *Ag;                         // [n_img][H][Qc] cx<R>        generic operands (q fastest)
+    void *Bg;                         // [n_tgt][T][H][Qc] cx<R>
     void *Af;                         // fast operands (tile-major planes)
     void *Bf;
     size_t Af_bytes, Bf_bytes;

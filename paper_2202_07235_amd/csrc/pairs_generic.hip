@@ -105,21 +105,23 @@ __global__ __launch_bounds__(256) void k_pairs_generic(
         const cx<R> *Bb = Bg + ((size_t)b * T + t) * Qc * H;
         __syncthreads();
         for (int q = tid; q < Qc; q += nt) {
-            const cx<R> *x = Aa + (size_t)q * H;
-            const cx<R> *y = Bb + (size_t)q * H;
+            const cx<R> *x = Aa + q;   // rank h at x[h * Qc]
+            const cx<R> *y = Bb + q;
             cx<R> acc;
             if (PREC == RADSVD_FP64) {
                 R re = 0, im = 0;
                 for (int h = 0; h < H; ++h) {
-                    re += x[h].re * y[h].re + x[h].im * y[h].im;
-                    im += x[h].re * y[h].im - x[h].im * y[h].re;
+                    const cx<R> u = x[(size_t)h * Qc], v = y[(size_t)h * Qc];
+                    re += u.re * v.re + u.im * v.im;
+                    im += u.re * v.im - u.im * v.re;
                 }
                 acc = cx<R>{re, im};
             } else {
                 float re = 0.f, im = 0.f;
                 for (int h = 0; h < H; ++h) {
-                    cx<float> xf = {(float)x[h].re, (float)x[h].im};
-                    cx<float> yf = {(float)y[h].re, (float)y[h].im};
+                    const cx<R> u = x[(size_t)h * Qc], v = y[(size_t)h * Qc];
+                    cx<float> xf = {(float)u.re, (float)u.im};
+                    cx<float> yf = {(float)v.re, (float)v.im};
                     contract_term<PREC>(xf, yf, products, re, im);
                 }
                 acc = cx<R>{(R)re, (R)im};

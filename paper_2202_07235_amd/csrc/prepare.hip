@@ -94,7 +94,7 @@ __device__ void emit_rows(cx<R> *ybuf, int nrows, int h0, int n, int t, int T, i
         cx<R> v = ybuf[hh * Q + fft_pos(q, pl)];
         v.re *= scale;
         v.im *= scale;
-        if (G) G[(((size_t)n * T + t) * Qc + q) * H + h] = v;
+        if (G) G[(((size_t)n * T + t) * H + h) * Qc + q] = v;
         if (F) {
             // image n_in: Re row 2 n_in = [ar | ai], Im row 2 n_in + 1 = [-ai | ar];
             // target n_in: column [br | bi]
@@ -219,11 +219,11 @@ __device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_t
     typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
     const int tid = threadIdx.x, nt = blockDim.x;
     if (G) {
-        cx<float> *Gn = G + ((size_t)n * T + t) * Qc * H;
+        cx<float> *Gn = G + ((size_t)n * T + t) * H * Qc;   // [H][Qc]: q fastest
         for (int i = tid; i < Qc * nr; i += nt) {
-            const int q = i / nr, hh = i - q * nr;
+            const int hh = i / Qc, q = i - hh * Qc;
             const cx<float> v = yb[hh * Q + pos_tab[q]];
-            Gn[(size_t)q * H + h0 + hh] = cx<float>{v.re * scale, v.im * scale};
+            Gn[(size_t)(h0 + hh) * Qc + q] = cx<float>{v.re * scale, v.im * scale};
         }
     }
     if (!F) return;

@@ -9,7 +9,8 @@
 // landscape exactly.
 //
 // One wavefront per pair.  Lane l holds S[q] = sum_h conj(At[a][h][q]) Bt[b][t][h][q]
-// for q = l, l + 64, ... (generic operand layout); each candidate rotation
+// for q = l, l + 64, ... (generic operand layout [item][h][q], so a wave's loads
+// of one rank are contiguous); each candidate rotation
 // is a lane-local partial sum over those q and one cross-lane reduction.
 #include <math.h>
 
@@ -62,11 +63,12 @@ __global__ __launch_bounds__(256) void k_refine_rotation(const cx<R> *__restrict
             const int q = lane + 64 * i;
             R re = 0, im = 0;
             if (q < Qc) {
-                const cx<R> *x = Aa + (size_t)q * H;
-                const cx<R> *y = Bb + (size_t)q * H;
+                const cx<R> *x = Aa + q;   // rank h at x[h * Qc]
+                const cx<R> *y = Bb + q;
                 for (int h = 0; h < H; ++h) {
-                    re += x[h].re * y[h].re + x[h].im * y[h].im;
-                    im += x[h].re * y[h].im - x[h].im * y[h].re;
+                    const cx<R> u = x[(size_t)h * Qc], v = y[(size_t)h * Qc];
+                    re += u.re * v.re + u.im * v.im;
+                    im += u.re * v.im - u.im * v.re;
                 }
             }
             S[i] = cx<R>{re, im};

@@ -661,13 +661,20 @@ __global__ __launch_bounds__(256) void k_bwd_gU_part(const cx<double> *__restric
     }
 }
 
-// gU[r][h] = sum_n part[n][r][h] in item order (column h of U's [K][H] block)
-__global__ void k_bwd_gU_reduce(const double *__restrict__ part, int n_items, int K, int H, double *__restrict__ gU) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= K * H) return;
+// gU[r][h] = sum_n part[n][r][h]: one workgroup per 64 outputs, its four waves
+// take contiguous quarters of the items and add them in wave order (fixed)
+__global__ __launch_bounds__(256) void k_bwd_gU_reduce(const double *__restrict__ part, int n_items, int K, int H,
+                                                       double *__restrict__ gU) {
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lane;
+    const int per = (n_items + 3) / 4, n0 = min(n_items, per * w), n1 = min(n_items, n0 + per);
     double s = 0.0;
-    for (int n = 0; n < n_items; ++n) s += part[(size_t)n * K * H + o];
-    gU[o] = s;
+    if (o < K * H)
+        for (int n = n0; n < n1; ++n) s += part[(size_t)n * K * H + o];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && o < K * H) gU[o] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 template <typename R>
@@ -759,7 +766,7 @@ hipError_t run_backward(const radsvd_plan *p, float inv_s2, const float *lse_img
         hipLaunchKernelGGL(k_bwd_gU_part<R>, dim3(nb), dim3(256), 0, s, gBpsi,
                            reinterpret_cast<const cx<R> *>(p->B_polar), p->d_eta, ph, K, H, Q, T,
                            part + (size_t)na * K * H);
-        hipLaunchKernelGGL(k_bwd_gU_reduce, dim3((K * H + 255) / 256), dim3(256), 0, s, part, na + nb, K, H, gU_out);
+        hipLaunchKernelGGL(k_bwd_gU_reduce, dim3((K * H + 63) / 64), dim3(256), 0, s, part, na + nb, K, H, gU_out);
     }
     return hipGetLastError();
 }

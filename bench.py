@@ -48,6 +48,8 @@ def parse():
                          "3 only the two leading terms")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of N_A and N_B (for quick local runs; 1.0 = the full workload)")
+    ap.add_argument("--only", choices=["plain", "batching", "differentiation"], default=None,
+                    help="run only that other workload and print its record as one JSON line")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (plain FP32 batch, batching, differentiation)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the same-GPU comparison runs (FP32, bf16x3 with 3 products)")
@@ -571,6 +573,11 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.only:
+        fn = {"plain": plain_workload, "batching": batching_workload,
+              "differentiation": differentiation_workload}[a.only]
+        print(json.dumps(fn(rs, synth, torch)))
+        return 0
     cfg = synth.config("precision")
     if a.scale != 1.0:
         cfg = synth.config("precision", n_img=max(16, int(cfg.n_img * a.scale)),

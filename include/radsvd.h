@@ -342,6 +342,98 @@ radsvd_status align_set_waves(radsvd_plan *plan, int waves);
 
 void align_plan_destroy(radsvd_plan *plan);
 
+/* ======================================================================== */
+/* Volume alignment with principal volumes (paper section 4)                */
+/* ======================================================================== */
+/*
+ * Volumes are given by their spherical-harmonic coefficients on K spherical
+ * shells of radius k_r in frequency space (section 4.3): complex
+ * [n][K][(L+1)^2], index l^2 + l + m for degree l = 0..L and order
+ * m = -l..l, orthonormal harmonics with the Condon-Shortley phase; FP64
+ * plans take complex128, FP32 plans complex64.  w_r weights the shells for
+ * the integral over k^2 dk.
+ *
+ * A rotation tau = (gamma, beta, alpha) is R_z(alpha) R_y(beta) R_z(gamma)
+ * (section 4.1); its action on coefficients is
+ * B_l^m1 -> sum_m2 e^{-i m1 alpha} d^l_{m1 m2}(beta) e^{-i m2 gamma} B_l^m2 with
+ * d^l(beta) = exp(-i beta J_y) (section 4.2).  The landscape is
+ * X[a][b][ib][m1'][m2'] = <A_a, R_tau B_b> at tau = (2 pi m2'/M, beta[ib], 2 pi m1'/M),
+ * M = 2L + 1, evaluated by the steps of section 4.9:
+ *   step 1   Xt_l(m1, m2)   = sum_{h < H_C} conj([u_h^T A]_l^m1) [u_h^T B]_l^m2
+ *   step 1b  Y_j(m1, m2)    = sum_l V[l][j] Xt_l(m1, m2),  j < H_D
+ *   step 2   Xhat(m1, m2)   = sum_j [v_j^T d]_{m1 m2}(beta) Y_j(m1, m2)
+ *   step 3   X(m1', m2')    = sum_{m1, m2} e^{-2 pi i m1 m1'/M} e^{-2 pi i m2 m2'/M} Xhat(m1, m2)
+ * with the principal shells [u_h^T A]_l^m = sum_r U[r][h] sqrt(w_r) A_l^m(k_r)
+ * (section 4.5).  U holds the eigenvectors of the radial kernel
+ * C_rr' = sqrt(w_r w_r') Re sum_{l >= 1, m} conj(B_l^m(k_r)) B_l^m(k_r') (section 4.6)
+ * and V those of the degree kernel
+ * D_ll' = Re sum_r w_r sum_m conj(B_l^m(k_r)) B_l'^m(k_r), l, l' >= 1 (section 4.8),
+ * both averaged over the targets, by descending eigenvalue.  At H_C = K and
+ * H_D = L + 1 the landscape is the full sum over shells and degrees of
+ * section 4.4.
+ */
+typedef struct {
+    int K;                  /* shells, 2..128                                            */
+    int L;                  /* largest degree: 1..64 (FP32), 1..48 (FP64); M = 2L+1       */
+    int H_C;                /* radial rank, 1..K                                          */
+    int H_D;                /* degree rank, 1..L+1                                        */
+    int n_beta;             /* interior angles, 1..256                                    */
+    const double *w;        /* host [K]: shell weights for \int g(k) k^2 dk, finite, > 0 */
+    const double *beta;     /* host [n_beta]: interior angles beta (radians, finite)      */
+    radsvd_precision prec;  /* RADSVD_FP64 or RADSVD_FP32 (contraction and I/O type)      */
+} radsvd_vol_problem;
+
+typedef struct radsvd_vol_plan radsvd_vol_plan;   /* opaque host metadata */
+
+/* Workspace bytes for vol_prepare (0 on invalid arguments, see
+ * radsvd_last_error).  It holds the kernels, U and V, the principal shells of
+ * every volume and target, the principal-degree Wigner tables
+ * [n_beta][H_D][M][M] and the per-pair intermediate of steps 1-1b for a
+ * block of pairs (at most 1 GiB; vol_align walks the pairs block by block). */
+size_t vol_prepare_workspace(const radsvd_vol_problem *prob, int n_vol, int n_tgt);
+
+/* Precompute (section 4.9, steps 1-7 of the operation count): C and D from
+ * the targets, their eigenvectors (FP64 Jacobi on the GPU), the principal
+ * shells of volumes and targets, and the tables [v_j^T d](beta) (Wigner-d by
+ * its three-term recurrence in l, in FP64).
+ *   A_sh  : device [n_vol][K][(L+1)^2] complex, the volumes to align;
+ *   B_sh  : device [n_tgt][K][(L+1)^2] complex, the targets (they define C, D);
+ *   U_in  : device [K][H_C] FP64 or NULL (NULL: from C);
+ *   V_in  : device [L+1][H_D] FP64 or NULL (NULL: from D);
+ *   ws    : caller-owned device workspace of vol_prepare_workspace bytes,
+ *           256-byte aligned; it must outlive every call with the plan.
+ * A_sh, B_sh, U_in and V_in are read by work enqueued on `stream` only and may
+ * be released once that work is done.  n_vol, n_tgt in [1, 2^20] with
+ * n_vol * n_tgt <= 2^31.  Errors: RADSVD_ERR_INVALID_ARG (sizes, NULL or
+ * misaligned pointers: 16 bytes for coefficients, 8 for U_in, V_in),
+ * RADSVD_ERR_WORKSPACE, RADSVD_ERR_DEVICE. */
+radsvd_status vol_prepare(const radsvd_vol_problem *prob, int n_vol, const void *A_sh, int n_tgt,
+                          const void *B_sh, const double *U_in, const double *V_in, void *ws,
+                          size_t ws_bytes, void *stream, radsvd_vol_plan **out);
+
+/* The landscape of every (volume, target) pair over (beta, alpha, gamma).
+ *   RADSVD_OUT_BEST : best_score[a][b] = max Re X (f32) and
+ *                     best_idx[a][b] = {ib, m1', m2'} (int32) at the first
+ *                     maximum in the order (ib, m1', m2'); a pair with a NaN
+ *                     anywhere in its landscape gets NaN and {-1, -1, -1};
+ *   RADSVD_OUT_FULL : X_full [n_vol][n_tgt][n_beta][M][M] complex (plan's I/O type).
+ * out_flags is a non-empty combination of these two.  Pairs are processed in
+ * blocks; calls with one plan on several streams share its workspace and
+ * race.  Errors: RADSVD_ERR_INVALID_ARG (flags, NULL or misaligned outputs:
+ * 4 bytes for BEST, 8 or 16 for FULL), RADSVD_ERR_DEVICE. */
+radsvd_status vol_align(const radsvd_vol_plan *plan, int out_flags, float *best_score, int32_t *best_idx,
+                        void *X_full, void *stream);
+
+/* Copy U (device [K][K]), the eigenvalues of C ([K]), V ([L+1][L+1], column
+ * j = eigenvector j) and the eigenvalues of D ([L+1]), all FP64 and
+ * descending, into caller buffers (any may be NULL).  With a caller-supplied
+ * U_in (V_in) only its first H_C (H_D) columns are defined and the
+ * eigenvalues are NaN. */
+radsvd_status vol_get_UV(const radsvd_vol_plan *plan, double *U_dev, double *lamC_dev, double *V_dev,
+                         double *lamD_dev, void *stream);
+
+void vol_plan_destroy(radsvd_vol_plan *plan);
+
 /* Description of the last error of the calling thread ("" if none). */
 const char *radsvd_last_error(void);
 

@@ -98,6 +98,16 @@ def _load():
     L.align_set_waves.argtypes = [vp, i32]
     L.align_set_waves.restype = i32
     L.align_plan_destroy.argtypes = [vp]
+    L.vol_prepare_workspace.argtypes = [vp, i32, i32]
+    L.vol_prepare_workspace.restype = sz
+    L.vol_prepare.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+    L.vol_prepare.restype = i32
+    L.vol_align.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.vol_align.restype = i32
+    L.vol_get_UV.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.vol_get_UV.restype = i32
+    L.vol_plan_destroy.argtypes = [vp]
+    L.vol_plan_destroy.restype = None
     L.align_plan_destroy.restype = None
     L.radsvd_last_error.argtypes = []
     L.radsvd_last_error.restype = ctypes.c_char_p

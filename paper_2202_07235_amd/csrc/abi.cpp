@@ -6,10 +6,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "common.h"
 #include "internal.h"
+#include "volume.h"
 
 using namespace radsvd;
 
@@ -471,5 +473,200 @@ radsvd_status align_set_waves(radsvd_plan *p, int waves) {
 }
 
 void align_plan_destroy(radsvd_plan *p) { delete p; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// volume alignment (paper section 4)
+// ---------------------------------------------------------------------------
+namespace {
+
+int vol_max_L(radsvd_precision prec) { return prec == RADSVD_FP64 ? kVolMaxL64 : kVolMaxL32; }
+
+radsvd_status validate_vol(const radsvd_vol_problem *pr) {
+    if (!pr) return fail(RADSVD_ERR_INVALID_ARG, "problem is NULL");
+    if (pr->prec != RADSVD_FP64 && pr->prec != RADSVD_FP32)
+        return fail(RADSVD_ERR_INVALID_ARG, "prec=%d: volume plans take RADSVD_FP64 or RADSVD_FP32", pr->prec);
+    if (pr->K < 2 || pr->K > kVolMaxK) return fail(RADSVD_ERR_INVALID_ARG, "K=%d outside [2, %d]", pr->K, kVolMaxK);
+    const int lmax = vol_max_L(pr->prec);
+    if (pr->L < 1 || pr->L > lmax) return fail(RADSVD_ERR_INVALID_ARG, "L=%d outside [1, %d]", pr->L, lmax);
+    if (pr->H_C < 1 || pr->H_C > pr->K) return fail(RADSVD_ERR_INVALID_ARG, "H_C=%d outside [1, %d]", pr->H_C, pr->K);
+    if (pr->H_D < 1 || pr->H_D > pr->L + 1)
+        return fail(RADSVD_ERR_INVALID_ARG, "H_D=%d outside [1, %d]", pr->H_D, pr->L + 1);
+    if (pr->n_beta < 1 || pr->n_beta > kVolMaxBeta)
+        return fail(RADSVD_ERR_INVALID_ARG, "n_beta=%d outside [1, %d]", pr->n_beta, kVolMaxBeta);
+    if (!pr->w || !pr->beta) return fail(RADSVD_ERR_INVALID_ARG, "w or beta is NULL");
+    for (int r = 0; r < pr->K; ++r)
+        if (!(pr->w[r] > 0.0) || !isfinite(pr->w[r]))
+            return fail(RADSVD_ERR_INVALID_ARG, "w[%d] must be finite and > 0", r);
+    for (int i = 0; i < pr->n_beta; ++i)
+        if (!isfinite(pr->beta[i])) return fail(RADSVD_ERR_INVALID_ARG, "beta[%d] not finite", i);
+    return RADSVD_OK;
+}
+
+radsvd_status validate_vol_counts(int n_vol, int n_tgt) {
+    if (n_vol < 1 || n_vol > (1 << 20) || n_tgt < 1 || n_tgt > (1 << 20))
+        return fail(RADSVD_ERR_INVALID_ARG, "n_vol=%d / n_tgt=%d outside [1, 2^20]", n_vol, n_tgt);
+    if ((long long)n_vol * n_tgt > (1LL << 31))
+        return fail(RADSVD_ERR_INVALID_ARG, "n_vol * n_tgt = %lld above 2^31", (long long)n_vol * n_tgt);
+    return RADSVD_OK;
+}
+
+struct VolLayout {
+    size_t off_w, off_beta, off_C, off_U, off_lamC, off_logC, off_D, off_V, off_lamD, off_logD, off_As, off_Bs,
+        off_Vd, off_Y, off_pv, off_pi, total;
+    int chunk;
+};
+
+VolLayout make_vol_layout(const radsvd_vol_problem *pr, int n_vol, int n_tgt) {
+    VolLayout Lo{};
+    const size_t R = pr->prec == RADSVD_FP64 ? 8 : 4, CX = 2 * R;
+    const int K = pr->K, L1 = pr->L + 1, M = 2 * pr->L + 1, NC = L1 * L1;
+    const size_t MM = (size_t)M * M;
+    const long long n_pairs = (long long)n_vol * n_tgt;
+    const size_t per_pair = (size_t)pr->H_D * MM * CX;
+    long long chunk = (long long)(kVolChunkBytes / per_pair);
+    chunk = std::max<long long>(1, std::min<long long>(chunk, kVolMaxChunk));
+    chunk = std::min(chunk, n_pairs);
+    Lo.chunk = (int)chunk;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    Lo.off_w = take(K * 8);
+    Lo.off_beta = take((size_t)pr->n_beta * 8);
+    Lo.off_C = take((size_t)K * K * 8);
+    Lo.off_U = take((size_t)K * K * 8);
+    Lo.off_lamC = take(K * 8);
+    Lo.off_logC = take(eig_log_bytes(K));
+    Lo.off_D = take((size_t)L1 * L1 * 8);
+    Lo.off_V = take((size_t)L1 * L1 * 8);
+    Lo.off_lamD = take(L1 * 8);
+    Lo.off_logD = take(eig_log_bytes(L1));
+    Lo.off_As = take((size_t)n_vol * pr->H_C * NC * CX);
+    Lo.off_Bs = take((size_t)n_tgt * pr->H_C * NC * CX);
+    Lo.off_Vd = take((size_t)pr->n_beta * pr->H_D * MM * R);
+    Lo.off_Y = take((size_t)chunk * per_pair);
+    Lo.off_pv = take((size_t)chunk * pr->n_beta * 8);
+    Lo.off_pi = take((size_t)chunk * pr->n_beta * 4);
+    Lo.total = off;
+    return Lo;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vol_prepare_workspace(const radsvd_vol_problem *prob, int n_vol, int n_tgt) {
+    g_err[0] = 0;
+    if (validate_vol(prob) != RADSVD_OK || validate_vol_counts(n_vol, n_tgt) != RADSVD_OK) return 0;
+    return make_vol_layout(prob, n_vol, n_tgt).total;
+}
+
+radsvd_status vol_prepare(const radsvd_vol_problem *prob, int n_vol, const void *A_sh, int n_tgt, const void *B_sh,
+                          const double *U_in, const double *V_in, void *ws, size_t ws_bytes, void *stream,
+                          radsvd_vol_plan **out) {
+    g_err[0] = 0;
+    radsvd_status st = validate_vol(prob);
+    if (st != RADSVD_OK) return st;
+    if (!out) return fail(RADSVD_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    st = validate_vol_counts(n_vol, n_tgt);
+    if (st != RADSVD_OK) return st;
+    if (!A_sh || !B_sh) return fail(RADSVD_ERR_INVALID_ARG, "A_sh or B_sh is NULL");
+    if (!aligned(A_sh, 16) || !aligned(B_sh, 16))
+        return fail(RADSVD_ERR_INVALID_ARG, "A_sh / B_sh must be 16-byte aligned");
+    if ((U_in && !aligned(U_in, 8)) || (V_in && !aligned(V_in, 8)))
+        return fail(RADSVD_ERR_INVALID_ARG, "U_in / V_in must be 8-byte aligned");
+    const VolLayout Lo = make_vol_layout(prob, n_vol, n_tgt);
+    if (!ws) return fail(RADSVD_ERR_WORKSPACE, "workspace is NULL");
+    if (!aligned(ws, 256)) return fail(RADSVD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < Lo.total)
+        return fail(RADSVD_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, Lo.total);
+    radsvd_vol_plan *p = new (std::nothrow) radsvd_vol_plan();
+    if (!p) return fail(RADSVD_ERR_DEVICE, "host allocation failed");
+    p->K = prob->K;
+    p->L = prob->L;
+    p->M = 2 * prob->L + 1;
+    p->NC = (prob->L + 1) * (prob->L + 1);
+    p->HC = prob->H_C;
+    p->HD = prob->H_D;
+    p->n_beta = prob->n_beta;
+    p->prec = prob->prec;
+    p->n_vol = n_vol;
+    p->n_tgt = n_tgt;
+    p->chunk = Lo.chunk;
+    p->user_U = U_in != nullptr;
+    p->user_V = V_in != nullptr;
+    p->ws = reinterpret_cast<char *>(ws);
+    p->ws_bytes = ws_bytes;
+    char *w = p->ws;
+    p->w = reinterpret_cast<double *>(w + Lo.off_w);
+    p->beta = reinterpret_cast<double *>(w + Lo.off_beta);
+    p->C = reinterpret_cast<double *>(w + Lo.off_C);
+    p->U = reinterpret_cast<double *>(w + Lo.off_U);
+    p->lamC = reinterpret_cast<double *>(w + Lo.off_lamC);
+    p->logC = w + Lo.off_logC;
+    p->D = reinterpret_cast<double *>(w + Lo.off_D);
+    p->V = reinterpret_cast<double *>(w + Lo.off_V);
+    p->lamD = reinterpret_cast<double *>(w + Lo.off_lamD);
+    p->logD = w + Lo.off_logD;
+    p->As = w + Lo.off_As;
+    p->Bs = w + Lo.off_Bs;
+    p->Vd = w + Lo.off_Vd;
+    p->Y = w + Lo.off_Y;
+    p->part_val = reinterpret_cast<double *>(w + Lo.off_pv);
+    p->part_idx = reinterpret_cast<int32_t *>(w + Lo.off_pi);
+    VolGrid g;
+    memset(&g, 0, sizeof(g));
+    g.K = prob->K;
+    g.n_beta = prob->n_beta;
+    for (int r = 0; r < prob->K; ++r) g.w[r] = prob->w[r];
+    for (int i = 0; i < prob->n_beta; ++i) g.beta[i] = prob->beta[i];
+    const hipError_t e = vol_launch_prepare(p, g, A_sh, B_sh, U_in, V_in, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) {
+        delete p;
+        return dev_check(e, "vol_prepare launch");
+    }
+    *out = p;
+    return RADSVD_OK;
+}
+
+radsvd_status vol_align(const radsvd_vol_plan *p, int flags, float *best_score, int32_t *best_idx, void *X_full,
+                        void *stream) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    if (flags <= 0 || (flags & ~(RADSVD_OUT_BEST | RADSVD_OUT_FULL)))
+        return fail(RADSVD_ERR_INVALID_ARG, "out_flags=%d invalid (RADSVD_OUT_BEST and/or RADSVD_OUT_FULL)", flags);
+    if ((flags & RADSVD_OUT_BEST) && (!best_score || !best_idx))
+        return fail(RADSVD_ERR_INVALID_ARG, "BEST output pointers must be non-NULL");
+    if ((flags & RADSVD_OUT_BEST) && (!aligned(best_score, 4) || !aligned(best_idx, 4)))
+        return fail(RADSVD_ERR_INVALID_ARG, "BEST outputs must be 4-byte aligned");
+    if ((flags & RADSVD_OUT_FULL) && !X_full) return fail(RADSVD_ERR_INVALID_ARG, "FULL output X_full must be non-NULL");
+    if ((flags & RADSVD_OUT_FULL) && !aligned(X_full, p->prec == RADSVD_FP64 ? 16 : 8))
+        return fail(RADSVD_ERR_INVALID_ARG, "X_full misaligned");
+    const hipError_t e = vol_launch_align(p, flags, (flags & RADSVD_OUT_BEST) ? best_score : nullptr,
+                                          (flags & RADSVD_OUT_BEST) ? best_idx : nullptr, X_full,
+                                          reinterpret_cast<hipStream_t>(stream));
+    return dev_check(e, "vol_align launch");
+}
+
+radsvd_status vol_get_UV(const radsvd_vol_plan *p, double *U_dev, double *lamC_dev, double *V_dev, double *lamD_dev,
+                         void *stream) {
+    g_err[0] = 0;
+    if (!p) return fail(RADSVD_ERR_INVALID_ARG, "plan is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t L1 = p->L + 1;
+    hipError_t e = hipSuccess;
+    if (U_dev) e = hipMemcpyAsync(U_dev, p->U, (size_t)p->K * p->K * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && lamC_dev) e = hipMemcpyAsync(lamC_dev, p->lamC, (size_t)p->K * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && V_dev) e = hipMemcpyAsync(V_dev, p->V, L1 * L1 * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && lamD_dev) e = hipMemcpyAsync(lamD_dev, p->lamD, L1 * 8, hipMemcpyDeviceToDevice, s);
+    return dev_check(e, "vol_get_UV copy");
+}
+
+void vol_plan_destroy(radsvd_vol_plan *p) { delete p; }
 
 }  // extern "C"

@@ -212,16 +212,17 @@ size_t eig_log_bytes(int K) {
     return (size_t)kEigMaxSweeps * (KP - 1) * (KP / 2) * sizeof(Rot);
 }
 
-hipError_t launch_eig(radsvd_plan *p, hipStream_t s) {
-    const int K = p->K;
+hipError_t launch_eig_raw(const double *C, int K, void *log, double *U, double *lam, hipStream_t s) {
     const int KP = (K + 1) & ~1;
     const size_t shmem = (size_t)KP * (KP + 1) * sizeof(double);
     hipError_t e = hipFuncSetAttribute((const void *)k_jacobi,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), shmem, s, p->C, K, KP,
-                       reinterpret_cast<Rot *>(p->eig_log), kEigMaxSweeps, p->U, p->lam);
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), shmem, s, C, K, KP, reinterpret_cast<Rot *>(log),
+                       kEigMaxSweeps, U, lam);
     return hipGetLastError();
 }
+
+hipError_t launch_eig(radsvd_plan *p, hipStream_t s) { return launch_eig_raw(p->C, p->K, p->eig_log, p->U, p->lam, s); }
 
 }  // namespace radsvd

@@ -1,0 +1,489 @@
+// Rotational volume alignment with principal volumes (paper section 4).
+//
+// Precompute (section 4.9, items 1-7 of its operation count):
+//   k_vol_C       radial kernel C_rr' = sqrt(w_r w_r') Re sum_{l>=1,m} conj(B_l^m(k_r)) B_l^m(k_r')
+//                 averaged over the targets (section 4.6);
+//   k_vol_D       degree kernel D_ll' = Re sum_r w_r sum_m conj(B_l^m(k_r)) B_l'^m(k_r),
+//                 l, l' >= 1, averaged over the targets (section 4.8);
+//   (Jacobi)      their eigenvectors, descending (the FP64 solver of C for images);
+//   k_vol_shells  principal shells [u_h^T A]_l^m = sum_r U[r][h] sqrt(w_r) A_l^m(k_r) (section 4.5);
+//   k_vol_wigner  [v_j^T d]_{m1 m2}(beta) = sum_l V[l][j] d^l_{m1 m2}(beta) on the periodic
+//                 M x M order grid, with d^l by its three-term recurrence in l from
+//                 the closed form at l = max(|m1|, |m2|) (section 4.7), in FP64.
+// Per pair (section 4.9, steps 1, 1b, 2, 3):
+//   k_vol_step1   Y_j(m1, m2) = sum_l V[l][j] sum_h conj(As[h]_l^m1) Bs[h]_l^m2;
+//   k_vol_land    one workgroup per (pair, beta): Xhat = sum_j [v_j^T d](beta) Y_j in
+//                 LDS, then the 2-D transform over the orders as two passes of
+//                 length-M DFTs (M = 2L + 1 is odd, so a direct DFT with an LDS
+//                 twiddle table; each wave owns whole rows, then whole columns),
+//                 then the best Re X of the angle and the FULL write;
+//   k_vol_best    per pair, the best over the angles.
+#include <math.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "internal.h"
+#include "volume.h"
+
+namespace radsvd {
+
+namespace {
+
+__device__ __forceinline__ void vol_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// sum over a 256-thread workgroup, the same value in every thread; fixed order
+__device__ double vol_block_sum(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return t;
+}
+
+__global__ void k_vol_setup(VolGrid g, double *w, double *beta) {
+    for (int i = threadIdx.x; i < g.K; i += blockDim.x) w[i] = g.w[i];
+    for (int i = threadIdx.x; i < g.n_beta; i += blockDim.x) beta[i] = g.beta[i];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_vol_C(const cx<R> *__restrict__ B, int n_tgt, int K, int NC,
+                                               const double *__restrict__ w, double *__restrict__ C) {
+    __shared__ double red[4];
+    const int r = blockIdx.x, rp = blockIdx.y;
+    if (rp < r) return;   // uniform in the workgroup
+    const long long per = NC - 1;   // every (l, m) with l >= 1
+    const long long n = (long long)n_tgt * per;
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < n; i += 256) {
+        const long long b = i / per;
+        const int c = 1 + (int)(i - b * per);
+        const cx<R> x = B[((size_t)b * K + r) * NC + c], y = B[((size_t)b * K + rp) * NC + c];
+        acc += (double)x.re * (double)y.re + (double)x.im * (double)y.im;
+    }
+    const double s = vol_block_sum(acc, red) * (sqrt(w[r]) * sqrt(w[rp])) / (double)n_tgt;
+    if (threadIdx.x == 0) {
+        C[(size_t)r * K + rp] = s;
+        C[(size_t)rp * K + r] = s;
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_vol_D(const cx<R> *__restrict__ B, int n_tgt, int K, int NC, int L,
+                                               const double *__restrict__ w, double *__restrict__ D) {
+    __shared__ double red[4];
+    const int l = blockIdx.x, lp = blockIdx.y;   // l <= lp: the orders |m| <= l
+    if (lp < l) return;
+    double s = 0.0;
+    if (l >= 1) {
+        const int nm = 2 * l + 1;
+        const long long n = (long long)n_tgt * K * nm;
+        double acc = 0.0;
+        for (long long i = threadIdx.x; i < n; i += 256) {
+            const long long br = i / nm;
+            const int m = (int)(i - br * nm) - l;
+            const int r = (int)(br % K);
+            const cx<R> *row = B + (size_t)br * NC;   // [b][r]
+            const cx<R> x = row[l * l + l + m], y = row[lp * lp + lp + m];
+            acc += w[r] * ((double)x.re * (double)y.re + (double)x.im * (double)y.im);
+        }
+        s = vol_block_sum(acc, red) / (double)n_tgt;
+    }
+    if (threadIdx.x == 0) {
+        D[(size_t)l * (L + 1) + lp] = s;
+        D[(size_t)lp * (L + 1) + l] = s;
+    }
+}
+
+// caller-supplied principal vectors [n][H] into the [n][n] column layout
+__global__ void k_vol_user_mat(const double *__restrict__ Uin, int n, int H, double *__restrict__ U,
+                               double *__restrict__ lam) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * n; i += gridDim.x * blockDim.x) {
+        const int r = i / n, c = i - r * n;
+        U[i] = c < H ? Uin[(size_t)r * H + c] : 0.0;
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        lam[i] = __builtin_nan("");
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_vol_shells(const cx<R> *__restrict__ X, int n, int K, int NC,
+                                                    const double *__restrict__ U, int H,
+                                                    const double *__restrict__ w, cx<R> *__restrict__ out) {
+    const int nbx = (NC + 255) / 256;
+    const long long v = blockIdx.x / nbx;
+    const int i = (int)(blockIdx.x - v * nbx) * 256 + threadIdx.x;
+    const int h = blockIdx.y;
+    if (i >= NC) return;
+    double re = 0.0, im = 0.0;
+    for (int r = 0; r < K; ++r) {
+        const double u = U[(size_t)r * K + h] * sqrt(w[r]);
+        const cx<R> x = X[((size_t)v * K + r) * NC + i];
+        re += u * (double)x.re;
+        im += u * (double)x.im;
+    }
+    out[((size_t)v * H + h) * NC + i] = cx<R>{(R)re, (R)im};
+}
+
+// d^l_{ab}(beta) at l = max(|a|, |b|), from c = cos(beta/2), s = sin(beta/2):
+// the one surviving term of the finite sum for d^l
+__device__ double wigner_seed(int l, int a, int b, double c, double s) {
+    int e, pc, ps;
+    double sgn = 1.0;
+    if (a == l) {
+        e = b;
+        pc = l + b;
+        ps = l - b;
+        if ((l - b) & 1) sgn = -1.0;
+    } else if (a == -l) {
+        e = b;
+        pc = l - b;
+        ps = l + b;
+    } else if (b == l) {
+        e = a;
+        pc = l + a;
+        ps = l - a;
+    } else {   // b == -l
+        e = a;
+        pc = l - a;
+        ps = l + a;
+        if ((a + l) & 1) sgn = -1.0;
+    }
+    // sqrt(binomial(2l, l + e)) = prod_{i=1}^{l-|e|} sqrt((l + |e| + i) / i)
+    const int ae = e < 0 ? -e : e;
+    double v = sgn;
+    for (int i = 1; i <= l - ae; ++i) v *= sqrt((double)(l + ae + i) / (double)i);
+    for (int i = 0; i < pc; ++i) v *= c;
+    for (int i = 0; i < ps; ++i) v *= s;
+    return v;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_vol_wigner(const double *__restrict__ beta, int n_beta, int L, int M,
+                                                    const double *__restrict__ V, int HD, R *__restrict__ Vd) {
+    const long long MM = (long long)M * M;
+    const long long total = (long long)n_beta * HD * MM;
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int im2 = (int)(i % M);
+    long long t = i / M;
+    const int im1 = (int)(t % M);
+    t /= M;
+    const int j = (int)(t % HD);
+    const int ib = (int)(t / HD);
+    const int a = im1 <= L ? im1 : im1 - M, b = im2 <= L ? im2 : im2 - M;
+    const int l0 = std::max(a < 0 ? -a : a, b < 0 ? -b : b);
+    double sb, cb;
+    sincos(0.5 * beta[ib], &sb, &cb);
+    const double x = cos(beta[ib]);
+    const int L1 = L + 1;
+    double dprev = 0.0, d = wigner_seed(l0, a, b, cb, sb);
+    double acc = V[(size_t)l0 * L1 + j] * d;
+    int l = l0;
+    if (l0 == 0) {   // d^1_00 = cos(beta); the recurrence below needs l >= 1
+        dprev = d;
+        d = x;
+        l = 1;
+        acc += V[(size_t)L1 + j] * d;
+    }
+    const double ab = (double)a * b, a2 = (double)a * a, b2 = (double)b * b;
+    for (; l < L; ++l) {
+        const double fl = l, fl1 = l + 1;
+        const double num = (2.0 * fl + 1.0) * (fl * fl1 * x - ab) * d -
+                           fl1 * sqrt((fl * fl - a2) * (fl * fl - b2)) * dprev;
+        const double den = fl * sqrt((fl1 * fl1 - a2) * (fl1 * fl1 - b2));
+        dprev = d;
+        d = num / den;
+        acc += V[(size_t)(l + 1) * L1 + j] * d;
+    }
+    Vd[i] = (R)acc;
+}
+
+constexpr int kStep1JB = 16;   // degree ranks accumulated per pass
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_vol_step1(const cx<R> *__restrict__ As, const cx<R> *__restrict__ Bs,
+                                                   int n_tgt, long long p0, int L, int M, int NC, int HC,
+                                                   int HD, const double *__restrict__ V,
+                                                   cx<R> *__restrict__ Y) {
+    __shared__ R sV[(kVolMaxL32 + 1) * (kVolMaxL32 + 1)];   // [l][j], j < HD
+    const int L1 = L + 1;
+    for (int i = threadIdx.x; i < L1 * HD; i += 256) {
+        const int l = i / HD, j = i - l * HD;
+        sV[i] = (R)V[(size_t)l * L1 + j];
+    }
+    __syncthreads();
+    const int MM = M * M;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= MM) return;
+    const long long p = blockIdx.y;
+    const long long pg = p0 + p;
+    const long long a = pg / n_tgt, b = pg - a * n_tgt;
+    const int im1 = i / M, im2 = i - im1 * M;
+    const int m1 = im1 <= L ? im1 : im1 - M, m2 = im2 <= L ? im2 : im2 - M;
+    const int l0 = std::max(m1 < 0 ? -m1 : m1, m2 < 0 ? -m2 : m2);
+    const cx<R> *Aa = As + (size_t)a * HC * NC;
+    const cx<R> *Bb = Bs + (size_t)b * HC * NC;
+    cx<R> *Yp = Y + (size_t)p * HD * MM;
+    for (int j0 = 0; j0 < HD; j0 += kStep1JB) {
+        R are[kStep1JB], aim[kStep1JB];
+#pragma unroll
+        for (int jj = 0; jj < kStep1JB; ++jj) are[jj] = aim[jj] = 0;
+        for (int l = l0; l <= L; ++l) {
+            const int ia = l * l + l + m1, ibb = l * l + l + m2;
+            R xr = 0, xi = 0;   // step 1: sum_h conj(As) Bs
+            for (int h = 0; h < HC; ++h) {
+                const cx<R> u = Aa[(size_t)h * NC + ia], v = Bb[(size_t)h * NC + ibb];
+                xr += u.re * v.re + u.im * v.im;
+                xi += u.re * v.im - u.im * v.re;
+            }
+#pragma unroll
+            for (int jj = 0; jj < kStep1JB; ++jj) {   // step 1b
+                if (j0 + jj < HD) {
+                    const R vv = sV[l * HD + j0 + jj];
+                    are[jj] += vv * xr;
+                    aim[jj] += vv * xi;
+                }
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < kStep1JB; ++jj)
+            if (j0 + jj < HD) Yp[(size_t)(j0 + jj) * MM + i] = cx<R>{are[jj], aim[jj]};
+    }
+}
+
+// (v, i) comes before (w, j): larger value first, then the smaller index
+template <typename R>
+__device__ __forceinline__ bool vol_before(R v, int i, R w, int j) {
+    if (i == 0x7fffffff) return false;
+    if (j == 0x7fffffff) return true;
+    return v > w || (v == w && i < j);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, const R *__restrict__ Vd,
+                                                  int n_beta, int M, int HD, long long p0,
+                                                  cx<R> *__restrict__ Xfull, double *__restrict__ part_val,
+                                                  int32_t *__restrict__ part_idx) {
+    extern __shared__ __align__(16) unsigned char vol_smem[];
+    cx<R> *S = reinterpret_cast<cx<R> *>(vol_smem);   // [M][M]
+    cx<R> *tw = S + M * M;                             // [M]: e^{-2 pi i k / M}
+    __shared__ R rv[4];
+    __shared__ int ri[4], rbad[4];
+    const int ib = blockIdx.x;
+    const long long p = blockIdx.y;
+    const int MM = M * M, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int k = tid; k < M; k += 256) {
+        double s, c;
+        sincospi(-2.0 * (double)k / (double)M, &s, &c);
+        tw[k] = cx<R>{(R)c, (R)s};
+    }
+    // step 2
+    const cx<R> *Yp = Y + (size_t)p * HD * MM;
+    const R *Vb = Vd + (size_t)ib * HD * MM;
+    for (int i = tid; i < MM; i += 256) {
+        R re = 0, im = 0;
+        for (int j = 0; j < HD; ++j) {
+            const R v = Vb[(size_t)j * MM + i];
+            const cx<R> y = Yp[(size_t)j * MM + i];
+            re += v * y.re;
+            im += v * y.im;
+        }
+        S[i] = cx<R>{re, im};
+    }
+    __syncthreads();
+    // step 3: length-M DFTs over m2 (rows), then over m1 (columns); a wave
+    // owns a whole row (column), reads it all, then overwrites it
+    constexpr int NCH = (kVolMaxM + 63) / 64;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int ld_in = pass == 0 ? 1 : M;      // step between the summed elements
+        for (int line = wv; line < M; line += 4) {
+            const int base = pass == 0 ? line * M : line;
+            cx<R> o[NCH];
+            int idx[NCH];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                o[c] = cx<R>{0, 0};
+                idx[c] = 0;
+            }
+            for (int e = 0; e < M; ++e) {
+                const cx<R> x = S[base + e * ld_in];
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int k = lane + 64 * c;
+                    if (k < M) {
+                        const cx<R> t = tw[idx[c]];
+                        o[c].re += x.re * t.re - x.im * t.im;
+                        o[c].im += x.re * t.im + x.im * t.re;
+                        idx[c] += k;
+                        if (idx[c] >= M) idx[c] -= M;
+                    }
+                }
+            }
+            vol_wave_sync();
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int k = lane + 64 * c;
+                if (k < M) S[base + k * ld_in] = o[c];
+            }
+            vol_wave_sync();
+        }
+        __syncthreads();
+    }
+    // the best Re X of this angle (first maximum in m1' M + m2' order); FULL
+    cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
+    R bv = 0;
+    int bi = 0x7fffffff, bad = 0;
+    for (int i = tid; i < MM; i += 256) {
+        const cx<R> x = S[i];
+        if (Xo) Xo[i] = x;
+        if (isnan(x.re)) {
+            bad = 1;
+        } else if (vol_before(x.re, i, bv, bi)) {
+            bv = x.re;
+            bi = i;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const R v2 = __shfl_xor(bv, o, 64);
+        const int i2 = __shfl_xor(bi, o, 64);
+        if (vol_before(v2, i2, bv, bi)) {
+            bv = v2;
+            bi = i2;
+        }
+        bad |= __shfl_xor(bad, o, 64);
+    }
+    if (lane == 0) {
+        rv[wv] = bv;
+        ri[wv] = bi;
+        rbad[wv] = bad;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int x = 1; x < 4; ++x) {
+            if (vol_before(rv[x], ri[x], bv, bi)) {
+                bv = rv[x];
+                bi = ri[x];
+            }
+            bad |= rbad[x];
+        }
+        const size_t o = (size_t)p * n_beta + ib;
+        part_val[o] = (bad || bi == 0x7fffffff) ? __builtin_nan("") : (double)bv;
+        part_idx[o] = bi;
+    }
+}
+
+__global__ void k_vol_best(const double *__restrict__ part_val, const int32_t *__restrict__ part_idx, int n_pairs,
+                           int n_beta, int M, long long p0, float *__restrict__ best_score,
+                           int32_t *__restrict__ best_idx) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pairs) return;
+    double bv = 0.0;
+    int bb = -1, bi = -1;
+    bool bad = false;
+    for (int ib = 0; ib < n_beta; ++ib) {
+        const double v = part_val[(size_t)p * n_beta + ib];
+        if (isnan(v)) {
+            bad = true;
+            break;
+        }
+        if (bb < 0 || v > bv) {   // strict: the smaller angle index on ties
+            bv = v;
+            bb = ib;
+            bi = part_idx[(size_t)p * n_beta + ib];
+        }
+    }
+    const size_t o = (size_t)(p0 + p);
+    if (best_score) best_score[o] = bad ? __builtin_nanf("") : (float)bv;
+    if (best_idx) {
+        best_idx[3 * o + 0] = bad ? -1 : bb;
+        best_idx[3 * o + 1] = bad ? -1 : bi / M;
+        best_idx[3 * o + 2] = bad ? -1 : bi % M;
+    }
+}
+
+template <typename R>
+hipError_t prepare_t(radsvd_vol_plan *p, const VolGrid &g, const void *A, const void *B, const double *U_in,
+                     const double *V_in, hipStream_t s) {
+    const cx<R> *Ac = reinterpret_cast<const cx<R> *>(A);
+    const cx<R> *Bc = reinterpret_cast<const cx<R> *>(B);
+    hipLaunchKernelGGL(k_vol_setup, dim3(1), dim3(256), 0, s, g, p->w, p->beta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int L1 = p->L + 1;
+    if (U_in) {
+        hipLaunchKernelGGL(k_vol_user_mat, dim3(64), dim3(256), 0, s, U_in, p->K, p->HC, p->U, p->lamC);
+    } else {
+        hipLaunchKernelGGL(k_vol_C<R>, dim3(p->K, p->K), dim3(256), 0, s, Bc, p->n_tgt, p->K, p->NC, p->w, p->C);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = launch_eig_raw(p->C, p->K, p->logC, p->U, p->lamC, s);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (V_in) {
+        hipLaunchKernelGGL(k_vol_user_mat, dim3(64), dim3(256), 0, s, V_in, L1, p->HD, p->V, p->lamD);
+    } else {
+        hipLaunchKernelGGL(k_vol_D<R>, dim3(L1, L1), dim3(256), 0, s, Bc, p->n_tgt, p->K, p->NC, p->L, p->w, p->D);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = launch_eig_raw(p->D, L1, p->logD, p->V, p->lamD, s);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nbx = (p->NC + 255) / 256;
+    hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_vol * nbx), p->HC), dim3(256), 0, s, Ac,
+                       p->n_vol, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->As));
+    hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_tgt * nbx), p->HC), dim3(256), 0, s, Bc,
+                       p->n_tgt, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->Bs));
+    const long long nvd = (long long)p->n_beta * p->HD * p->M * p->M;
+    hipLaunchKernelGGL(k_vol_wigner<R>, dim3((unsigned)((nvd + 255) / 256)), dim3(256), 0, s, p->beta,
+                       p->n_beta, p->L, p->M, p->V, p->HD, reinterpret_cast<R *>(p->Vd));
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32_t *best_idx, void *X_full,
+                   hipStream_t s) {
+    const size_t shmem = (size_t)(p->M * p->M + p->M) * sizeof(cx<R>);
+    hipError_t e = hipFuncSetAttribute((const void *)k_vol_land<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)shmem);
+    if (e != hipSuccess) return e;
+    const long long n_pairs = (long long)p->n_vol * p->n_tgt;
+    const int MM = p->M * p->M;
+    cx<R> *Xf = (flags & RADSVD_OUT_FULL) ? reinterpret_cast<cx<R> *>(X_full) : nullptr;
+    for (long long p0 = 0; p0 < n_pairs; p0 += p->chunk) {
+        const int np = (int)std::min<long long>(p->chunk, n_pairs - p0);
+        hipLaunchKernelGGL(k_vol_step1<R>, dim3((MM + 255) / 256, np), dim3(256), 0, s,
+                           reinterpret_cast<const cx<R> *>(p->As), reinterpret_cast<const cx<R> *>(p->Bs),
+                           p->n_tgt, p0, p->L, p->M, p->NC, p->HC, p->HD, p->V, reinterpret_cast<cx<R> *>(p->Y));
+        hipLaunchKernelGGL(k_vol_land<R>, dim3(p->n_beta, np), dim3(256), shmem, s,
+                           reinterpret_cast<const cx<R> *>(p->Y), reinterpret_cast<const R *>(p->Vd), p->n_beta,
+                           p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
+        if (flags & RADSVD_OUT_BEST)
+            hipLaunchKernelGGL(k_vol_best, dim3((np + 255) / 256), dim3(256), 0, s, p->part_val, p->part_idx, np,
+                               p->n_beta, p->M, p0, best_score, best_idx);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t vol_launch_prepare(radsvd_vol_plan *p, const VolGrid &g, const void *A, const void *B,
+                              const double *U_in, const double *V_in, hipStream_t s) {
+    if (p->prec == RADSVD_FP64) return prepare_t<double>(p, g, A, B, U_in, V_in, s);
+    return prepare_t<float>(p, g, A, B, U_in, V_in, s);
+}
+
+hipError_t vol_launch_align(const radsvd_vol_plan *p, int flags, float *best_score, int32_t *best_idx,
+                            void *X_full, hipStream_t s) {
+    if (p->prec == RADSVD_FP64) return align_t<double>(p, flags, best_score, best_idx, X_full, s);
+    return align_t<float>(p, flags, best_score, best_idx, X_full, s);
+}
+
+}  // namespace radsvd

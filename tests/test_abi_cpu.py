@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "radsvd.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(align_\w+|radsvd_\w+)\s*\(", src)
+    names = re.findall(r"\b(align_\w+|vol_\w+|radsvd_\w+)\s*\(", src)
     return sorted(set(names))
 
 
@@ -24,6 +24,7 @@ def test_library_exports_every_declared_function():
     lib = rs._load()
     names = _declared()
     assert "align_prepare" in names and "align_pairs" in names and "align_pairs_backward" in names
+    assert "vol_prepare" in names and "vol_align" in names and "vol_get_UV" in names
     for n in names:
         assert hasattr(lib, n), n
 
@@ -113,3 +114,52 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(rs, "_LIB_PATH", "/nonexistent/libradsvd.so")
     with pytest.raises(ImportError):
         rs._load()
+
+
+def _vprob(**kw):
+    from paper_2202_07235_amd import volume as rv
+    K, L = kw.get("K", 8), kw.get("L", 6)
+    return rv.make_vol_problem(K, L, kw.get("H_C", 4), kw.get("H_D", 4), kw.get("w", np.ones(K)),
+                               kw.get("beta", np.linspace(0, 6, 5)), kw.get("prec", rs.FP32))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(K=1), dict(K=129), dict(L=0), dict(L=65), dict(L=49, prec=rs.FP64), dict(prec=rs.BF16),
+    dict(prec=rs.BF16X3), dict(H_C=0), dict(H_C=9), dict(H_D=0), dict(H_D=8), dict(beta=np.zeros(0)),
+    dict(beta=np.zeros(257)), dict(beta=np.array([0.0, np.inf])), dict(w=np.r_[np.ones(7), 0.0]),
+    dict(w=np.r_[np.ones(7), np.nan]),
+])
+def test_invalid_volume_problem_rejected(bad):
+    pr, keep = _vprob(**bad)
+    assert rs._load().vol_prepare_workspace(ctypes.byref(pr), 4, 4) == 0
+    assert rs.radsvd_last_error() != ""
+
+
+def test_volume_workspace_and_argument_errors():
+    from paper_2202_07235_amd import volume as rv
+    lib = rs._load()
+    pr, keep = _vprob()
+    a = rv.vol_prepare_workspace(pr, 4, 1)
+    b = rv.vol_prepare_workspace(pr, 40, 2)
+    assert 0 < a < b
+    assert lib.vol_prepare_workspace(ctypes.byref(pr), 0, 1) == 0
+    assert lib.vol_prepare_workspace(ctypes.byref(pr), 1 << 20, 1 << 20) == 0   # n_vol * n_tgt > 2^31
+    # the largest FP32 and FP64 degrees are accepted
+    for L, prec in ((64, rs.FP32), (48, rs.FP64)):
+        p2, k2 = _vprob(L=L, prec=prec)
+        assert rv.vol_prepare_workspace(p2, 2, 1) > 0
+    out = ctypes.c_void_p()
+    fake = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+    st = lib.vol_prepare(ctypes.byref(pr), 4, None, 1, fake, None, None, ws, a, None, ctypes.byref(out))
+    assert st == 1 and "NULL" in rs.radsvd_last_error()
+    st = lib.vol_prepare(ctypes.byref(pr), 4, ctypes.c_void_p(4100), 1, fake, None, None, ws, a, None,
+                         ctypes.byref(out))
+    assert st == 1 and "aligned" in rs.radsvd_last_error()
+    st = lib.vol_prepare(ctypes.byref(pr), 4, fake, 1, fake, None, None, ws, a - 1, None, ctypes.byref(out))
+    assert st == 3
+    st = lib.vol_prepare(ctypes.byref(pr), 4, fake, 1, fake, None, None, ctypes.c_void_p((1 << 20) + 8), a, None,
+                         ctypes.byref(out))
+    assert st == 3
+    assert lib.vol_align(None, 1, fake, fake, None, None) == 1
+    assert lib.vol_get_UV(None, None, None, None, None, None) == 1

@@ -48,10 +48,10 @@ def parse():
                          "3 only the two leading terms")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="fraction of N_A and N_B (for quick local runs; 1.0 = the full workload)")
-    ap.add_argument("--only", choices=["plain", "batching", "differentiation"], default=None,
+    ap.add_argument("--only", choices=["plain", "batching", "differentiation", "volume"], default=None,
                     help="run only that other workload and print its record as one JSON line")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the other workloads (plain FP32 batch, batching, differentiation)")
+                    help="skip the other workloads (plain FP32 batch, batching, differentiation, volume)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the same-GPU comparison runs (FP32, bf16x3 with 3 products)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB streaming kernel (x -> -x) whose HBM counters calibrate FETCH_SIZE / "
@@ -549,6 +549,69 @@ def differentiation_workload(rs, synth, torch, reps=3):
     return res
 
 
+def volume_flops(cfg):
+    """Algorithmic flops of one volume-target pair at ranks H_C, H_D (section
+    4.9): step 1 (complex MACs over the principal shells), step 1b (real x
+    complex over the degrees), step 2 per interior angle, and step 3 counted
+    as a 2-D FFT (5 n log2 n, n = M^2); also the flops the library executes
+    for step 3, a direct length-M DFT along rows then columns."""
+    L, M, nb = cfg.L, 2 * cfg.L + 1, cfg.n_beta
+    lm2 = sum((2 * l + 1) ** 2 for l in range(L + 1))
+    s1 = 8.0 * cfg.H_C * lm2
+    s1b = 4.0 * cfg.H_D * lm2
+    s2 = 4.0 * nb * cfg.H_D * M * M
+    s3 = nb * 5.0 * M * M * math.log2(M * M)
+    s3_exec = nb * 2.0 * M ** 3 * 8.0
+    return {"step1": s1, "step1b": s1b, "step2": s2, "step3_fft": s3, "step3_executed": s3_exec,
+            "algorithmic": s1 + s1b + s2 + s3, "executed": s1 + s1b + s2 + s3_exec}
+
+
+def volume_workload(rs, synth, torch, reps=3):
+    """Volume alignment (section 4): 96 noisy rotated copies of one target
+    (blob volumes standing in for the paper's reconstructions), K = 48 shells,
+    degrees to L = 48 (M = 97 orders), 97 interior angles, H_C = H_D = 16,
+    FP32 plan.  One step = vol_prepare + vol_align(BEST)."""
+    from paper_2202_07235_amd import volume as rv
+    from synth import volumes as sv
+    cfg = sv.vol_config("volume")
+    P = sv.make_volume_problem(cfg, 6006)
+    A = torch.tensor(P.A, dtype=torch.complex64, device="cuda")
+    B = torch.tensor(P.B, dtype=torch.complex64, device="cuda")
+
+    def make():
+        return rv.VolPlan(A, B, P.w, cfg.L, cfg.H_C, cfg.H_D, P.beta, precision="fp32")
+
+    plan = make()
+    plan.align("best")
+    torch.cuda.synchronize()
+    plan.close()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    prep, al = [], []
+    for _ in range(reps):
+        ev[0].record()
+        plan = make()
+        ev[1].record()
+        plan.align("best")
+        ev[2].record()
+        torch.cuda.synchronize()
+        prep.append(ev[0].elapsed_time(ev[1]))
+        al.append(ev[1].elapsed_time(ev[2]))
+        plan.close()
+    n_pairs = cfg.n_vol * cfg.n_tgt
+    fl = volume_flops(cfg)
+    t = min(al) * 1e-3
+    res = {"workload": f"volume: {cfg.n_vol} volumes x {cfg.n_tgt} target, K={cfg.K} L={cfg.L} (M={2 * cfg.L + 1}), "
+                       f"n_beta={cfg.n_beta}, H_C={cfg.H_C} H_D={cfg.H_D}, FP32 plan",
+           "vol_prepare_ms": min(prep), "vol_align_ms": min(al),
+           "pairs_per_s": n_pairs / t, "pairs_per_s_with_prepare": n_pairs / ((min(al) + min(prep)) * 1e-3),
+           "flops_per_pair": fl,
+           "roofline": {"bound": "alu", "achieved": n_pairs * fl["algorithmic"] / t / 1e12, "peak": 157.3,
+                        "unit": "TFLOP/s", "frac": n_pairs * fl["algorithmic"] / t / 1e12 / 157.3,
+                        "executed_tflops": n_pairs * fl["executed"] / t / 1e12, "kernel": "vol_align (all kernels)"}}
+    print(f"[bench] volume workload: {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     a = parse()
     if a.reduce_counters:
@@ -575,7 +638,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.only:
         fn = {"plain": plain_workload, "batching": batching_workload,
-              "differentiation": differentiation_workload}[a.only]
+              "differentiation": differentiation_workload, "volume": volume_workload}[a.only]
         print(json.dumps(fn(rs, synth, torch)))
         return 0
     cfg = synth.config("precision")
@@ -648,6 +711,7 @@ def main():
         extras["plain_fp32_workload"] = plain_workload(rs, synth, torch)
         extras["batching_workload"] = batching_workload(rs, synth, torch)
         extras["differentiation_workload"] = differentiation_workload(rs, synth, torch)
+        extras["volume_workload"] = volume_workload(rs, synth, torch)
 
     cpu = None
     accuracy = None

@@ -12,11 +12,12 @@
 //                 the closed form at l = max(|m1|, |m2|) (section 4.7), in FP64.
 // Per pair (section 4.9, steps 1, 1b, 2, 3):
 //   k_vol_step1   Y_j(m1, m2) = sum_l V[l][j] sum_h conj(As[h]_l^m1) Bs[h]_l^m2;
-//   k_vol_land    one workgroup per (pair, beta): Xhat = sum_j [v_j^T d](beta) Y_j in
-//                 LDS, then the 2-D transform over the orders as two passes of
-//                 length-M DFTs (M = 2L + 1 is odd, so a direct DFT with an LDS
-//                 twiddle table; each wave owns whole rows, then whole columns),
-//                 then the best Re X of the angle and the FULL write;
+//   k_vol_land*   one workgroup per (pair, beta): Xhat = sum_j [v_j^T d](beta) Y_j in
+//                 LDS, then the 2-D transform over the orders (M = 2L + 1 is odd:
+//                 a direct DFT against an LDS twiddle table, as two dense complex
+//                 matrix products on the FP32 matrix cores, or for FP64 plans
+//                 two passes on the vector units), then the best Re X of the
+//                 angle and the FULL write;
 //   k_vol_best    per pair, the best over the angles.
 #include <math.h>
 
@@ -265,6 +266,79 @@ __device__ __forceinline__ bool vol_before(R v, int i, R w, int j) {
     return v > w || (v == w && i < j);
 }
 
+// step 2 into LDS: S[i] = sum_j Vd[ib][j][i] Y[p][j][i]
+template <typename R>
+__device__ __forceinline__ void land_step2(const cx<R> *__restrict__ Yp, const R *__restrict__ Vb, int HD, int MM,
+                                           cx<R> *S, int tid, int nthr) {
+    for (int i = tid; i < MM; i += nthr) {
+        R re = 0, im = 0;
+        for (int j = 0; j < HD; ++j) {
+            const R v = Vb[(size_t)j * MM + i];
+            const cx<R> y = Yp[(size_t)j * MM + i];
+            re += v * y.re;
+            im += v * y.im;
+        }
+        S[i] = cx<R>{re, im};
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void land_twiddles(cx<R> *tw, int M, int tid, int nthr) {
+    for (int k = tid; k < M; k += nthr) {
+        double s, c;
+        sincospi(-2.0 * (double)k / (double)M, &s, &c);
+        tw[k] = cx<R>{(R)c, (R)s};
+    }
+}
+
+// the best Re X of one angle (first maximum in m1' M + m2' order) and the FULL
+// write; rv, ri, rbad hold one entry per wave
+template <typename R>
+__device__ void land_epilogue(const cx<R> *S, int MM, cx<R> *Xo, int tid, int nthr, R *rv, int *ri, int *rbad,
+                              double *pv, int32_t *pi) {
+    const int lane = tid & 63, wv = tid >> 6;
+    R bv = 0;
+    int bi = 0x7fffffff, bad = 0;
+    for (int i = tid; i < MM; i += nthr) {
+        const cx<R> x = S[i];
+        if (Xo) Xo[i] = x;
+        if (isnan(x.re)) {
+            bad = 1;
+        } else if (vol_before(x.re, i, bv, bi)) {
+            bv = x.re;
+            bi = i;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const R v2 = __shfl_xor(bv, o, 64);
+        const int i2 = __shfl_xor(bi, o, 64);
+        if (vol_before(v2, i2, bv, bi)) {
+            bv = v2;
+            bi = i2;
+        }
+        bad |= __shfl_xor(bad, o, 64);
+    }
+    if (lane == 0) {
+        rv[wv] = bv;
+        ri[wv] = bi;
+        rbad[wv] = bad;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int x = 1; x < (nthr >> 6); ++x) {
+            if (vol_before(rv[x], ri[x], bv, bi)) {
+                bv = rv[x];
+                bi = ri[x];
+            }
+            bad |= rbad[x];
+        }
+        *pv = (bad || bi == 0x7fffffff) ? __builtin_nan("") : (double)bv;
+        *pi = bi;
+    }
+}
+
+// FP64 plans: step 3 on the vector units, four waves; each wave owns whole
+// rows (then whole columns), reads all of one, then overwrites it
 template <typename R>
 __global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, const R *__restrict__ Vd,
                                                   int n_beta, int M, int HD, long long p0,
@@ -278,27 +352,9 @@ __global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, c
     const int ib = blockIdx.x;
     const long long p = blockIdx.y;
     const int MM = M * M, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int k = tid; k < M; k += 256) {
-        double s, c;
-        sincospi(-2.0 * (double)k / (double)M, &s, &c);
-        tw[k] = cx<R>{(R)c, (R)s};
-    }
-    // step 2
-    const cx<R> *Yp = Y + (size_t)p * HD * MM;
-    const R *Vb = Vd + (size_t)ib * HD * MM;
-    for (int i = tid; i < MM; i += 256) {
-        R re = 0, im = 0;
-        for (int j = 0; j < HD; ++j) {
-            const R v = Vb[(size_t)j * MM + i];
-            const cx<R> y = Yp[(size_t)j * MM + i];
-            re += v * y.re;
-            im += v * y.im;
-        }
-        S[i] = cx<R>{re, im};
-    }
+    land_twiddles(tw, M, tid, 256);
+    land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, S, tid, 256);
     __syncthreads();
-    // step 3: length-M DFTs over m2 (rows), then over m1 (columns); a wave
-    // owns a whole row (column), reads it all, then overwrites it
     constexpr int NCH = (kVolMaxM + 63) / 64;
     for (int pass = 0; pass < 2; ++pass) {
         const int ld_in = pass == 0 ? 1 : M;      // step between the summed elements
@@ -335,47 +391,99 @@ __global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, c
         }
         __syncthreads();
     }
-    // the best Re X of this angle (first maximum in m1' M + m2' order); FULL
     cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
-    R bv = 0;
-    int bi = 0x7fffffff, bad = 0;
-    for (int i = tid; i < MM; i += 256) {
-        const cx<R> x = S[i];
-        if (Xo) Xo[i] = x;
-        if (isnan(x.re)) {
-            bad = 1;
-        } else if (vol_before(x.re, i, bv, bi)) {
-            bv = x.re;
-            bi = i;
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        const R v2 = __shfl_xor(bv, o, 64);
-        const int i2 = __shfl_xor(bi, o, 64);
-        if (vol_before(v2, i2, bv, bi)) {
-            bv = v2;
-            bi = i2;
-        }
-        bad |= __shfl_xor(bad, o, 64);
-    }
-    if (lane == 0) {
-        rv[wv] = bv;
-        ri[wv] = bi;
-        rbad[wv] = bad;
-    }
+    land_epilogue<R>(S, MM, Xo, tid, 256, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
+                     part_idx + (size_t)p * n_beta + ib);
+}
+
+typedef float vol_f4 __attribute__((ext_vector_type(4)));
+
+// FP32 plans: step 3 as two complex matrix products on the matrix cores,
+// Xrow = S F, then X = F Xrow (F[a][b] = e^{-2 pi i ab / M}, symmetric), each
+// as four real FP32 MFMA 16x16x4 products (re = Sr Fr - Si Fi, im = Sr Fi + Si Fr)
+// over 16 x 16 output tiles, the order grid padded to NT tiles of 16 by
+// zero operands.  Wave w owns row block w in the first product (column block
+// w in the second): it reads only that block and overwrites it after its
+// last read, so a wave-level fence suffices between read and write.
+// Operand layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16], r = 0..3.
+template <int NT>
+__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__restrict__ Y,
+                                                           const float *__restrict__ Vd, int n_beta, int M, int HD,
+                                                           long long p0, cx<float> *__restrict__ Xfull,
+                                                           double *__restrict__ part_val,
+                                                           int32_t *__restrict__ part_idx) {
+    extern __shared__ __align__(16) unsigned char vol_smem[];
+    cx<float> *S = reinterpret_cast<cx<float> *>(vol_smem);   // [M][M]
+    cx<float> *tw = S + M * M;
+    __shared__ float rv[NT];
+    __shared__ int ri[NT], rbad[NT];
+    constexpr int NTHR = 64 * NT;
+    const int ib = blockIdx.x;
+    const long long p = blockIdx.y;
+    const int MM = M * M, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    land_twiddles(tw, M, tid, NTHR);
+    land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, S, tid, NTHR);
     __syncthreads();
-    if (tid == 0) {
-        for (int x = 1; x < 4; ++x) {
-            if (vol_before(rv[x], ri[x], bv, bi)) {
-                bv = rv[x];
-                bi = ri[x];
-            }
-            bad |= rbad[x];
+    const int li = lane & 15, lk = lane >> 4;
+    const int ia = wv * 16 + li;   // A row: m1 (first product) or c (second)
+    for (int pass = 0; pass < 2; ++pass) {
+        vol_f4 are[NT], aim[NT];
+        int tix[NT], tst[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            are[t] = vol_f4{0.f, 0.f, 0.f, 0.f};
+            aim[t] = vol_f4{0.f, 0.f, 0.f, 0.f};
+            const int j = t * 16 + li;   // B column
+            tix[t] = (lk * j) % M;       // (e j) mod M for e = lk
+            tst[t] = (4 * j) % M;
         }
-        const size_t o = (size_t)p * n_beta + ib;
-        part_val[o] = (bad || bi == 0x7fffffff) ? __builtin_nan("") : (double)bv;
-        part_idx[o] = bi;
+        for (int e0 = 0; e0 < NT * 16; e0 += 4) {
+            const int e = e0 + lk;
+            float xr = 0.f, xi = 0.f;
+            if (e < M && ia < M) {
+                const cx<float> x = pass == 0 ? S[ia * M + e] : S[e * M + ia];
+                xr = x.re;
+                xi = x.im;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int j = t * 16 + li;
+                float fr = 0.f, fi = 0.f;
+                if (e < M && j < M) {
+                    const cx<float> f = tw[tix[t]];
+                    fr = f.re;
+                    fi = f.im;
+                }
+                tix[t] += tst[t];
+                if (tix[t] >= M) tix[t] -= M;
+                are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fr, are[t], 0, 0, 0);
+                are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, -fi, are[t], 0, 0, 0);
+                aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fi, aim[t], 0, 0, 0);
+                aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, fr, aim[t], 0, 0, 0);
+            }
+        }
+        vol_wave_sync();
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = t * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = wv * 16 + 4 * lk + r;
+                if (i < M && j < M) {
+                    const cx<float> v{are[t][r], aim[t][r]};
+                    if (pass == 0)
+                        S[i * M + j] = v;
+                    else
+                        S[j * M + i] = v;
+                }
+            }
+        }
+        __syncthreads();
     }
+    cx<float> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
+    land_epilogue<float>(S, MM, Xo, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
+                         part_idx + (size_t)p * n_beta + ib);
 }
 
 __global__ void k_vol_best(const double *__restrict__ part_val, const int32_t *__restrict__ part_idx, int n_pairs,
@@ -445,13 +553,48 @@ hipError_t prepare_t(radsvd_vol_plan *p, const VolGrid &g, const void *A, const 
     return hipGetLastError();
 }
 
+template <int NT>
+hipError_t launch_land_mfma(const radsvd_vol_plan *p, int np, long long p0, cx<float> *Xf, size_t shmem,
+                            hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_vol_land_mfma<NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vol_land_mfma<NT>, dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
+                       reinterpret_cast<const cx<float> *>(p->Y), reinterpret_cast<const float *>(p->Vd), p->n_beta,
+                       p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_land(const radsvd_vol_plan *p, int np, long long p0, cx<R> *Xf, size_t shmem, hipStream_t s) {
+    if constexpr (sizeof(R) == 4) {
+        switch ((p->M + 15) / 16) {   // tiles of 16 orders; M <= 129
+            case 1: return launch_land_mfma<1>(p, np, p0, Xf, shmem, s);
+            case 2: return launch_land_mfma<2>(p, np, p0, Xf, shmem, s);
+            case 3: return launch_land_mfma<3>(p, np, p0, Xf, shmem, s);
+            case 4: return launch_land_mfma<4>(p, np, p0, Xf, shmem, s);
+            case 5: return launch_land_mfma<5>(p, np, p0, Xf, shmem, s);
+            case 6: return launch_land_mfma<6>(p, np, p0, Xf, shmem, s);
+            case 7: return launch_land_mfma<7>(p, np, p0, Xf, shmem, s);
+            case 8: return launch_land_mfma<8>(p, np, p0, Xf, shmem, s);
+            case 9: return launch_land_mfma<9>(p, np, p0, Xf, shmem, s);
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        hipError_t e = hipFuncSetAttribute((const void *)k_vol_land<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)shmem);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_vol_land<R>, dim3(p->n_beta, np), dim3(256), shmem, s,
+                           reinterpret_cast<const cx<R> *>(p->Y), reinterpret_cast<const R *>(p->Vd), p->n_beta,
+                           p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
+        return hipGetLastError();
+    }
+}
+
 template <typename R>
 hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32_t *best_idx, void *X_full,
                    hipStream_t s) {
     const size_t shmem = (size_t)(p->M * p->M + p->M) * sizeof(cx<R>);
-    hipError_t e = hipFuncSetAttribute((const void *)k_vol_land<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shmem);
-    if (e != hipSuccess) return e;
     const long long n_pairs = (long long)p->n_vol * p->n_tgt;
     const int MM = p->M * p->M;
     cx<R> *Xf = (flags & RADSVD_OUT_FULL) ? reinterpret_cast<cx<R> *>(X_full) : nullptr;
@@ -460,13 +603,12 @@ hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32
         hipLaunchKernelGGL(k_vol_step1<R>, dim3((MM + 255) / 256, np), dim3(256), 0, s,
                            reinterpret_cast<const cx<R> *>(p->As), reinterpret_cast<const cx<R> *>(p->Bs),
                            p->n_tgt, p0, p->L, p->M, p->NC, p->HC, p->HD, p->V, reinterpret_cast<cx<R> *>(p->Y));
-        hipLaunchKernelGGL(k_vol_land<R>, dim3(p->n_beta, np), dim3(256), shmem, s,
-                           reinterpret_cast<const cx<R> *>(p->Y), reinterpret_cast<const R *>(p->Vd), p->n_beta,
-                           p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
-        if (flags & RADSVD_OUT_BEST)
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = launch_land<R>(p, np, p0, Xf, shmem, s);
+        if (e == hipSuccess && (flags & RADSVD_OUT_BEST))
             hipLaunchKernelGGL(k_vol_best, dim3((np + 255) / 256), dim3(256), 0, s, p->part_val, p->part_idx, np,
                                p->n_beta, p->M, p0, best_score, best_idx);
-        e = hipGetLastError();
+        if (e == hipSuccess) e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -35,7 +35,8 @@ struct radsvd_vol_plan {
     void *logC, *logD;         // Jacobi rotation logs
     void *As, *Bs;             // principal shells [n][H_C][(L+1)^2] complex
     void *Vd;                  // [n_beta][H_D][M][M] real: [v_j^T d](beta)
-    void *Y;                   // [chunk][H_D][M][M] complex: steps 1-1b
+    void *Xt;                  // [chunk][sum_l (2l+1)^2] complex: step 1, degree-major
+    void *Y;                   // [chunk][H_D][M][M] complex: step 1b
     double *part_val;          // [chunk][n_beta]: best Re X of one angle (NaN: a NaN seen)
     int32_t *part_idx;         // [chunk][n_beta]: its m1' M + m2'
 };

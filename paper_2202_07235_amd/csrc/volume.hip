@@ -9,9 +9,12 @@
 //   k_vol_shells  principal shells [u_h^T A]_l^m = sum_r U[r][h] sqrt(w_r) A_l^m(k_r) (section 4.5);
 //   k_vol_wigner  [v_j^T d]_{m1 m2}(beta) = sum_l V[l][j] d^l_{m1 m2}(beta) on the periodic
 //                 M x M order grid, with d^l by its three-term recurrence in l from
-//                 the closed form at l = max(|m1|, |m2|) (section 4.7), in FP64.
+//                 the closed form at l = max(|m1|, |m2|) (section 4.7), in FP64, one
+//                 recurrence for up to 16 ranks.
 // Per pair (section 4.9, steps 1, 1b, 2, 3):
-//   k_vol_step1   Y_j(m1, m2) = sum_l V[l][j] sum_h conj(As[h]_l^m1) Bs[h]_l^m2;
+//   k_vol_xt      step 1, Xt_l(m1, m2) = sum_h conj(As[h]_l^m1) Bs[h]_l^m2, one workgroup
+//                 per (degree, pair) with the degree's blocks staged in LDS;
+//   k_vol_step1b  Y_j(m1, m2) = sum_l V[l][j] Xt_l(m1, m2);
 //   k_vol_land*   one workgroup per (pair, beta): Xhat = sum_j [v_j^T d](beta) Y_j in
 //                 LDS, then the 2-D transform over the orders (M = 2L + 1 is odd:
 //                 a direct DFT against an LDS twiddle table, as two dense complex
@@ -164,33 +167,46 @@ __device__ double wigner_seed(int l, int a, int b, double c, double s) {
     return v;
 }
 
+constexpr int kWigJB = 16;   // degree ranks accumulated per recurrence
+
+// thread per (beta, m1, m2) and block of up to kWigJB ranks: one recurrence
+// in l, accumulated into each rank's table
 template <typename R>
 __global__ __launch_bounds__(256) void k_vol_wigner(const double *__restrict__ beta, int n_beta, int L, int M,
                                                     const double *__restrict__ V, int HD, R *__restrict__ Vd) {
     const long long MM = (long long)M * M;
-    const long long total = (long long)n_beta * HD * MM;
+    const int njb = (HD + kWigJB - 1) / kWigJB;
+    const long long total = (long long)n_beta * njb * MM;
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= total) return;
-    const int im2 = (int)(i % M);
-    long long t = i / M;
-    const int im1 = (int)(t % M);
-    t /= M;
-    const int j = (int)(t % HD);
-    const int ib = (int)(t / HD);
+    const long long el = i % MM;   // im1 M + im2
+    const long long t = i / MM;
+    const int jb = (int)(t % njb) * kWigJB;
+    const int ib = (int)(t / njb);
+    const int im1 = (int)(el / M), im2 = (int)(el - (long long)im1 * M);
     const int a = im1 <= L ? im1 : im1 - M, b = im2 <= L ? im2 : im2 - M;
     const int l0 = std::max(a < 0 ? -a : a, b < 0 ? -b : b);
     double sb, cb;
     sincos(0.5 * beta[ib], &sb, &cb);
     const double x = cos(beta[ib]);
     const int L1 = L + 1;
+    double acc[kWigJB];
+#pragma unroll
+    for (int jj = 0; jj < kWigJB; ++jj) acc[jj] = 0.0;
+    auto add = [&](int l, double d) {
+        const double *v = V + (size_t)l * L1 + jb;
+#pragma unroll
+        for (int jj = 0; jj < kWigJB; ++jj)
+            if (jb + jj < HD) acc[jj] += v[jj] * d;
+    };
     double dprev = 0.0, d = wigner_seed(l0, a, b, cb, sb);
-    double acc = V[(size_t)l0 * L1 + j] * d;
+    add(l0, d);
     int l = l0;
     if (l0 == 0) {   // d^1_00 = cos(beta); the recurrence below needs l >= 1
         dprev = d;
         d = x;
         l = 1;
-        acc += V[(size_t)L1 + j] * d;
+        add(1, d);
     }
     const double ab = (double)a * b, a2 = (double)a * a, b2 = (double)b * b;
     for (; l < L; ++l) {
@@ -200,18 +216,77 @@ __global__ __launch_bounds__(256) void k_vol_wigner(const double *__restrict__ b
         const double den = fl * sqrt((fl1 * fl1 - a2) * (fl1 * fl1 - b2));
         dprev = d;
         d = num / den;
-        acc += V[(size_t)(l + 1) * L1 + j] * d;
+        add(l + 1, d);
     }
-    Vd[i] = (R)acc;
+    R *out = Vd + ((size_t)ib * HD + jb) * MM + el;
+#pragma unroll
+    for (int jj = 0; jj < kWigJB; ++jj)
+        if (jb + jj < HD) out[(size_t)jj * MM] = (R)acc[jj];
+}
+
+// offset of degree l in the per-pair step-1 array: sum_{l' < l} (2l' + 1)^2
+__host__ __device__ __forceinline__ long long xt_off(int l) { return (long long)l * (2 * l - 1) * (2 * l + 1) / 3; }
+
+constexpr int kXtH = 16;    // ranks staged in LDS per round
+constexpr int kXtOut = 8;   // outputs per thread per pass
+
+// step 1, one workgroup per (degree l, pair): Xt_l = As_l^H Bs_l, a
+// (2l+1) x (2l+1) product over the H_C principal shells, with the shells'
+// degree-l blocks staged through LDS kXtH ranks at a time
+template <typename R>
+__global__ __launch_bounds__(256) void k_vol_xt(const cx<R> *__restrict__ As, const cx<R> *__restrict__ Bs,
+                                                int n_tgt, long long p0, int NC, int HC, long long NXT,
+                                                cx<R> *__restrict__ Xt) {
+    __shared__ cx<R> sa[kXtH][2 * kVolMaxL32 + 1], sb[kXtH][2 * kVolMaxL32 + 1];
+    const int l = blockIdx.x;
+    const long long p = blockIdx.y;
+    const long long pg = p0 + p;
+    const long long a = pg / n_tgt, b = pg - a * n_tgt;
+    const int n = 2 * l + 1, nn = n * n, base = l * l;
+    const cx<R> *Aa = As + (size_t)a * HC * NC + base;
+    const cx<R> *Bb = Bs + (size_t)b * HC * NC + base;
+    cx<R> *out = Xt + (size_t)p * NXT + xt_off(l);
+    for (int o0 = 0; o0 < nn; o0 += 256 * kXtOut) {
+        R re[kXtOut], im[kXtOut];
+#pragma unroll
+        for (int c = 0; c < kXtOut; ++c) re[c] = im[c] = 0;
+        for (int h0 = 0; h0 < HC; h0 += kXtH) {
+            const int hn = std::min(kXtH, HC - h0);
+            __syncthreads();
+            for (int i = threadIdx.x; i < hn * n; i += 256) {
+                const int h = i / n, m = i - h * n;
+                sa[h][m] = Aa[(size_t)(h0 + h) * NC + m];
+                sb[h][m] = Bb[(size_t)(h0 + h) * NC + m];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < kXtOut; ++c) {
+                const int o = o0 + c * 256 + threadIdx.x;
+                if (o < nn) {
+                    const int m1 = o / n, m2 = o - m1 * n;
+                    for (int h = 0; h < hn; ++h) {
+                        const cx<R> u = sa[h][m1], v = sb[h][m2];
+                        re[c] += u.re * v.re + u.im * v.im;   // conj(u) v
+                        im[c] += u.re * v.im - u.im * v.re;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kXtOut; ++c) {
+            const int o = o0 + c * 256 + threadIdx.x;
+            if (o < nn) out[o] = cx<R>{re[c], im[c]};
+        }
+    }
 }
 
 constexpr int kStep1JB = 16;   // degree ranks accumulated per pass
 
+// step 1b, thread per (pair, m1, m2): Y_j(m1, m2) = sum_{l >= max(|m1|,|m2|)} V[l][j] Xt_l(m1, m2);
+// every Xt entry is read once
 template <typename R>
-__global__ __launch_bounds__(256) void k_vol_step1(const cx<R> *__restrict__ As, const cx<R> *__restrict__ Bs,
-                                                   int n_tgt, long long p0, int L, int M, int NC, int HC,
-                                                   int HD, const double *__restrict__ V,
-                                                   cx<R> *__restrict__ Y) {
+__global__ __launch_bounds__(256) void k_vol_step1b(const cx<R> *__restrict__ Xt, int L, int M, int HD, long long NXT,
+                                                    const double *__restrict__ V, cx<R> *__restrict__ Y) {
     __shared__ R sV[(kVolMaxL32 + 1) * (kVolMaxL32 + 1)];   // [l][j], j < HD
     const int L1 = L + 1;
     for (int i = threadIdx.x; i < L1 * HD; i += 256) {
@@ -223,32 +298,24 @@ __global__ __launch_bounds__(256) void k_vol_step1(const cx<R> *__restrict__ As,
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= MM) return;
     const long long p = blockIdx.y;
-    const long long pg = p0 + p;
-    const long long a = pg / n_tgt, b = pg - a * n_tgt;
     const int im1 = i / M, im2 = i - im1 * M;
     const int m1 = im1 <= L ? im1 : im1 - M, m2 = im2 <= L ? im2 : im2 - M;
     const int l0 = std::max(m1 < 0 ? -m1 : m1, m2 < 0 ? -m2 : m2);
-    const cx<R> *Aa = As + (size_t)a * HC * NC;
-    const cx<R> *Bb = Bs + (size_t)b * HC * NC;
+    const cx<R> *Xp = Xt + (size_t)p * NXT;
     cx<R> *Yp = Y + (size_t)p * HD * MM;
     for (int j0 = 0; j0 < HD; j0 += kStep1JB) {
         R are[kStep1JB], aim[kStep1JB];
 #pragma unroll
         for (int jj = 0; jj < kStep1JB; ++jj) are[jj] = aim[jj] = 0;
         for (int l = l0; l <= L; ++l) {
-            const int ia = l * l + l + m1, ibb = l * l + l + m2;
-            R xr = 0, xi = 0;   // step 1: sum_h conj(As) Bs
-            for (int h = 0; h < HC; ++h) {
-                const cx<R> u = Aa[(size_t)h * NC + ia], v = Bb[(size_t)h * NC + ibb];
-                xr += u.re * v.re + u.im * v.im;
-                xi += u.re * v.im - u.im * v.re;
-            }
+            const int n = 2 * l + 1;
+            const cx<R> x = Xp[xt_off(l) + (long long)(m1 + l) * n + (m2 + l)];
 #pragma unroll
-            for (int jj = 0; jj < kStep1JB; ++jj) {   // step 1b
+            for (int jj = 0; jj < kStep1JB; ++jj) {
                 if (j0 + jj < HD) {
                     const R vv = sV[l * HD + j0 + jj];
-                    are[jj] += vv * xr;
-                    aim[jj] += vv * xi;
+                    are[jj] += vv * x.re;
+                    aim[jj] += vv * x.im;
                 }
             }
         }
@@ -547,7 +614,7 @@ hipError_t prepare_t(radsvd_vol_plan *p, const VolGrid &g, const void *A, const 
                        p->n_vol, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->As));
     hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_tgt * nbx), p->HC), dim3(256), 0, s, Bc,
                        p->n_tgt, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->Bs));
-    const long long nvd = (long long)p->n_beta * p->HD * p->M * p->M;
+    const long long nvd = (long long)p->n_beta * ((p->HD + kWigJB - 1) / kWigJB) * p->M * p->M;
     hipLaunchKernelGGL(k_vol_wigner<R>, dim3((unsigned)((nvd + 255) / 256)), dim3(256), 0, s, p->beta,
                        p->n_beta, p->L, p->M, p->V, p->HD, reinterpret_cast<R *>(p->Vd));
     return hipGetLastError();
@@ -600,9 +667,13 @@ hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32
     cx<R> *Xf = (flags & RADSVD_OUT_FULL) ? reinterpret_cast<cx<R> *>(X_full) : nullptr;
     for (long long p0 = 0; p0 < n_pairs; p0 += p->chunk) {
         const int np = (int)std::min<long long>(p->chunk, n_pairs - p0);
-        hipLaunchKernelGGL(k_vol_step1<R>, dim3((MM + 255) / 256, np), dim3(256), 0, s,
-                           reinterpret_cast<const cx<R> *>(p->As), reinterpret_cast<const cx<R> *>(p->Bs),
-                           p->n_tgt, p0, p->L, p->M, p->NC, p->HC, p->HD, p->V, reinterpret_cast<cx<R> *>(p->Y));
+        const long long NXT = xt_off(p->L + 1);
+        hipLaunchKernelGGL(k_vol_xt<R>, dim3(p->L + 1, np), dim3(256), 0, s, reinterpret_cast<const cx<R> *>(p->As),
+                           reinterpret_cast<const cx<R> *>(p->Bs), p->n_tgt, p0, p->NC, p->HC, NXT,
+                           reinterpret_cast<cx<R> *>(p->Xt));
+        hipLaunchKernelGGL(k_vol_step1b<R>, dim3((MM + 255) / 256, np), dim3(256), 0, s,
+                           reinterpret_cast<const cx<R> *>(p->Xt), p->L, p->M, p->HD, NXT, p->V,
+                           reinterpret_cast<cx<R> *>(p->Y));
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = launch_land<R>(p, np, p0, Xf, shmem, s);
         if (e == hipSuccess && (flags & RADSVD_OUT_BEST))

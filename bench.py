@@ -568,9 +568,10 @@ def volume_flops(cfg):
 
 def volume_workload(rs, synth, torch, reps=3):
     """Volume alignment (section 4): 96 noisy rotated copies of one target
-    (blob volumes standing in for the paper's reconstructions), K = 48 shells,
-    degrees to L = 48 (M = 97 orders), 97 interior angles, H_C = H_D = 16,
-    FP32 plan.  One step = vol_prepare + vol_align(BEST)."""
+    (real blob volumes standing in for the paper's reconstructions), K = 48
+    shells, degrees to L = 48 (M = 97 orders), 97 interior angles,
+    H_C = H_D = 16, FP32 plan with the real-volume mode; the general complex
+    mode is timed beside it.  One step = vol_prepare + vol_align(BEST)."""
     from paper_2202_07235_amd import volume as rv
     from synth import volumes as sv
     cfg = sv.vol_config("volume")
@@ -578,31 +579,39 @@ def volume_workload(rs, synth, torch, reps=3):
     A = torch.tensor(P.A, dtype=torch.complex64, device="cuda")
     B = torch.tensor(P.B, dtype=torch.complex64, device="cuda")
 
-    def make():
-        return rv.VolPlan(A, B, P.w, cfg.L, cfg.H_C, cfg.H_D, P.beta, precision="fp32")
+    def make(real):
+        return rv.VolPlan(A, B, P.w, cfg.L, cfg.H_C, cfg.H_D, P.beta, precision="fp32", real=real)
 
-    plan = make()
-    plan.align("best")
-    torch.cuda.synchronize()
-    plan.close()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    prep, al = [], []
-    for _ in range(reps):
-        ev[0].record()
-        plan = make()
-        ev[1].record()
+
+    def run(real):
+        plan = make(real)
         plan.align("best")
-        ev[2].record()
         torch.cuda.synchronize()
-        prep.append(ev[0].elapsed_time(ev[1]))
-        al.append(ev[1].elapsed_time(ev[2]))
         plan.close()
+        prep, al = [], []
+        for _ in range(reps):
+            ev[0].record()
+            plan = make(real)
+            ev[1].record()
+            plan.align("best")
+            ev[2].record()
+            torch.cuda.synchronize()
+            prep.append(ev[0].elapsed_time(ev[1]))
+            al.append(ev[1].elapsed_time(ev[2]))
+            plan.close()
+        return prep, al
+
+    prep_c, al_c = run(False)
+    prep, al = run(True)
     n_pairs = cfg.n_vol * cfg.n_tgt
     fl = volume_flops(cfg)
     t = min(al) * 1e-3
     res = {"workload": f"volume: {cfg.n_vol} volumes x {cfg.n_tgt} target, K={cfg.K} L={cfg.L} (M={2 * cfg.L + 1}), "
                        f"n_beta={cfg.n_beta}, H_C={cfg.H_C} H_D={cfg.H_D}, FP32 plan",
            "vol_prepare_ms": min(prep), "vol_align_ms": min(al),
+           "complex_mode": {"vol_prepare_ms": min(prep_c), "vol_align_ms": min(al_c),
+                            "pairs_per_s": n_pairs / (min(al_c) * 1e-3)},
            "pairs_per_s": n_pairs / t, "pairs_per_s_with_prepare": n_pairs / ((min(al) + min(prep)) * 1e-3),
            "flops_per_pair": fl,
            "roofline": {"bound": "alu", "achieved": n_pairs * fl["algorithmic"] / t / 1e12, "peak": 157.3,

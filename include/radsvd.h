@@ -381,6 +381,10 @@ typedef struct {
     const double *w;        /* host [K]: shell weights for \int g(k) k^2 dk, finite, > 0 */
     const double *beta;     /* host [n_beta]: interior angles beta (radians, finite)      */
     radsvd_precision prec;  /* RADSVD_FP64 or RADSVD_FP32 (contraction and I/O type)      */
+    int real_volumes;       /* 1: the caller asserts every volume and target is real in    */
+                            /* space, conj(A_l^m) = (-1)^(l+m) A_l^-m; X is then real and  */
+                            /* only its real part is computed, from the orders m1 >= 0     */
+                            /* (FULL has zero imaginary parts); 0: general complex         */
 } radsvd_vol_problem;
 
 typedef struct radsvd_vol_plan radsvd_vol_plan;   /* opaque host metadata */

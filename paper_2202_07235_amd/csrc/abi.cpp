@@ -501,6 +501,8 @@ radsvd_status validate_vol(const radsvd_vol_problem *pr) {
             return fail(RADSVD_ERR_INVALID_ARG, "w[%d] must be finite and > 0", r);
     for (int i = 0; i < pr->n_beta; ++i)
         if (!isfinite(pr->beta[i])) return fail(RADSVD_ERR_INVALID_ARG, "beta[%d] not finite", i);
+    if (pr->real_volumes != 0 && pr->real_volumes != 1)
+        return fail(RADSVD_ERR_INVALID_ARG, "real_volumes must be 0 or 1");
     return RADSVD_OK;
 }
 
@@ -603,6 +605,7 @@ radsvd_status vol_prepare(const radsvd_vol_problem *prob, int n_vol, const void 
     p->chunk = Lo.chunk;
     p->user_U = U_in != nullptr;
     p->user_V = V_in != nullptr;
+    p->real = prob->real_volumes;
     p->ws = reinterpret_cast<char *>(ws);
     p->ws_bytes = ws_bytes;
     char *w = p->ws;

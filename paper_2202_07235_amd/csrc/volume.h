@@ -27,6 +27,7 @@ struct radsvd_vol_plan {
     int K, L, M, NC, HC, HD, n_beta, prec, n_vol, n_tgt;
     int chunk;                 // pairs per block of pairs
     int user_U, user_V;
+    int real;                  // real volumes: half the orders, real X
     char *ws;
     size_t ws_bytes;
     double *w, *beta;          // [K], [n_beta]

@@ -173,7 +173,8 @@ constexpr int kWigJB = 16;   // degree ranks accumulated per recurrence
 // in l, accumulated into each rank's table
 template <typename R>
 __global__ __launch_bounds__(256) void k_vol_wigner(const double *__restrict__ beta, int n_beta, int L, int M,
-                                                    const double *__restrict__ V, int HD, R *__restrict__ Vd) {
+                                                    const double *__restrict__ V, int HD, int real,
+                                                    R *__restrict__ Vd) {
     const long long MM = (long long)M * M;
     const int njb = (HD + kWigJB - 1) / kWigJB;
     const long long total = (long long)n_beta * njb * MM;
@@ -184,6 +185,7 @@ __global__ __launch_bounds__(256) void k_vol_wigner(const double *__restrict__ b
     const int jb = (int)(t % njb) * kWigJB;
     const int ib = (int)(t / njb);
     const int im1 = (int)(el / M), im2 = (int)(el - (long long)im1 * M);
+    if (real && im1 > L) return;   // orders m1 < 0 are not read for real volumes
     const int a = im1 <= L ? im1 : im1 - M, b = im2 <= L ? im2 : im2 - M;
     const int l0 = std::max(a < 0 ? -a : a, b < 0 ? -b : b);
     double sb, cb;
@@ -286,7 +288,7 @@ constexpr int kStep1JB = 16;   // degree ranks accumulated per pass
 // every Xt entry is read once
 template <typename R>
 __global__ __launch_bounds__(256) void k_vol_step1b(const cx<R> *__restrict__ Xt, int L, int M, int HD, long long NXT,
-                                                    const double *__restrict__ V, cx<R> *__restrict__ Y) {
+                                                    const double *__restrict__ V, int nrow, cx<R> *__restrict__ Y) {
     __shared__ R sV[(kVolMaxL32 + 1) * (kVolMaxL32 + 1)];   // [l][j], j < HD
     const int L1 = L + 1;
     for (int i = threadIdx.x; i < L1 * HD; i += 256) {
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(256) void k_vol_step1b(const cx<R> *__restrict__ Xt
     __syncthreads();
     const int MM = M * M;
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= MM) return;
+    if (i >= nrow * M) return;   // nrow = M, or L + 1 for real volumes (orders m1 >= 0)
     const long long p = blockIdx.y;
     const int im1 = i / M, im2 = i - im1 * M;
     const int m1 = im1 <= L ? im1 : im1 - M, m2 = im2 <= L ? im2 : im2 - M;
@@ -333,11 +335,11 @@ __device__ __forceinline__ bool vol_before(R v, int i, R w, int j) {
     return v > w || (v == w && i < j);
 }
 
-// step 2 into LDS: S[i] = sum_j Vd[ib][j][i] Y[p][j][i]
+// step 2 into LDS: S[i] = sum_j Vd[ib][j][i] Y[p][j][i] for i < count (planes of MM entries)
 template <typename R>
 __device__ __forceinline__ void land_step2(const cx<R> *__restrict__ Yp, const R *__restrict__ Vb, int HD, int MM,
-                                           cx<R> *S, int tid, int nthr) {
-    for (int i = tid; i < MM; i += nthr) {
+                                           int count, cx<R> *S, int tid, int nthr) {
+    for (int i = tid; i < count; i += nthr) {
         R re = 0, im = 0;
         for (int j = 0; j < HD; ++j) {
             const R v = Vb[(size_t)j * MM + i];
@@ -408,7 +410,7 @@ __device__ void land_epilogue(const cx<R> *S, int MM, cx<R> *Xo, int tid, int nt
 // rows (then whole columns), reads all of one, then overwrites it
 template <typename R>
 __global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, const R *__restrict__ Vd,
-                                                  int n_beta, int M, int HD, long long p0,
+                                                  int n_beta, int M, int HD, long long p0, int real,
                                                   cx<R> *__restrict__ Xfull, double *__restrict__ part_val,
                                                   int32_t *__restrict__ part_idx) {
     extern __shared__ __align__(16) unsigned char vol_smem[];
@@ -420,7 +422,18 @@ __global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, c
     const long long p = blockIdx.y;
     const int MM = M * M, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     land_twiddles(tw, M, tid, 256);
-    land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, S, tid, 256);
+    const int L = M / 2;
+    if (real) {   // X-hat(-m1, -m2) = conj X-hat(m1, m2): the rows m1 < 0 from the rows m1 > 0
+        land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, (L + 1) * M, S, tid, 256);
+        __syncthreads();
+        for (int i = (L + 1) * M + tid; i < MM; i += 256) {
+            const int im1 = i / M, im2 = i - im1 * M;
+            const cx<R> x = S[(M - im1) * M + (im2 == 0 ? 0 : M - im2)];
+            S[i] = cx<R>{x.re, -x.im};
+        }
+    } else {
+        land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, MM, S, tid, 256);
+    }
     __syncthreads();
     constexpr int NCH = (kVolMaxM + 63) / 64;
     for (int pass = 0; pass < 2; ++pass) {
@@ -458,6 +471,10 @@ __global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, c
         }
         __syncthreads();
     }
+    if (real) {
+        for (int i = tid; i < MM; i += 256) S[i].im = 0;
+        __syncthreads();
+    }
     cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
     land_epilogue<R>(S, MM, Xo, tid, 256, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
                      part_idx + (size_t)p * n_beta + ib);
@@ -490,7 +507,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
     const long long p = blockIdx.y;
     const int MM = M * M, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     land_twiddles(tw, M, tid, NTHR);
-    land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, S, tid, NTHR);
+    land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, MM, S, tid, NTHR);
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
     const int ia = wv * 16 + li;   // A row: m1 (first product) or c (second)
@@ -505,7 +522,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
             tix[t] = (lk * j) % M;       // (e j) mod M for e = lk
             tst[t] = (4 * j) % M;
         }
-        for (int e0 = 0; e0 < NT * 16; e0 += 4) {
+        for (int e0 = 0; e0 < M; e0 += 4) {
             const int e = e0 + lk;
             float xr = 0.f, xi = 0.f;
             if (e < M && ia < M) {
@@ -544,6 +561,133 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
                     else
                         S[j * M + i] = v;
                 }
+            }
+        }
+        __syncthreads();
+    }
+    cx<float> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
+    land_epilogue<float>(S, MM, Xo, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
+                         part_idx + (size_t)p * n_beta + ib);
+}
+
+
+// FP32 plans of real volumes: X-hat(-m1, -m2) = conj X-hat(m1, m2), so only the
+// rows m1 = 0..L of X-hat are formed, and X is real:
+//   R(m1, k)   = sum_{m2} X-hat(m1, m2) F[m2][k]                      (complex, rows m1 >= 0)
+//   X(m1', k)  = sum_{m1 = 0..L} c(m1) Re[F[m1][m1'] R(m1, k)],  c(0) = 1, c(m1 > 0) = 2.
+// The first product: wave w computes column tile w for every row block of
+// m1 >= 0 (the twiddle fragment is shared by the row blocks); its in-place
+// write waits for a workgroup barrier, since every wave reads whole rows.
+// The second: wave w owns column block w (as in the complex kernel), two real
+// MFMA products per tile (re R x re F - im R x im F), over K = L + 1 orders.
+template <int NT>
+__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> *__restrict__ Y,
+                                                                const float *__restrict__ Vd, int n_beta, int M,
+                                                                int HD, long long p0, cx<float> *__restrict__ Xfull,
+                                                                double *__restrict__ part_val,
+                                                                int32_t *__restrict__ part_idx) {
+    extern __shared__ __align__(16) unsigned char vol_smem[];
+    cx<float> *S = reinterpret_cast<cx<float> *>(vol_smem);   // [M][M]
+    cx<float> *tw = S + M * M;
+    __shared__ float rv[NT];
+    __shared__ int ri[NT], rbad[NT];
+    constexpr int NTHR = 64 * NT;
+    constexpr int NRB = (NT * 16 / 2 + 1 + 15) / 16;   // row blocks covering m1 = 0..L, L < 8 NT
+    const int ib = blockIdx.x;
+    const long long p = blockIdx.y;
+    const int MM = M * M, L = M / 2, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    land_twiddles(tw, M, tid, NTHR);
+    land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, (L + 1) * M, S, tid, NTHR);
+    __syncthreads();
+    const int li = lane & 15, lk = lane >> 4;
+    {   // first product: rows m1 = 0..L, column tile wv
+        vol_f4 are[NRB], aim[NRB];
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) {
+            are[r] = vol_f4{0.f, 0.f, 0.f, 0.f};
+            aim[r] = vol_f4{0.f, 0.f, 0.f, 0.f};
+        }
+        const int j = wv * 16 + li;
+        int tix = (lk * j) % M;
+        const int tst = (4 * j) % M;
+        for (int e0 = 0; e0 < M; e0 += 4) {
+            const int e = e0 + lk;
+            float fr = 0.f, fi = 0.f;
+            if (e < M && j < M) {
+                const cx<float> f = tw[tix];
+                fr = f.re;
+                fi = f.im;
+            }
+            tix += tst;
+            if (tix >= M) tix -= M;
+#pragma unroll
+            for (int r = 0; r < NRB; ++r) {
+                const int row = r * 16 + li;
+                float xr = 0.f, xi = 0.f;
+                if (e < M && row <= L) {
+                    const cx<float> x = S[row * M + e];
+                    xr = x.re;
+                    xi = x.im;
+                }
+                are[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fr, are[r], 0, 0, 0);
+                are[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, -fi, are[r], 0, 0, 0);
+                aim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fi, aim[r], 0, 0, 0);
+                aim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, fr, aim[r], 0, 0, 0);
+            }
+        }
+        __syncthreads();   // every wave has read its rows
+#pragma unroll
+        for (int r = 0; r < NRB; ++r)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = r * 16 + 4 * lk + q;
+                if (row <= L && j < M) S[row * M + j] = cx<float>{are[r][q], aim[r][q]};
+            }
+        __syncthreads();
+    }
+    {   // second product: column block wv, all rows m1' of the output
+        vol_f4 acc[NT];
+        int tix[NT], tst[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            acc[t] = vol_f4{0.f, 0.f, 0.f, 0.f};
+            const int j = t * 16 + li;
+            tix[t] = (lk * j) % M;
+            tst[t] = (4 * j) % M;
+        }
+        const int ia = wv * 16 + li;   // column c of R
+        for (int e0 = 0; e0 <= L; e0 += 4) {
+            const int e = e0 + lk;     // order m1 >= 0
+            float xr = 0.f, xi = 0.f;
+            if (e <= L && ia < M) {
+                const cx<float> x = S[e * M + ia];
+                const float c = e == 0 ? 1.f : 2.f;
+                xr = c * x.re;
+                xi = -c * x.im;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int j = t * 16 + li;
+                float fr = 0.f, fi = 0.f;
+                if (e <= L && j < M) {
+                    const cx<float> f = tw[tix[t]];
+                    fr = f.re;
+                    fi = f.im;
+                }
+                tix[t] += tst[t];
+                if (tix[t] >= M) tix[t] -= M;
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fr, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, fi, acc[t], 0, 0, 0);
+            }
+        }
+        vol_wave_sync();
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = t * 16 + li;   // output row m1'
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int c = wv * 16 + 4 * lk + q;
+                if (c < M && j < M) S[j * M + c] = cx<float>{acc[t][q], 0.f};
             }
         }
         __syncthreads();
@@ -616,19 +760,24 @@ hipError_t prepare_t(radsvd_vol_plan *p, const VolGrid &g, const void *A, const 
                        p->n_tgt, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->Bs));
     const long long nvd = (long long)p->n_beta * ((p->HD + kWigJB - 1) / kWigJB) * p->M * p->M;
     hipLaunchKernelGGL(k_vol_wigner<R>, dim3((unsigned)((nvd + 255) / 256)), dim3(256), 0, s, p->beta,
-                       p->n_beta, p->L, p->M, p->V, p->HD, reinterpret_cast<R *>(p->Vd));
+                       p->n_beta, p->L, p->M, p->V, p->HD, p->real, reinterpret_cast<R *>(p->Vd));
     return hipGetLastError();
 }
 
 template <int NT>
 hipError_t launch_land_mfma(const radsvd_vol_plan *p, int np, long long p0, cx<float> *Xf, size_t shmem,
                             hipStream_t s) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_vol_land_mfma<NT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    const void *fn = p->real ? (const void *)k_vol_land_mfma_real<NT> : (const void *)k_vol_land_mfma<NT>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_vol_land_mfma<NT>, dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
-                       reinterpret_cast<const cx<float> *>(p->Y), reinterpret_cast<const float *>(p->Vd), p->n_beta,
-                       p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
+    if (p->real)
+        hipLaunchKernelGGL(k_vol_land_mfma_real<NT>, dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
+                           reinterpret_cast<const cx<float> *>(p->Y), reinterpret_cast<const float *>(p->Vd),
+                           p->n_beta, p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
+    else
+        hipLaunchKernelGGL(k_vol_land_mfma<NT>, dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
+                           reinterpret_cast<const cx<float> *>(p->Y), reinterpret_cast<const float *>(p->Vd),
+                           p->n_beta, p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
     return hipGetLastError();
 }
 
@@ -653,7 +802,7 @@ hipError_t launch_land(const radsvd_vol_plan *p, int np, long long p0, cx<R> *Xf
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_vol_land<R>, dim3(p->n_beta, np), dim3(256), shmem, s,
                            reinterpret_cast<const cx<R> *>(p->Y), reinterpret_cast<const R *>(p->Vd), p->n_beta,
-                           p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
+                           p->M, p->HD, p0, p->real, Xf, p->part_val, p->part_idx);
         return hipGetLastError();
     }
 }
@@ -671,8 +820,9 @@ hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32
         hipLaunchKernelGGL(k_vol_xt<R>, dim3(p->L + 1, np), dim3(256), 0, s, reinterpret_cast<const cx<R> *>(p->As),
                            reinterpret_cast<const cx<R> *>(p->Bs), p->n_tgt, p0, p->NC, p->HC, NXT,
                            reinterpret_cast<cx<R> *>(p->Xt));
-        hipLaunchKernelGGL(k_vol_step1b<R>, dim3((MM + 255) / 256, np), dim3(256), 0, s,
-                           reinterpret_cast<const cx<R> *>(p->Xt), p->L, p->M, p->HD, NXT, p->V,
+        const int nrow = p->real ? p->L + 1 : p->M;
+        hipLaunchKernelGGL(k_vol_step1b<R>, dim3((nrow * p->M + 255) / 256, np), dim3(256), 0, s,
+                           reinterpret_cast<const cx<R> *>(p->Xt), p->L, p->M, p->HD, NXT, p->V, nrow,
                            reinterpret_cast<cx<R> *>(p->Y));
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = launch_land<R>(p, np, p0, Xf, shmem, s);

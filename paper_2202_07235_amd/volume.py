@@ -22,15 +22,15 @@ __all__ = ["VolPlan", "vol_prepare_workspace", "vol_prepare", "vol_align", "vol_
 class _VolProblem(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int), ("L", ctypes.c_int), ("H_C", ctypes.c_int), ("H_D", ctypes.c_int),
                 ("n_beta", ctypes.c_int), ("w", ctypes.POINTER(ctypes.c_double)),
-                ("beta", ctypes.POINTER(ctypes.c_double)), ("prec", ctypes.c_int)]
+                ("beta", ctypes.POINTER(ctypes.c_double)), ("prec", ctypes.c_int), ("real_volumes", ctypes.c_int)]
 
 
-def make_vol_problem(K, L, H_C, H_D, w, beta, prec):
+def make_vol_problem(K, L, H_C, H_D, w, beta, prec, real=0):
     """The C problem struct and the host arrays it points into (keep both)."""
     w = np.ascontiguousarray(w, dtype=np.float64)
     beta = np.ascontiguousarray(beta, dtype=np.float64)
     dp = ctypes.POINTER(ctypes.c_double)
-    pr = _VolProblem(K, L, H_C, H_D, len(beta), w.ctypes.data_as(dp), beta.ctypes.data_as(dp), prec)
+    pr = _VolProblem(K, L, H_C, H_D, len(beta), w.ctypes.data_as(dp), beta.ctypes.data_as(dp), prec, int(real))
     return pr, (w, beta)
 
 
@@ -65,7 +65,10 @@ class VolPlan:
 
     def __init__(self, A_sh: torch.Tensor, B_sh: torch.Tensor, w, L: int, H_C: int, H_D: int, beta,
                  precision: str = "fp32", U: torch.Tensor | None = None, V: torch.Tensor | None = None,
-                 stream=None):
+                 real: bool = False, stream=None):
+        """real=True asserts that every volume and target is real in space
+        (conj(A_l^m) = (-1)^(l+m) A_l^-m): X is then real and computed from
+        half the orders."""
         prec = PRECISIONS[precision]
         if prec not in (FP32, FP64):
             raise ValueError("volume plans take precision 'fp32' or 'fp64'")
@@ -80,8 +83,8 @@ class VolPlan:
         self.L, self.M, self.H_C, self.H_D = L, 2 * L + 1, H_C, H_D
         self.beta = np.asarray(beta, dtype=np.float64).reshape(-1)
         self.n_beta = len(self.beta)
-        self.precision, self.prec = precision, prec
-        self.problem, self._keep = make_vol_problem(self.K, L, H_C, H_D, w, self.beta, prec)
+        self.precision, self.prec, self.real = precision, prec, bool(real)
+        self.problem, self._keep = make_vol_problem(self.K, L, H_C, H_D, w, self.beta, prec, int(real))
         nbytes = vol_prepare_workspace(self.problem, self.n_vol, self.n_tgt)
         self.device = A_sh.device
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

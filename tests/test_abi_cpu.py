@@ -120,14 +120,14 @@ def _vprob(**kw):
     from paper_2202_07235_amd import volume as rv
     K, L = kw.get("K", 8), kw.get("L", 6)
     return rv.make_vol_problem(K, L, kw.get("H_C", 4), kw.get("H_D", 4), kw.get("w", np.ones(K)),
-                               kw.get("beta", np.linspace(0, 6, 5)), kw.get("prec", rs.FP32))
+                               kw.get("beta", np.linspace(0, 6, 5)), kw.get("prec", rs.FP32), kw.get("real", 0))
 
 
 @pytest.mark.parametrize("bad", [
     dict(K=1), dict(K=129), dict(L=0), dict(L=65), dict(L=49, prec=rs.FP64), dict(prec=rs.BF16),
     dict(prec=rs.BF16X3), dict(H_C=0), dict(H_C=9), dict(H_D=0), dict(H_D=8), dict(beta=np.zeros(0)),
     dict(beta=np.zeros(257)), dict(beta=np.array([0.0, np.inf])), dict(w=np.r_[np.ones(7), 0.0]),
-    dict(w=np.r_[np.ones(7), np.nan]),
+    dict(w=np.r_[np.ones(7), np.nan]), dict(real=2), dict(real=-1),
 ])
 def test_invalid_volume_problem_rejected(bad):
     pr, keep = _vprob(**bad)

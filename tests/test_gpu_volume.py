@@ -78,12 +78,17 @@ def _proj_dist(U1, U2, H):
     return np.abs(U1[:, :H] @ U1[:, :H].T - U2[:, :H] @ U2[:, :H].T).max()
 
 
-@pytest.mark.parametrize("name,precision", [("vtiny", "fp64"), ("vtiny", "fp32"), ("vsmall", "fp32"),
-                                            ("vsmall", "fp64")])
-def test_volume_matches_oracle(name, precision):
+@pytest.mark.parametrize("name,precision,real", [("vtiny", "fp64", False), ("vtiny", "fp32", False),
+                                                 ("vsmall", "fp32", False), ("vsmall", "fp64", False),
+                                                 ("vtiny", "fp32", True), ("vsmall", "fp32", True),
+                                                 ("vsmall", "fp64", True)])
+def test_volume_matches_oracle(name, precision, real):
+    """real=True: the volumes are real in space (blob maps plus real noise), the
+    library computes X from half the orders; the oracle's complex X has an
+    imaginary part at rounding level, the library's is exactly zero."""
     cfg = sv.vol_config(name)
     P = sv.make_volume_problem(cfg, seed=2000 + len(name))
-    plan, A, B = _plan(P, precision)
+    plan, A, B = _plan(P, precision, real=real)
     out = plan.align("best+full")
     U, lc, V, ld = (t.cpu().numpy() for t in plan.UV())
     torch.cuda.synchronize()
@@ -100,7 +105,9 @@ def test_volume_matches_oracle(name, precision):
     # landscape with the library's U, V
     Xo = ov.landscape_all(A, B, P.w, U, cfg.H_C, V, cfg.H_D, cfg.L, P.beta)
     Xg = _host(out["X"])
-    _compare(Xg, Xo, TOL[precision], f"{name}-{precision}")
+    if real:
+        assert np.all(Xg.imag == 0)
+    _compare(Xg, Xo, TOL[precision], f"{name}-{precision}{'-real' if real else ''}")
     _check_best(out["best_score"].cpu().numpy(), out["best_idx"].cpu().numpy(), Xo, TOL[precision])
 
 
@@ -167,8 +174,9 @@ def test_volume_edges():
     assert torch.isnan(lc).all() and torch.isnan(ld).all()
 
 
-@pytest.mark.parametrize("L,precision,n_vol", [(64, "fp32", 130), (48, "fp64", 3)])
-def test_volume_largest_degree(L, precision, n_vol):
+@pytest.mark.parametrize("L,precision,n_vol,real", [(64, "fp32", 130, False), (48, "fp64", 3, False),
+                                                    (64, "fp32", 130, True)])
+def test_volume_largest_degree(L, precision, n_vol, real):
     """The largest supported degree; for FP32 at H_D = L + 1 the 130 pairs span
     two blocks of pairs (the per-pair intermediates take 11.6 MB, so a block of
     the 1 GiB scratch holds 92 pairs)."""
@@ -176,7 +184,7 @@ def test_volume_largest_degree(L, precision, n_vol):
                         n_beta=2)
     P = sv.make_volume_problem(cfg, seed=2400 + L)
     betas = np.array([0.8, 2.6])
-    plan, A, B = _plan(P, precision, betas=betas)
+    plan, A, B = _plan(P, precision, betas=betas, real=real)
     out = plan.align("best+full")
     U, _, V, _ = (t.cpu().numpy() for t in plan.UV())
     pairs = [(0, 0), (n_vol // 2, 0), (n_vol - 1, 0)]
@@ -194,11 +202,12 @@ def _rot_angle(R):
     return math.acos(max(-1.0, min(1.0, (np.trace(R) - 1) / 2)))
 
 
-def test_volume_paper_shaped_workload():
+@pytest.mark.parametrize("real", [False, True])
+def test_volume_paper_shaped_workload(real):
     """96 noisy rotated copies against one target, K = L = 48, 97 angles."""
     cfg = sv.vol_config("volume")
     P = sv.make_volume_problem(cfg, seed=2500)
-    plan, A, B = _plan(P, "fp32")
+    plan, A, B = _plan(P, "fp32", real=real)
     out = plan.align("best+full")
     U, _, V, _ = (t.cpu().numpy() for t in plan.UV())
     bs, bi = out["best_score"].cpu().numpy(), out["best_idx"].cpu().numpy()

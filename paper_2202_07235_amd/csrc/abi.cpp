@@ -516,7 +516,7 @@ radsvd_status validate_vol_counts(int n_vol, int n_tgt) {
 
 struct VolLayout {
     size_t off_w, off_beta, off_C, off_U, off_lamC, off_logC, off_D, off_V, off_lamD, off_logD, off_As, off_Bs,
-        off_Vd, off_Xt, off_Y, off_pv, off_pi, total;
+        off_Vd, off_Xt, off_Y, off_Xh, off_pv, off_pi, total;
     int chunk;
 };
 
@@ -528,7 +528,7 @@ VolLayout make_vol_layout(const radsvd_vol_problem *pr, int n_vol, int n_tgt) {
     const long long n_pairs = (long long)n_vol * n_tgt;
     const long long L1l = L1;
     const size_t nxt = (size_t)(L1l * (2 * L1l - 1) * (2 * L1l + 1) / 3);   // sum_{l <= L} (2l+1)^2
-    const size_t per_pair = ((size_t)pr->H_D * MM + nxt) * CX;
+    const size_t per_pair = ((size_t)pr->H_D * MM + nxt + (size_t)pr->n_beta * MM) * CX;
     long long chunk = (long long)(kVolChunkBytes / per_pair);
     chunk = std::max<long long>(1, std::min<long long>(chunk, kVolMaxChunk));
     chunk = std::min(chunk, n_pairs);
@@ -554,6 +554,7 @@ VolLayout make_vol_layout(const radsvd_vol_problem *pr, int n_vol, int n_tgt) {
     Lo.off_Vd = take((size_t)pr->n_beta * pr->H_D * MM * R);
     Lo.off_Xt = take((size_t)chunk * nxt * CX);
     Lo.off_Y = take((size_t)chunk * pr->H_D * MM * CX);
+    Lo.off_Xh = take((size_t)chunk * pr->n_beta * MM * CX);
     Lo.off_pv = take((size_t)chunk * pr->n_beta * 8);
     Lo.off_pi = take((size_t)chunk * pr->n_beta * 4);
     Lo.total = off;
@@ -624,6 +625,7 @@ radsvd_status vol_prepare(const radsvd_vol_problem *prob, int n_vol, const void 
     p->Vd = w + Lo.off_Vd;
     p->Xt = w + Lo.off_Xt;
     p->Y = w + Lo.off_Y;
+    p->Xh = w + Lo.off_Xh;
     p->part_val = reinterpret_cast<double *>(w + Lo.off_pv);
     p->part_idx = reinterpret_cast<int32_t *>(w + Lo.off_pi);
     VolGrid g;

@@ -38,6 +38,7 @@ struct radsvd_vol_plan {
     void *Vd;                  // [n_beta][H_D][M][M] real: [v_j^T d](beta)
     void *Xt;                  // [chunk][sum_l (2l+1)^2] complex: step 1, degree-major
     void *Y;                   // [chunk][H_D][M][M] complex: step 1b
+    void *Xh;                  // [chunk][n_beta][count] complex: step 2 (count = M^2, or (L+1) M real)
     double *part_val;          // [chunk][n_beta]: best Re X of one angle (NaN: a NaN seen)
     int32_t *part_idx;         // [chunk][n_beta]: its m1' M + m2'
 };

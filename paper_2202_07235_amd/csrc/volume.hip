@@ -15,8 +15,10 @@
 //   k_vol_xt      step 1, Xt_l(m1, m2) = sum_h conj(As[h]_l^m1) Bs[h]_l^m2, one workgroup
 //                 per (degree, pair) with the degree's blocks staged in LDS;
 //   k_vol_step1b  Y_j(m1, m2) = sum_l V[l][j] Xt_l(m1, m2);
-//   k_vol_land*   one workgroup per (pair, beta): Xhat = sum_j [v_j^T d](beta) Y_j in
-//                 LDS, then the 2-D transform over the orders (M = 2L + 1 is odd:
+//   k_vol_step2   Xhat(beta) = sum_j [v_j^T d](beta) Y_j for a block of pairs and every
+//                 angle, 8 pairs x 8 angles per thread;
+//   k_vol_land*   one workgroup per (pair, beta): Xhat into LDS, then the 2-D
+//                 transform over the orders (M = 2L + 1 is odd:
 //                 a direct DFT against an LDS twiddle table, as two dense complex
 //                 matrix products on the FP32 matrix cores, or for FP64 plans
 //                 two passes on the vector units), then the best Re X of the
@@ -335,20 +337,47 @@ __device__ __forceinline__ bool vol_before(R v, int i, R w, int j) {
     return v > w || (v == w && i < j);
 }
 
-// step 2 into LDS: S[i] = sum_j Vd[ib][j][i] Y[p][j][i] for i < count (planes of MM entries)
-template <typename R>
-__device__ __forceinline__ void land_step2(const cx<R> *__restrict__ Yp, const R *__restrict__ Vb, int HD, int MM,
-                                           int count, cx<R> *S, int tid, int nthr) {
-    for (int i = tid; i < count; i += nthr) {
-        R re = 0, im = 0;
-        for (int j = 0; j < HD; ++j) {
-            const R v = Vb[(size_t)j * MM + i];
-            const cx<R> y = Yp[(size_t)j * MM + i];
-            re += v * y.re;
-            im += v * y.im;
-        }
-        S[i] = cx<R>{re, im};
+// step 2 for a block of pairs: Xh[p][ib][i] = sum_j Vd[ib][j][i] Y[p][j][i] for i < count
+// (count = M^2, or (L+1) M for real volumes: the orders m1 >= 0).  Each thread
+// keeps PB pairs x BB angles of one entry in registers, so every Y value is
+// read by ceil(n_beta / BB) threads and every table value by ceil(np / PB).
+template <typename R, int PB, int BB>
+__global__ __launch_bounds__(256) void k_vol_step2(const cx<R> *__restrict__ Y, const R *__restrict__ Vd, int np,
+                                                   int n_beta, int HD, int MM, int count, cx<R> *__restrict__ Xh) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const int pa = blockIdx.y * PB, ba = blockIdx.z * BB;
+    cx<R> acc[PB][BB];
+#pragma unroll
+    for (int a = 0; a < PB; ++a)
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[a][b] = cx<R>{0, 0};
+    for (int j = 0; j < HD; ++j) {
+        cx<R> y[PB];
+        R v[BB];
+#pragma unroll
+        for (int a = 0; a < PB; ++a)
+            y[a] = pa + a < np ? Y[((size_t)(pa + a) * HD + j) * MM + i] : cx<R>{0, 0};
+#pragma unroll
+        for (int b = 0; b < BB; ++b) v[b] = ba + b < n_beta ? Vd[((size_t)(ba + b) * HD + j) * MM + i] : R(0);
+#pragma unroll
+        for (int a = 0; a < PB; ++a)
+#pragma unroll
+            for (int b = 0; b < BB; ++b) {
+                acc[a][b].re += v[b] * y[a].re;
+                acc[a][b].im += v[b] * y[a].im;
+            }
     }
+#pragma unroll
+    for (int a = 0; a < PB; ++a)
+#pragma unroll
+        for (int b = 0; b < BB; ++b)
+            if (pa + a < np && ba + b < n_beta) Xh[((size_t)(pa + a) * n_beta + ba + b) * count + i] = acc[a][b];
+}
+
+template <typename R>
+__device__ __forceinline__ void land_load(const cx<R> *__restrict__ Xp, int count, cx<R> *S, int tid, int nthr) {
+    for (int i = tid; i < count; i += nthr) S[i] = Xp[i];
 }
 
 template <typename R>
@@ -409,8 +438,8 @@ __device__ void land_epilogue(const cx<R> *S, int MM, cx<R> *Xo, int tid, int nt
 // FP64 plans: step 3 on the vector units, four waves; each wave owns whole
 // rows (then whole columns), reads all of one, then overwrites it
 template <typename R>
-__global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, const R *__restrict__ Vd,
-                                                  int n_beta, int M, int HD, long long p0, int real,
+__global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Xh, int n_beta, int M, long long p0,
+                                                  int real,
                                                   cx<R> *__restrict__ Xfull, double *__restrict__ part_val,
                                                   int32_t *__restrict__ part_idx) {
     extern __shared__ __align__(16) unsigned char vol_smem[];
@@ -424,7 +453,7 @@ __global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, c
     land_twiddles(tw, M, tid, 256);
     const int L = M / 2;
     if (real) {   // X-hat(-m1, -m2) = conj X-hat(m1, m2): the rows m1 < 0 from the rows m1 > 0
-        land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, (L + 1) * M, S, tid, 256);
+        land_load(Xh + ((size_t)p * n_beta + ib) * (L + 1) * M, (L + 1) * M, S, tid, 256);
         __syncthreads();
         for (int i = (L + 1) * M + tid; i < MM; i += 256) {
             const int im1 = i / M, im2 = i - im1 * M;
@@ -432,7 +461,7 @@ __global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Y, c
             S[i] = cx<R>{x.re, -x.im};
         }
     } else {
-        land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, MM, S, tid, 256);
+        land_load(Xh + ((size_t)p * n_beta + ib) * MM, MM, S, tid, 256);
     }
     __syncthreads();
     constexpr int NCH = (kVolMaxM + 63) / 64;
@@ -492,8 +521,7 @@ typedef float vol_f4 __attribute__((ext_vector_type(4)));
 // Operand layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16], r = 0..3.
 template <int NT>
-__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__restrict__ Y,
-                                                           const float *__restrict__ Vd, int n_beta, int M, int HD,
+__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__restrict__ Xh, int n_beta, int M,
                                                            long long p0, cx<float> *__restrict__ Xfull,
                                                            double *__restrict__ part_val,
                                                            int32_t *__restrict__ part_idx) {
@@ -507,7 +535,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
     const long long p = blockIdx.y;
     const int MM = M * M, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     land_twiddles(tw, M, tid, NTHR);
-    land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, MM, S, tid, NTHR);
+    land_load(Xh + ((size_t)p * n_beta + ib) * MM, MM, S, tid, NTHR);
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
     const int ia = wv * 16 + li;   // A row: m1 (first product) or c (second)
@@ -581,9 +609,8 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
 // The second: wave w owns column block w (as in the complex kernel), two real
 // MFMA products per tile (re R x re F - im R x im F), over K = L + 1 orders.
 template <int NT>
-__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> *__restrict__ Y,
-                                                                const float *__restrict__ Vd, int n_beta, int M,
-                                                                int HD, long long p0, cx<float> *__restrict__ Xfull,
+__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> *__restrict__ Xh, int n_beta, int M,
+                                                                long long p0, cx<float> *__restrict__ Xfull,
                                                                 double *__restrict__ part_val,
                                                                 int32_t *__restrict__ part_idx) {
     extern __shared__ __align__(16) unsigned char vol_smem[];
@@ -597,7 +624,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> 
     const long long p = blockIdx.y;
     const int MM = M * M, L = M / 2, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     land_twiddles(tw, M, tid, NTHR);
-    land_step2(Y + (size_t)p * HD * MM, Vd + (size_t)ib * HD * MM, HD, MM, (L + 1) * M, S, tid, NTHR);
+    land_load(Xh + ((size_t)p * n_beta + ib) * (L + 1) * M, (L + 1) * M, S, tid, NTHR);
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
     {   // first product: rows m1 = 0..L, column tile wv
@@ -772,12 +799,12 @@ hipError_t launch_land_mfma(const radsvd_vol_plan *p, int np, long long p0, cx<f
     if (e != hipSuccess) return e;
     if (p->real)
         hipLaunchKernelGGL(k_vol_land_mfma_real<NT>, dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
-                           reinterpret_cast<const cx<float> *>(p->Y), reinterpret_cast<const float *>(p->Vd),
-                           p->n_beta, p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
+                           reinterpret_cast<const cx<float> *>(p->Xh), p->n_beta, p->M, p0, Xf, p->part_val,
+                           p->part_idx);
     else
         hipLaunchKernelGGL(k_vol_land_mfma<NT>, dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
-                           reinterpret_cast<const cx<float> *>(p->Y), reinterpret_cast<const float *>(p->Vd),
-                           p->n_beta, p->M, p->HD, p0, Xf, p->part_val, p->part_idx);
+                           reinterpret_cast<const cx<float> *>(p->Xh), p->n_beta, p->M, p0, Xf, p->part_val,
+                           p->part_idx);
     return hipGetLastError();
 }
 
@@ -801,8 +828,8 @@ hipError_t launch_land(const radsvd_vol_plan *p, int np, long long p0, cx<R> *Xf
                                            (int)shmem);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_vol_land<R>, dim3(p->n_beta, np), dim3(256), shmem, s,
-                           reinterpret_cast<const cx<R> *>(p->Y), reinterpret_cast<const R *>(p->Vd), p->n_beta,
-                           p->M, p->HD, p0, p->real, Xf, p->part_val, p->part_idx);
+                           reinterpret_cast<const cx<R> *>(p->Xh), p->n_beta, p->M, p0, p->real, Xf, p->part_val,
+                           p->part_idx);
         return hipGetLastError();
     }
 }
@@ -824,6 +851,13 @@ hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32
         hipLaunchKernelGGL(k_vol_step1b<R>, dim3((nrow * p->M + 255) / 256, np), dim3(256), 0, s,
                            reinterpret_cast<const cx<R> *>(p->Xt), p->L, p->M, p->HD, NXT, p->V, nrow,
                            reinterpret_cast<cx<R> *>(p->Y));
+        // step 2: 8 pairs x 8 angles per thread in FP32, 4 x 4 in FP64 (registers)
+        constexpr int PB = sizeof(R) == 4 ? 8 : 4;
+        const int count = nrow * p->M;
+        hipLaunchKernelGGL((k_vol_step2<R, PB, PB>), dim3((count + 255) / 256, (np + PB - 1) / PB,
+                                                         (p->n_beta + PB - 1) / PB),
+                           dim3(256), 0, s, reinterpret_cast<const cx<R> *>(p->Y), reinterpret_cast<const R *>(p->Vd),
+                           np, p->n_beta, p->HD, MM, count, reinterpret_cast<cx<R> *>(p->Xh));
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = launch_land<R>(p, np, p0, Xf, shmem, s);
         if (e == hipSuccess && (flags & RADSVD_OUT_BEST))

@@ -15,6 +15,8 @@
 // barrier, fetching the next round's rotations while it applies the current.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -37,9 +39,23 @@ __device__ inline double block_sum_1024(double v, double *red) {
     return t;
 }
 
-__global__ __launch_bounds__(1024) void k_jacobi(const double *__restrict__ C, int K, int KP,
-                                                 Rot *__restrict__ log, int max_sweeps,
-                                                 double *__restrict__ U, double *__restrict__ lam) {
+// up to two independent decompositions, one workgroup each
+struct EigJobs {
+    const double *C[2];
+    int K[2];
+    Rot *log[2];
+    double *U[2];
+    double *lam[2];
+};
+
+__global__ __launch_bounds__(1024) void k_jacobi(EigJobs jobs, int max_sweeps) {
+    const int jb = blockIdx.x;
+    const double *__restrict__ C = jobs.C[jb];
+    const int K = jobs.K[jb];
+    const int KP = (K + 1) & ~1;
+    Rot *__restrict__ log = jobs.log[jb];
+    double *__restrict__ U = jobs.U[jb];
+    double *__restrict__ lam = jobs.lam[jb];
     extern __shared__ double sm[];   // phase 1: A [KP][KP+1]; phase 2: V [KP][KP+1]
     __shared__ int sp[kMaxK / 2], sq[kMaxK / 2];
     __shared__ double sc[kMaxK / 2], ss[kMaxK / 2];
@@ -212,15 +228,27 @@ size_t eig_log_bytes(int K) {
     return (size_t)kEigMaxSweeps * (KP - 1) * (KP / 2) * sizeof(Rot);
 }
 
-hipError_t launch_eig_raw(const double *C, int K, void *log, double *U, double *lam, hipStream_t s) {
-    const int KP = (K + 1) & ~1;
-    const size_t shmem = (size_t)KP * (KP + 1) * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void *)k_jacobi,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+hipError_t launch_eig_raw2(int n, const double *const *C, const int *K, void *const *log, double *const *U,
+                           double *const *lam, hipStream_t s) {
+    EigJobs jobs{};
+    int KPmax = 0;
+    for (int i = 0; i < n; ++i) {
+        jobs.C[i] = C[i];
+        jobs.K[i] = K[i];
+        jobs.log[i] = reinterpret_cast<Rot *>(log[i]);
+        jobs.U[i] = U[i];
+        jobs.lam[i] = lam[i];
+        KPmax = std::max(KPmax, (K[i] + 1) & ~1);
+    }
+    const size_t shmem = (size_t)KPmax * (KPmax + 1) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), shmem, s, C, K, KP, reinterpret_cast<Rot *>(log),
-                       kEigMaxSweeps, U, lam);
+    hipLaunchKernelGGL(k_jacobi, dim3(n), dim3(1024), shmem, s, jobs, kEigMaxSweeps);
     return hipGetLastError();
+}
+
+hipError_t launch_eig_raw(const double *C, int K, void *log, double *U, double *lam, hipStream_t s) {
+    return launch_eig_raw2(1, &C, &K, &log, &U, &lam, s);
 }
 
 hipError_t launch_eig(radsvd_plan *p, hipStream_t s) { return launch_eig_raw(p->C, p->K, p->eig_log, p->U, p->lam, s); }

@@ -145,6 +145,9 @@ hipError_t launch_kernel_C(radsvd_plan *p, hipStream_t s);
 hipError_t launch_eig(radsvd_plan *p, hipStream_t s);
 // the same solver on any symmetric K x K FP64 matrix (K <= kMaxK); log of eig_log_bytes(K)
 hipError_t launch_eig_raw(const double *C, int K, void *log, double *U, double *lam, hipStream_t s);
+// n <= 2 independent decompositions in one launch (one workgroup each)
+hipError_t launch_eig_raw2(int n, const double *const *C, const int *K, void *const *log, double *const *U,
+                           double *const *lam, hipStream_t s);
 size_t eig_log_bytes(int K);
 // pairs_generic.hip
 hipError_t launch_pairs_generic(const radsvd_plan *p, int flags, float inv_s2, float *best_score,

@@ -762,24 +762,29 @@ hipError_t prepare_t(radsvd_vol_plan *p, const VolGrid &g, const void *A, const 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int L1 = p->L + 1;
-    if (U_in) {
-        hipLaunchKernelGGL(k_vol_user_mat, dim3(64), dim3(256), 0, s, U_in, p->K, p->HC, p->U, p->lamC);
-    } else {
-        hipLaunchKernelGGL(k_vol_C<R>, dim3(p->K, p->K), dim3(256), 0, s, Bc, p->n_tgt, p->K, p->NC, p->w, p->C);
-        e = hipGetLastError();
-        if (e == hipSuccess) e = launch_eig_raw(p->C, p->K, p->logC, p->U, p->lamC, s);
-    }
-    if (e == hipSuccess) e = hipGetLastError();
+    if (U_in) hipLaunchKernelGGL(k_vol_user_mat, dim3(64), dim3(256), 0, s, U_in, p->K, p->HC, p->U, p->lamC);
+    else hipLaunchKernelGGL(k_vol_C<R>, dim3(p->K, p->K), dim3(256), 0, s, Bc, p->n_tgt, p->K, p->NC, p->w, p->C);
+    if (V_in) hipLaunchKernelGGL(k_vol_user_mat, dim3(64), dim3(256), 0, s, V_in, L1, p->HD, p->V, p->lamD);
+    else hipLaunchKernelGGL(k_vol_D<R>, dim3(L1, L1), dim3(256), 0, s, Bc, p->n_tgt, p->K, p->NC, p->L, p->w, p->D);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (V_in) {
-        hipLaunchKernelGGL(k_vol_user_mat, dim3(64), dim3(256), 0, s, V_in, L1, p->HD, p->V, p->lamD);
-    } else {
-        hipLaunchKernelGGL(k_vol_D<R>, dim3(L1, L1), dim3(256), 0, s, Bc, p->n_tgt, p->K, p->NC, p->L, p->w, p->D);
-        e = hipGetLastError();
-        if (e == hipSuccess) e = launch_eig_raw(p->D, L1, p->logD, p->V, p->lamD, s);
+    {   // the eigendecompositions still to do, in one launch
+        const double *C[2];
+        int K[2];
+        void *log[2];
+        double *U[2], *lam[2];
+        int n = 0;
+        if (!U_in) {
+            C[n] = p->C, K[n] = p->K, log[n] = p->logC, U[n] = p->U, lam[n] = p->lamC;
+            ++n;
+        }
+        if (!V_in) {
+            C[n] = p->D, K[n] = L1, log[n] = p->logD, U[n] = p->V, lam[n] = p->lamD;
+            ++n;
+        }
+        if (n) e = launch_eig_raw2(n, C, K, log, U, lam, s);
+        if (e != hipSuccess) return e;
     }
-    if (e == hipSuccess) e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const int nbx = (p->NC + 255) / 256;
     hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_vol * nbx), p->HC), dim3(256), 0, s, Ac,
                        p->n_vol, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->As));

@@ -571,28 +571,33 @@ def volume_workload(rs, synth, torch, reps=3):
     (real blob volumes standing in for the paper's reconstructions), K = 48
     shells, degrees to L = 48 (M = 97 orders), 97 interior angles,
     H_C = H_D = 16, FP32 plan with the real-volume mode; the general complex
-    mode is timed beside it.  One step = vol_prepare + vol_align(BEST)."""
+    mode and an FP64 plan are timed beside it.  One step = vol_prepare +
+    vol_align(BEST)."""
     from paper_2202_07235_amd import volume as rv
     from synth import volumes as sv
     cfg = sv.vol_config("volume")
     P = sv.make_volume_problem(cfg, 6006)
     A = torch.tensor(P.A, dtype=torch.complex64, device="cuda")
     B = torch.tensor(P.B, dtype=torch.complex64, device="cuda")
+    A64 = torch.tensor(P.A, dtype=torch.complex128, device="cuda")
+    B64 = torch.tensor(P.B, dtype=torch.complex128, device="cuda")
 
-    def make(real):
+    def make(real, fp64=False):
+        if fp64:
+            return rv.VolPlan(A64, B64, P.w, cfg.L, cfg.H_C, cfg.H_D, P.beta, precision="fp64", real=real)
         return rv.VolPlan(A, B, P.w, cfg.L, cfg.H_C, cfg.H_D, P.beta, precision="fp32", real=real)
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
-    def run(real):
-        plan = make(real)
+    def run(real, fp64=False):
+        plan = make(real, fp64)
         plan.align("best")
         torch.cuda.synchronize()
         plan.close()
         prep, al = [], []
         for _ in range(reps):
             ev[0].record()
-            plan = make(real)
+            plan = make(real, fp64)
             ev[1].record()
             plan.align("best")
             ev[2].record()
@@ -603,6 +608,7 @@ def volume_workload(rs, synth, torch, reps=3):
         return prep, al
 
     prep_c, al_c = run(False)
+    prep_64, al_64 = run(True, fp64=True)
     prep, al = run(True)
     n_pairs = cfg.n_vol * cfg.n_tgt
     fl = volume_flops(cfg)
@@ -612,6 +618,8 @@ def volume_workload(rs, synth, torch, reps=3):
            "vol_prepare_ms": min(prep), "vol_align_ms": min(al),
            "complex_mode": {"vol_prepare_ms": min(prep_c), "vol_align_ms": min(al_c),
                             "pairs_per_s": n_pairs / (min(al_c) * 1e-3)},
+           "fp64_real_mode": {"vol_prepare_ms": min(prep_64), "vol_align_ms": min(al_64),
+                              "pairs_per_s": n_pairs / (min(al_64) * 1e-3)},
            "pairs_per_s": n_pairs / t, "pairs_per_s_with_prepare": n_pairs / ((min(al) + min(prep)) * 1e-3),
            "flops_per_pair": fl,
            "roofline": {"bound": "alu", "achieved": n_pairs * fl["algorithmic"] / t / 1e12, "peak": 157.3,

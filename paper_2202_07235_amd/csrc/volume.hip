@@ -18,11 +18,10 @@
 //   k_vol_step2   Xhat(beta) = sum_j [v_j^T d](beta) Y_j for a block of pairs and every
 //                 angle, 8 pairs x 8 angles per thread;
 //   k_vol_land*   one workgroup per (pair, beta): Xhat into LDS, then the 2-D
-//                 transform over the orders (M = 2L + 1 is odd:
-//                 a direct DFT against an LDS twiddle table, as two dense complex
-//                 matrix products on the FP32 matrix cores, or for FP64 plans
-//                 two passes on the vector units), then the best Re X of the
-//                 angle and the FULL write;
+//                 transform over the orders (M = 2L + 1 is odd: a direct DFT
+//                 against an LDS twiddle table, as two dense complex matrix
+//                 products on the matrix cores, FP32 or FP64 as the plan), then
+//                 the best Re X of the angle and the FULL write;
 //   k_vol_best    per pair, the best over the angles.
 #include <math.h>
 
@@ -435,100 +434,46 @@ __device__ void land_epilogue(const cx<R> *S, int MM, cx<R> *Xo, int tid, int nt
     }
 }
 
-// FP64 plans: step 3 on the vector units, four waves; each wave owns whole
-// rows (then whole columns), reads all of one, then overwrites it
+// the 16x16x4 matrix-core product of either precision.  Both take
+// A[l % 16][l / 16] and B[l / 16][l % 16] from lane l; the lane's four results
+// are D rows 4 (l / 16) + r (FP32) or l / 16 + 4 r (FP64), r = 0..3, column l % 16.
 template <typename R>
-__global__ __launch_bounds__(256) void k_vol_land(const cx<R> *__restrict__ Xh, int n_beta, int M, long long p0,
-                                                  int real,
-                                                  cx<R> *__restrict__ Xfull, double *__restrict__ part_val,
-                                                  int32_t *__restrict__ part_idx) {
-    extern __shared__ __align__(16) unsigned char vol_smem[];
-    cx<R> *S = reinterpret_cast<cx<R> *>(vol_smem);   // [M][M]
-    cx<R> *tw = S + M * M;                             // [M]: e^{-2 pi i k / M}
-    __shared__ R rv[4];
-    __shared__ int ri[4], rbad[4];
-    const int ib = blockIdx.x;
-    const long long p = blockIdx.y;
-    const int MM = M * M, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    land_twiddles(tw, M, tid, 256);
-    const int L = M / 2;
-    if (real) {   // X-hat(-m1, -m2) = conj X-hat(m1, m2): the rows m1 < 0 from the rows m1 > 0
-        land_load(Xh + ((size_t)p * n_beta + ib) * (L + 1) * M, (L + 1) * M, S, tid, 256);
-        __syncthreads();
-        for (int i = (L + 1) * M + tid; i < MM; i += 256) {
-            const int im1 = i / M, im2 = i - im1 * M;
-            const cx<R> x = S[(M - im1) * M + (im2 == 0 ? 0 : M - im2)];
-            S[i] = cx<R>{x.re, -x.im};
-        }
-    } else {
-        land_load(Xh + ((size_t)p * n_beta + ib) * MM, MM, S, tid, 256);
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
-    __syncthreads();
-    constexpr int NCH = (kVolMaxM + 63) / 64;
-    for (int pass = 0; pass < 2; ++pass) {
-        const int ld_in = pass == 0 ? 1 : M;      // step between the summed elements
-        for (int line = wv; line < M; line += 4) {
-            const int base = pass == 0 ? line * M : line;
-            cx<R> o[NCH];
-            int idx[NCH];
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                o[c] = cx<R>{0, 0};
-                idx[c] = 0;
-            }
-            for (int e = 0; e < M; ++e) {
-                const cx<R> x = S[base + e * ld_in];
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const int k = lane + 64 * c;
-                    if (k < M) {
-                        const cx<R> t = tw[idx[c]];
-                        o[c].re += x.re * t.re - x.im * t.im;
-                        o[c].im += x.re * t.im + x.im * t.re;
-                        idx[c] += k;
-                        if (idx[c] >= M) idx[c] -= M;
-                    }
-                }
-            }
-            vol_wave_sync();
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int k = lane + 64 * c;
-                if (k < M) S[base + k * ld_in] = o[c];
-            }
-            vol_wave_sync();
-        }
-        __syncthreads();
+    static __device__ __forceinline__ int drow(int lk, int r) { return 4 * lk + r; }
+};
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    if (real) {
-        for (int i = tid; i < MM; i += 256) S[i].im = 0;
-        __syncthreads();
-    }
-    cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
-    land_epilogue<R>(S, MM, Xo, tid, 256, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
-                     part_idx + (size_t)p * n_beta + ib);
-}
+    static __device__ __forceinline__ int drow(int lk, int r) { return lk + 4 * r; }
+};
 
-typedef float vol_f4 __attribute__((ext_vector_type(4)));
-
-// FP32 plans: step 3 as two complex matrix products on the matrix cores,
+// Step 3 as two complex matrix products on the matrix cores,
 // Xrow = S F, then X = F Xrow (F[a][b] = e^{-2 pi i ab / M}, symmetric), each
-// as four real FP32 MFMA 16x16x4 products (re = Sr Fr - Si Fi, im = Sr Fi + Si Fr)
+// as four real MFMA 16x16x4 products (re = Sr Fr - Si Fi, im = Sr Fi + Si Fr)
 // over 16 x 16 output tiles, the order grid padded to NT tiles of 16 by
 // zero operands.  Wave w owns row block w in the first product (column block
 // w in the second): it reads only that block and overwrites it after its
 // last read, so a wave-level fence suffices between read and write.
-// Operand layout of v_mfma_f32_16x16x4f32: lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16], r = 0..3.
-template <int NT>
-__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__restrict__ Xh, int n_beta, int M,
-                                                           long long p0, cx<float> *__restrict__ Xfull,
+// FP32 plans use the FP32 products, FP64 plans the FP64 ones (Mfma<R>).
+template <typename R, int NT>
+__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<R> *__restrict__ Xh, int n_beta, int M,
+                                                           long long p0, cx<R> *__restrict__ Xfull,
                                                            double *__restrict__ part_val,
                                                            int32_t *__restrict__ part_idx) {
     extern __shared__ __align__(16) unsigned char vol_smem[];
-    cx<float> *S = reinterpret_cast<cx<float> *>(vol_smem);   // [M][M]
-    cx<float> *tw = S + M * M;
-    __shared__ float rv[NT];
+    using V4 = typename Mfma<R>::v4;
+    cx<R> *S = reinterpret_cast<cx<R> *>(vol_smem);   // [M][M]
+    cx<R> *tw = S + M * M;
+    __shared__ R rv[NT];
     __shared__ int ri[NT], rbad[NT];
     constexpr int NTHR = 64 * NT;
     const int ib = blockIdx.x;
@@ -540,39 +485,39 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
     const int li = lane & 15, lk = lane >> 4;
     const int ia = wv * 16 + li;   // A row: m1 (first product) or c (second)
     for (int pass = 0; pass < 2; ++pass) {
-        vol_f4 are[NT], aim[NT];
+        V4 are[NT], aim[NT];
         int tix[NT], tst[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            are[t] = vol_f4{0.f, 0.f, 0.f, 0.f};
-            aim[t] = vol_f4{0.f, 0.f, 0.f, 0.f};
+            are[t] = V4{0, 0, 0, 0};
+            aim[t] = V4{0, 0, 0, 0};
             const int j = t * 16 + li;   // B column
             tix[t] = (lk * j) % M;       // (e j) mod M for e = lk
             tst[t] = (4 * j) % M;
         }
         for (int e0 = 0; e0 < M; e0 += 4) {
             const int e = e0 + lk;
-            float xr = 0.f, xi = 0.f;
+            R xr = 0, xi = 0;
             if (e < M && ia < M) {
-                const cx<float> x = pass == 0 ? S[ia * M + e] : S[e * M + ia];
+                const cx<R> x = pass == 0 ? S[ia * M + e] : S[e * M + ia];
                 xr = x.re;
                 xi = x.im;
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int j = t * 16 + li;
-                float fr = 0.f, fi = 0.f;
+                R fr = 0, fi = 0;
                 if (e < M && j < M) {
-                    const cx<float> f = tw[tix[t]];
+                    const cx<R> f = tw[tix[t]];
                     fr = f.re;
                     fi = f.im;
                 }
                 tix[t] += tst[t];
                 if (tix[t] >= M) tix[t] -= M;
-                are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fr, are[t], 0, 0, 0);
-                are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, -fi, are[t], 0, 0, 0);
-                aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fi, aim[t], 0, 0, 0);
-                aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, fr, aim[t], 0, 0, 0);
+                are[t] = Mfma<R>::mma(xr, fr, are[t]);
+                are[t] = Mfma<R>::mma(xi, -fi, are[t]);
+                aim[t] = Mfma<R>::mma(xr, fi, aim[t]);
+                aim[t] = Mfma<R>::mma(xi, fr, aim[t]);
             }
         }
         vol_wave_sync();
@@ -581,9 +526,9 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
             const int j = t * 16 + li;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = wv * 16 + 4 * lk + r;
+                const int i = wv * 16 + Mfma<R>::drow(lk, r);
                 if (i < M && j < M) {
-                    const cx<float> v{are[t][r], aim[t][r]};
+                    const cx<R> v{are[t][r], aim[t][r]};
                     if (pass == 0)
                         S[i * M + j] = v;
                     else
@@ -593,13 +538,13 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
         }
         __syncthreads();
     }
-    cx<float> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
-    land_epilogue<float>(S, MM, Xo, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
+    cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
+    land_epilogue<R>(S, MM, Xo, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
                          part_idx + (size_t)p * n_beta + ib);
 }
 
 
-// FP32 plans of real volumes: X-hat(-m1, -m2) = conj X-hat(m1, m2), so only the
+// Real volumes: X-hat(-m1, -m2) = conj X-hat(m1, m2), so only the
 // rows m1 = 0..L of X-hat are formed, and X is real:
 //   R(m1, k)   = sum_{m2} X-hat(m1, m2) F[m2][k]                      (complex, rows m1 >= 0)
 //   X(m1', k)  = sum_{m1 = 0..L} c(m1) Re[F[m1][m1'] R(m1, k)],  c(0) = 1, c(m1 > 0) = 2.
@@ -608,15 +553,16 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<float> *__re
 // write waits for a workgroup barrier, since every wave reads whole rows.
 // The second: wave w owns column block w (as in the complex kernel), two real
 // MFMA products per tile (re R x re F - im R x im F), over K = L + 1 orders.
-template <int NT>
-__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> *__restrict__ Xh, int n_beta, int M,
-                                                                long long p0, cx<float> *__restrict__ Xfull,
+template <typename R, int NT>
+__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__restrict__ Xh, int n_beta, int M,
+                                                                long long p0, cx<R> *__restrict__ Xfull,
                                                                 double *__restrict__ part_val,
                                                                 int32_t *__restrict__ part_idx) {
     extern __shared__ __align__(16) unsigned char vol_smem[];
-    cx<float> *S = reinterpret_cast<cx<float> *>(vol_smem);   // [M][M]
-    cx<float> *tw = S + M * M;
-    __shared__ float rv[NT];
+    using V4 = typename Mfma<R>::v4;
+    cx<R> *S = reinterpret_cast<cx<R> *>(vol_smem);   // [M][M]
+    cx<R> *tw = S + M * M;
+    __shared__ R rv[NT];
     __shared__ int ri[NT], rbad[NT];
     constexpr int NTHR = 64 * NT;
     constexpr int NRB = (NT * 16 / 2 + 1 + 15) / 16;   // row blocks covering m1 = 0..L, L < 8 NT
@@ -628,20 +574,20 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> 
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
     {   // first product: rows m1 = 0..L, column tile wv
-        vol_f4 are[NRB], aim[NRB];
+        V4 are[NRB], aim[NRB];
 #pragma unroll
         for (int r = 0; r < NRB; ++r) {
-            are[r] = vol_f4{0.f, 0.f, 0.f, 0.f};
-            aim[r] = vol_f4{0.f, 0.f, 0.f, 0.f};
+            are[r] = V4{0, 0, 0, 0};
+            aim[r] = V4{0, 0, 0, 0};
         }
         const int j = wv * 16 + li;
         int tix = (lk * j) % M;
         const int tst = (4 * j) % M;
         for (int e0 = 0; e0 < M; e0 += 4) {
             const int e = e0 + lk;
-            float fr = 0.f, fi = 0.f;
+            R fr = 0, fi = 0;
             if (e < M && j < M) {
-                const cx<float> f = tw[tix];
+                const cx<R> f = tw[tix];
                 fr = f.re;
                 fi = f.im;
             }
@@ -650,16 +596,16 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> 
 #pragma unroll
             for (int r = 0; r < NRB; ++r) {
                 const int row = r * 16 + li;
-                float xr = 0.f, xi = 0.f;
+                R xr = 0, xi = 0;
                 if (e < M && row <= L) {
-                    const cx<float> x = S[row * M + e];
+                    const cx<R> x = S[row * M + e];
                     xr = x.re;
                     xi = x.im;
                 }
-                are[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fr, are[r], 0, 0, 0);
-                are[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, -fi, are[r], 0, 0, 0);
-                aim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fi, aim[r], 0, 0, 0);
-                aim[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, fr, aim[r], 0, 0, 0);
+                are[r] = Mfma<R>::mma(xr, fr, are[r]);
+                are[r] = Mfma<R>::mma(xi, -fi, are[r]);
+                aim[r] = Mfma<R>::mma(xr, fi, aim[r]);
+                aim[r] = Mfma<R>::mma(xi, fr, aim[r]);
             }
         }
         __syncthreads();   // every wave has read its rows
@@ -667,17 +613,17 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> 
         for (int r = 0; r < NRB; ++r)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = r * 16 + 4 * lk + q;
-                if (row <= L && j < M) S[row * M + j] = cx<float>{are[r][q], aim[r][q]};
+                const int row = r * 16 + Mfma<R>::drow(lk, q);
+                if (row <= L && j < M) S[row * M + j] = cx<R>{are[r][q], aim[r][q]};
             }
         __syncthreads();
     }
     {   // second product: column block wv, all rows m1' of the output
-        vol_f4 acc[NT];
+        V4 acc[NT];
         int tix[NT], tst[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            acc[t] = vol_f4{0.f, 0.f, 0.f, 0.f};
+            acc[t] = V4{0, 0, 0, 0};
             const int j = t * 16 + li;
             tix[t] = (lk * j) % M;
             tst[t] = (4 * j) % M;
@@ -685,26 +631,26 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> 
         const int ia = wv * 16 + li;   // column c of R
         for (int e0 = 0; e0 <= L; e0 += 4) {
             const int e = e0 + lk;     // order m1 >= 0
-            float xr = 0.f, xi = 0.f;
+            R xr = 0, xi = 0;
             if (e <= L && ia < M) {
-                const cx<float> x = S[e * M + ia];
-                const float c = e == 0 ? 1.f : 2.f;
+                const cx<R> x = S[e * M + ia];
+                const R c = e == 0 ? R(1) : R(2);
                 xr = c * x.re;
                 xi = -c * x.im;
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const int j = t * 16 + li;
-                float fr = 0.f, fi = 0.f;
+                R fr = 0, fi = 0;
                 if (e <= L && j < M) {
-                    const cx<float> f = tw[tix[t]];
+                    const cx<R> f = tw[tix[t]];
                     fr = f.re;
                     fi = f.im;
                 }
                 tix[t] += tst[t];
                 if (tix[t] >= M) tix[t] -= M;
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr, fr, acc[t], 0, 0, 0);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi, fi, acc[t], 0, 0, 0);
+                acc[t] = Mfma<R>::mma(xr, fr, acc[t]);
+                acc[t] = Mfma<R>::mma(xi, fi, acc[t]);
             }
         }
         vol_wave_sync();
@@ -713,14 +659,14 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<float> 
             const int j = t * 16 + li;   // output row m1'
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int c = wv * 16 + 4 * lk + q;
-                if (c < M && j < M) S[j * M + c] = cx<float>{acc[t][q], 0.f};
+                const int c = wv * 16 + Mfma<R>::drow(lk, q);
+                if (c < M && j < M) S[j * M + c] = cx<R>{acc[t][q], R(0)};
             }
         }
         __syncthreads();
     }
-    cx<float> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
-    land_epilogue<float>(S, MM, Xo, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
+    cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
+    land_epilogue<R>(S, MM, Xo, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
                          part_idx + (size_t)p * n_beta + ib);
 }
 
@@ -796,46 +742,36 @@ hipError_t prepare_t(radsvd_vol_plan *p, const VolGrid &g, const void *A, const 
     return hipGetLastError();
 }
 
-template <int NT>
-hipError_t launch_land_mfma(const radsvd_vol_plan *p, int np, long long p0, cx<float> *Xf, size_t shmem,
-                            hipStream_t s) {
-    const void *fn = p->real ? (const void *)k_vol_land_mfma_real<NT> : (const void *)k_vol_land_mfma<NT>;
+template <typename R, int NT>
+hipError_t launch_land_mfma(const radsvd_vol_plan *p, int np, long long p0, cx<R> *Xf, size_t shmem, hipStream_t s) {
+    const void *fn = p->real ? (const void *)k_vol_land_mfma_real<R, NT> : (const void *)k_vol_land_mfma<R, NT>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
     if (p->real)
-        hipLaunchKernelGGL(k_vol_land_mfma_real<NT>, dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
-                           reinterpret_cast<const cx<float> *>(p->Xh), p->n_beta, p->M, p0, Xf, p->part_val,
-                           p->part_idx);
+        hipLaunchKernelGGL((k_vol_land_mfma_real<R, NT>), dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
+                           reinterpret_cast<const cx<R> *>(p->Xh), p->n_beta, p->M, p0, Xf, p->part_val, p->part_idx);
     else
-        hipLaunchKernelGGL(k_vol_land_mfma<NT>, dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
-                           reinterpret_cast<const cx<float> *>(p->Xh), p->n_beta, p->M, p0, Xf, p->part_val,
-                           p->part_idx);
+        hipLaunchKernelGGL((k_vol_land_mfma<R, NT>), dim3(p->n_beta, np), dim3(64 * NT), shmem, s,
+                           reinterpret_cast<const cx<R> *>(p->Xh), p->n_beta, p->M, p0, Xf, p->part_val, p->part_idx);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_land(const radsvd_vol_plan *p, int np, long long p0, cx<R> *Xf, size_t shmem, hipStream_t s) {
-    if constexpr (sizeof(R) == 4) {
-        switch ((p->M + 15) / 16) {   // tiles of 16 orders; M <= 129
-            case 1: return launch_land_mfma<1>(p, np, p0, Xf, shmem, s);
-            case 2: return launch_land_mfma<2>(p, np, p0, Xf, shmem, s);
-            case 3: return launch_land_mfma<3>(p, np, p0, Xf, shmem, s);
-            case 4: return launch_land_mfma<4>(p, np, p0, Xf, shmem, s);
-            case 5: return launch_land_mfma<5>(p, np, p0, Xf, shmem, s);
-            case 6: return launch_land_mfma<6>(p, np, p0, Xf, shmem, s);
-            case 7: return launch_land_mfma<7>(p, np, p0, Xf, shmem, s);
-            case 8: return launch_land_mfma<8>(p, np, p0, Xf, shmem, s);
-            case 9: return launch_land_mfma<9>(p, np, p0, Xf, shmem, s);
-            default: return hipErrorInvalidValue;
-        }
-    } else {
-        hipError_t e = hipFuncSetAttribute((const void *)k_vol_land<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)shmem);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_vol_land<R>, dim3(p->n_beta, np), dim3(256), shmem, s,
-                           reinterpret_cast<const cx<R> *>(p->Xh), p->n_beta, p->M, p0, p->real, Xf, p->part_val,
-                           p->part_idx);
-        return hipGetLastError();
+    switch ((p->M + 15) / 16) {   // tiles of 16 orders; M <= 129 (FP32), <= 97 (FP64)
+        case 1: return launch_land_mfma<R, 1>(p, np, p0, Xf, shmem, s);
+        case 2: return launch_land_mfma<R, 2>(p, np, p0, Xf, shmem, s);
+        case 3: return launch_land_mfma<R, 3>(p, np, p0, Xf, shmem, s);
+        case 4: return launch_land_mfma<R, 4>(p, np, p0, Xf, shmem, s);
+        case 5: return launch_land_mfma<R, 5>(p, np, p0, Xf, shmem, s);
+        case 6: return launch_land_mfma<R, 6>(p, np, p0, Xf, shmem, s);
+        case 7: return launch_land_mfma<R, 7>(p, np, p0, Xf, shmem, s);
+        default:
+            if constexpr (sizeof(R) == 4) {
+                if ((p->M + 15) / 16 == 8) return launch_land_mfma<R, 8>(p, np, p0, Xf, shmem, s);
+                if ((p->M + 15) / 16 == 9) return launch_land_mfma<R, 9>(p, np, p0, Xf, shmem, s);
+            }
+            return hipErrorInvalidValue;
     }
 }
 

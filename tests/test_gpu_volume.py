@@ -112,6 +112,27 @@ def test_volume_matches_oracle(name, precision, real):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_volume_complex_inputs(precision):
+    """Coefficients that belong to no real volume (independent complex Gaussian
+    entries): X is complex, and the general mode must match the oracle in both
+    parts."""
+    cfg = sv.vol_config("vtiny", n_vol=3, n_tgt=2, L=7, K=5, H_C=4, H_D=6)
+    rng = np.random.default_rng(2150)
+    nc = (cfg.L + 1) ** 2
+    A = rng.standard_normal((cfg.n_vol, cfg.K, nc)) + 1j * rng.standard_normal((cfg.n_vol, cfg.K, nc))
+    B = rng.standard_normal((cfg.n_tgt, cfg.K, nc)) + 1j * rng.standard_normal((cfg.n_tgt, cfg.K, nc))
+    k, w = sv.shell_grid(cfg.k_max, cfg.K)
+    P = sv.VolProblem(cfg, k, w, sv.beta_grid(9), A, B, {})
+    plan, Ah, Bh = _plan(P, precision)
+    out = plan.align("best+full")
+    U, _, V, _ = (t.cpu().numpy() for t in plan.UV())
+    Xo = ov.landscape_all(Ah, Bh, w, U, cfg.H_C, V, cfg.H_D, cfg.L, P.beta)
+    assert np.abs(Xo.imag).max() > 0.1 * np.abs(Xo).max()   # genuinely complex
+    _compare(_host(out["X"]), Xo, TOL[precision], f"complex inputs {precision}")
+    _check_best(out["best_score"].cpu().numpy(), out["best_idx"].cpu().numpy(), Xo, TOL[precision])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_volume_full_rank_equals_direct_sum(precision):
     cfg = sv.vol_config("vtiny", n_vol=3, n_tgt=2)
     P = sv.make_volume_problem(cfg, seed=2100)

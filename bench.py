@@ -62,6 +62,11 @@ def parse():
     ap.add_argument("--summarize-kernel-stats", metavar="CSV",
                     help="summarise a rocprofv3 --kernel-trace --stats kernel_stats.csv of bench.py runs "
                          "(library kernels only) and exit")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="HBM bytes per dispatch of every kernel matching --kernel-regex in two rocprofv3 --pmc "
+                         "runs (FETCH_SIZE, then WRITE_SIZE) made with --copy-probe, scaled by the copy kernel's "
+                         "readings, and exit")
+    ap.add_argument("--kernel-regex", default=None, help="kernel-name pattern for --summarize-traffic")
     ap.add_argument("--kernel-ms", type=float, default=None,
                     help="the pair kernel's duration (from a kernel-trace run), for the derived rates")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -200,6 +205,44 @@ def summarize_counters(dirs, kernel_ms):
     if have("TA_BUSY_avr", "GRBM_GUI_ACTIVE"):
         lines.append(f"  TA busy (TA_BUSY_avr / (GRBM_GUI_ACTIVE / 8 XCDs)): "
                      f"{v['TA_BUSY_avr'] / (v['GRBM_GUI_ACTIVE'] / 8):.3f}")
+    return "\n".join(lines)
+
+
+def summarize_traffic(fetch_dir, write_dir, pattern):
+    """FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of every library kernel whose
+    name matches the pattern, averaged per kernel, as HBM bytes via the scale
+    the same counters give for the 1 GiB copy kernel of --copy-probe."""
+    import collections
+    import re
+    rx = re.compile(pattern)
+    lines = []
+    per = {}
+    scale = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        acc = collections.defaultdict(list)
+        copy = []
+        for r in _counter_rows(d):
+            if r.get("Counter_Name") != name:
+                continue
+            kn, v = r.get("Kernel_Name", ""), float(r["Counter_Value"])
+            if "neg" in kn and "elementwise" in kn:
+                copy.append(v)
+            elif rx.search(kn):
+                short = kn.replace("void ", "").replace("(anonymous namespace)::", "").replace("radsvd::", "")
+                short = short[:short.index("(")] if "(" in short else short
+                acc[short].append(v)
+        if not copy:
+            raise SystemExit(f"{d}: no copy-kernel rows (run with --copy-probe)")
+        scale[name] = COPY_BYTES / (max(copy) * 1024.0)
+        per[name] = acc
+    lines.append(f"copy kernel scale: FETCH_SIZE x {scale['FETCH_SIZE']:.4f}, WRITE_SIZE x {scale['WRITE_SIZE']:.4f}")
+    lines.append(f"{'kernel':56s} {'dispatches':>10s} {'fetch B':>12s} {'write B':>12s}")
+    for k in sorted(set(per["FETCH_SIZE"]) | set(per["WRITE_SIZE"])):
+        f = per["FETCH_SIZE"].get(k, [])
+        w = per["WRITE_SIZE"].get(k, [])
+        fb = sum(f) / len(f) * 1024.0 * scale["FETCH_SIZE"] if f else float("nan")
+        wb = sum(w) / len(w) * 1024.0 * scale["WRITE_SIZE"] if w else float("nan")
+        lines.append(f"{k[:56]:56s} {len(f):10d} {fb:12.4g} {wb:12.4g}")
     return "\n".join(lines)
 
 
@@ -637,6 +680,11 @@ def main():
     if a.summarize_kernel_stats:
         print(summarize_kernel_stats(a.summarize_kernel_stats))
         return 0
+    if a.summarize_traffic:
+        if not a.kernel_regex:
+            raise SystemExit("--summarize-traffic needs --kernel-regex")
+        print(summarize_traffic(*a.summarize_traffic, a.kernel_regex))
+        return 0
     if a.summarize_counters:
         if a.kernel_ms is None:
             raise SystemExit("--summarize-counters needs --kernel-ms")
@@ -654,6 +702,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.only:
+        if a.copy_probe:   # a 1 GiB streaming kernel whose counters calibrate the HBM counters
+            src = torch.randn(COPY_BYTES // 4, device="cuda")
+            torch.neg(src, out=torch.empty_like(src))
+            torch.cuda.synchronize()
+            del src
         fn = {"plain": plain_workload, "batching": batching_workload,
               "differentiation": differentiation_workload, "volume": volume_workload}[a.only]
         print(json.dumps(fn(rs, synth, torch)))

@@ -654,6 +654,21 @@ def volume_workload(rs, synth, torch, reps=3):
     prep_64, al_64 = run(True, fp64=True)
     prep, al = run(True)
     n_pairs = cfg.n_vol * cfg.n_tgt
+    # quality of the compressed landscape against the full sum over shells and
+    # degrees (the measures of the paper's volume example), at several ranks
+    from paper_2202_07235_amd import march
+    full = rv.VolPlan(A, B, P.w, cfg.L, cfg.K, cfg.L + 1, P.beta, precision="fp32", real=True)
+    X_ref = full.align("full")["X"]
+    quality = {}
+    for h in (4, 8, cfg.H_C, 24):
+        pl = rv.VolPlan(A, B, P.w, cfg.L, h, h, P.beta, precision="fp32", real=True)
+        X_est = pl.align("full")["X"]
+        mq = march.landscape_metrics(X_est, X_ref)
+        quality[f"H_C=H_D={h}"] = {"rel_fro": mq["rel_fro"], "corr": mq["corr"], "mean_f": mq["mean_f"]}
+        pl.close()
+        del X_est
+    full.close()
+    del X_ref
     fl = volume_flops(cfg)
     t = min(al) * 1e-3
     res = {"workload": f"volume: {cfg.n_vol} volumes x {cfg.n_tgt} target, K={cfg.K} L={cfg.L} (M={2 * cfg.L + 1}), "
@@ -664,6 +679,7 @@ def volume_workload(rs, synth, torch, reps=3):
            "fp64_real_mode": {"vol_prepare_ms": min(prep_64), "vol_align_ms": min(al_64),
                               "pairs_per_s": n_pairs / (min(al_64) * 1e-3)},
            "pairs_per_s": n_pairs / t, "pairs_per_s_with_prepare": n_pairs / ((min(al) + min(prep)) * 1e-3),
+           "quality_vs_full_rank": quality,
            "flops_per_pair": fl,
            "roofline": {"bound": "alu", "achieved": n_pairs * fl["algorithmic"] / t / 1e12, "peak": 157.3,
                         "unit": "TFLOP/s", "frac": n_pairs * fl["algorithmic"] / t / 1e12 / 157.3,

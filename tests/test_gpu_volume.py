@@ -26,6 +26,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from oracle import volume as ov
 from paper_2202_07235_amd import volume as rv
 from synth import volumes as sv
@@ -249,3 +250,28 @@ def test_volume_paper_shaped_workload(real):
         worst = max(worst, ang)
         assert ang <= 3 * step, (a, ang)
     print(f"worst rotation error {worst:.3f} rad (grid step {step:.3f})")
+
+
+def test_volume_quality_measures():
+    """The quality measures of the paper's volume example (section 4.10: relative
+    Frobenius error, correlation and percentile f of a low-rank landscape against
+    the full sum), computed by the library's metrics kernel on volume landscapes,
+    against the oracle's measures of the same arrays; at full rank they are exact
+    (0, 1, 1)."""
+    from paper_2202_07235_amd import march
+    cfg = sv.vol_config("vsmall", n_vol=8, n_tgt=2)
+    P = sv.make_volume_problem(cfg, seed=2600)
+    full, A, B = _plan(P, "fp32", H_C=cfg.K, H_D=cfg.L + 1, real=True)
+    Xr = full.align("full")["X"]
+    low, _, _ = _plan(P, "fp32", H_C=4, H_D=4, real=True)
+    Xe = low.align("full")["X"]
+    m = march.landscape_metrics(Xe, Xr)
+    n = cfg.n_vol * cfg.n_tgt
+    rel, corr, f = oracle.landscape_metrics(_host(Xe).reshape(n, -1), _host(Xr).reshape(n, -1))
+    assert abs(m["rel_fro"] - rel) <= 1e-9 * max(1.0, rel)
+    assert abs(m["corr"] - corr) <= 1e-9
+    assert np.array_equal(m["f"].cpu().numpy().ravel(), f.astype(np.float32))
+    print(f"rank 4/4 of {cfg.K}/{cfg.L + 1}: rel fro {m['rel_fro']:.3f}, corr {m['corr']:.4f}, mean f {m['mean_f']:.4f}")
+    assert m["rel_fro"] > 0.0
+    same = march.landscape_metrics(Xr, Xr)
+    assert same["rel_fro"] == 0.0 and abs(same["corr"] - 1.0) < 1e-12 and same["mean_f"] == 1.0

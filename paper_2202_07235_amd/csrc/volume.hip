@@ -458,7 +458,8 @@ struct Mfma<double> {
 
 // Step 3 as two complex matrix products on the matrix cores,
 // Xrow = S F, then X = F Xrow (F[a][b] = e^{-2 pi i ab / M}, symmetric), each
-// as four real MFMA 16x16x4 products (re = Sr Fr - Si Fi, im = Sr Fi + Si Fr)
+// as three real MFMA 16x16x4 products (Gauss: k1 = (Sr + Si) Fr, k2 = Sr (Fi - Fr),
+// k3 = Si (Fr + Fi); re = k1 - k3, im = k1 + k2)
 // over 16 x 16 output tiles, the order grid padded to NT tiles of 16 by
 // zero operands.  Wave w owns row block w in the first product (column block
 // w in the second): it reads only that block and overwrites it after its
@@ -485,12 +486,13 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<R> *__restri
     const int li = lane & 15, lk = lane >> 4;
     const int ia = wv * 16 + li;   // A row: m1 (first product) or c (second)
     for (int pass = 0; pass < 2; ++pass) {
-        V4 are[NT], aim[NT];
+        V4 k1[NT], k2[NT], k3[NT];   // Gauss: re = k1 - k3, im = k1 + k2
         int tix[NT], tst[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            are[t] = V4{0, 0, 0, 0};
-            aim[t] = V4{0, 0, 0, 0};
+            k1[t] = V4{0, 0, 0, 0};
+            k2[t] = V4{0, 0, 0, 0};
+            k3[t] = V4{0, 0, 0, 0};
             const int j = t * 16 + li;   // B column
             tix[t] = (lk * j) % M;       // (e j) mod M for e = lk
             tst[t] = (4 * j) % M;
@@ -514,10 +516,10 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<R> *__restri
                 }
                 tix[t] += tst[t];
                 if (tix[t] >= M) tix[t] -= M;
-                are[t] = Mfma<R>::mma(xr, fr, are[t]);
-                are[t] = Mfma<R>::mma(xi, -fi, are[t]);
-                aim[t] = Mfma<R>::mma(xr, fi, aim[t]);
-                aim[t] = Mfma<R>::mma(xi, fr, aim[t]);
+                // (xr + i xi)(fr + i fi) with three products
+                k1[t] = Mfma<R>::mma(xr + xi, fr, k1[t]);
+                k2[t] = Mfma<R>::mma(xr, fi - fr, k2[t]);
+                k3[t] = Mfma<R>::mma(xi, fr + fi, k3[t]);
             }
         }
         vol_wave_sync();
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<R> *__restri
             for (int r = 0; r < 4; ++r) {
                 const int i = wv * 16 + Mfma<R>::drow(lk, r);
                 if (i < M && j < M) {
-                    const cx<R> v{are[t][r], aim[t][r]};
+                    const cx<R> v{k1[t][r] - k3[t][r], k1[t][r] + k2[t][r]};
                     if (pass == 0)
                         S[i * M + j] = v;
                     else
@@ -574,11 +576,12 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
     {   // first product: rows m1 = 0..L, column tile wv
-        V4 are[NRB], aim[NRB];
+        V4 k1[NRB], k2[NRB], k3[NRB];   // Gauss: re = k1 - k3, im = k1 + k2
 #pragma unroll
         for (int r = 0; r < NRB; ++r) {
-            are[r] = V4{0, 0, 0, 0};
-            aim[r] = V4{0, 0, 0, 0};
+            k1[r] = V4{0, 0, 0, 0};
+            k2[r] = V4{0, 0, 0, 0};
+            k3[r] = V4{0, 0, 0, 0};
         }
         const int j = wv * 16 + li;
         int tix = (lk * j) % M;
@@ -602,10 +605,9 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
                     xr = x.re;
                     xi = x.im;
                 }
-                are[r] = Mfma<R>::mma(xr, fr, are[r]);
-                are[r] = Mfma<R>::mma(xi, -fi, are[r]);
-                aim[r] = Mfma<R>::mma(xr, fi, aim[r]);
-                aim[r] = Mfma<R>::mma(xi, fr, aim[r]);
+                k1[r] = Mfma<R>::mma(xr + xi, fr, k1[r]);
+                k2[r] = Mfma<R>::mma(xr, fi - fr, k2[r]);
+                k3[r] = Mfma<R>::mma(xi, fr + fi, k3[r]);
             }
         }
         __syncthreads();   // every wave has read its rows
@@ -614,7 +616,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = r * 16 + Mfma<R>::drow(lk, q);
-                if (row <= L && j < M) S[row * M + j] = cx<R>{are[r][q], aim[r][q]};
+                if (row <= L && j < M) S[row * M + j] = cx<R>{k1[r][q] - k3[r][q], k1[r][q] + k2[r][q]};
             }
         __syncthreads();
     }

@@ -275,3 +275,18 @@ def test_volume_quality_measures():
     assert m["rel_fro"] > 0.0
     same = march.landscape_metrics(Xr, Xr)
     assert same["rel_fro"] == 0.0 and abs(same["corr"] - 1.0) < 1e-12 and same["mean_f"] == 1.0
+
+
+def test_volume_largest_shell_and_angle_counts():
+    """K = 128 shells (the eigensolver's largest matrix) and 256 interior angles,
+    FP64: eigenvalues of C against the oracle's and the landscape of every pair."""
+    cfg = sv.vol_config("vtiny", K=128, L=5, k_max=8.0, n_vol=2, n_tgt=2, n_blobs=6, H_C=12, H_D=5, n_beta=256)
+    P = sv.make_volume_problem(cfg, seed=2700)
+    plan, A, B = _plan(P, "fp64", betas=sv.beta_grid(256), real=True)
+    out = plan.align("best+full")
+    U, lc, V, _ = (t.cpu().numpy() for t in plan.UV())
+    lco = np.linalg.eigvalsh(ov.vol_kernel_C(B, P.w, cfg.L))[::-1]
+    assert np.abs(lc - lco).max() <= 1e-11 * lco[0]
+    Xo = ov.landscape_all(A, B, P.w, U, cfg.H_C, V, cfg.H_D, cfg.L, sv.beta_grid(256))
+    _compare(_host(out["X"]), Xo, 1e-10, "K=128, 256 angles")
+    _check_best(out["best_score"].cpu().numpy(), out["best_idx"].cpu().numpy(), Xo, 1e-10)

@@ -8,7 +8,9 @@
 // full one X_ref, the relative error in the Frobenius norm over the whole
 // array, the correlation over the whole array, and per pair the true
 // percentile f of the approximate alignment: the fraction of the pair's
-// X_ref values (over t and m) that are <= X_ref at the argmax of X_est.
+// X_ref values (over its whole landscape) that are <= X_ref at the argmax of
+// X_est.  A wave per pair for short landscapes, a workgroup per pair for long
+// ones.
 #include <math.h>
 
 #include <algorithm>
@@ -151,6 +153,110 @@ __global__ __launch_bounds__(256) void k_landscape_pair_stats(const R *__restric
     }
 }
 
+// The same per-pair measures for long landscapes (volume landscapes hold
+// n_beta M^2 values per pair, far more than one wave should scan): one
+// 512-thread workgroup per pair, each thread a strided set of indices, the
+// partial results combined in fixed order (lanes by the xor tree, then waves
+// in index order).
+constexpr int kLongStatsThreads = 512;
+constexpr int kLongLandscape = 16384;   // from this length on, a workgroup per pair
+
+template <typename R>
+__global__ __launch_bounds__(kLongStatsThreads) void k_landscape_pair_stats_long(
+    const R *__restrict__ Xe, const R *__restrict__ Xr, long long n_pairs, int len, float *__restrict__ f,
+    double *__restrict__ stats) {
+    constexpr int NW = kLongStatsThreads / 64;
+    __shared__ double sv[NW][6];
+    __shared__ double sb[NW];
+    __shared__ int si[NW], sbad[NW], scnt[NW];
+    __shared__ double sthr;
+    __shared__ int sbad_all;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (long long pair = blockIdx.x; pair < n_pairs; pair += gridDim.x) {
+        const size_t base = (size_t)pair * len;
+        double bv = -INFINITY;
+        int bi = 0x7fffffff;
+        int bad = 0;
+        double sd = 0, srr = 0, se = 0, sr = 0, see = 0, ser = 0;
+        for (int i = tid; i < len; i += kLongStatsThreads) {
+            const double e = re_at(Xe, base + i), r = re_at(Xr, base + i);
+            if (!isfinite(e) || !isfinite(r)) bad = 1;
+            if (e > bv) {
+                bv = e;
+                bi = i;
+            }
+            const double d = e - r;
+            sd += d * d;
+            srr += r * r;
+            se += e;
+            sr += r;
+            see += e * e;
+            ser += e * r;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(bv, o, 64);
+            const int i2 = __shfl_xor(bi, o, 64);
+            if (v2 > bv || (v2 == bv && i2 < bi)) {
+                bv = v2;
+                bi = i2;
+            }
+            bad |= __shfl_xor(bad, o, 64);
+            sd += __shfl_xor(sd, o, 64);
+            srr += __shfl_xor(srr, o, 64);
+            se += __shfl_xor(se, o, 64);
+            sr += __shfl_xor(sr, o, 64);
+            see += __shfl_xor(see, o, 64);
+            ser += __shfl_xor(ser, o, 64);
+        }
+        if (lane == 0) {
+            sb[w] = bv;
+            si[w] = bi;
+            sbad[w] = bad;
+            sv[w][0] = sd;
+            sv[w][1] = srr;
+            sv[w][2] = se;
+            sv[w][3] = sr;
+            sv[w][4] = see;
+            sv[w][5] = ser;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double tv = sb[0];
+            int ti = si[0], tb = sbad[0];
+            double acc[6] = {sv[0][0], sv[0][1], sv[0][2], sv[0][3], sv[0][4], sv[0][5]};
+#pragma unroll 1
+            for (int x = 1; x < NW; ++x) {
+                if (sb[x] > tv || (sb[x] == tv && si[x] < ti)) {
+                    tv = sb[x];
+                    ti = si[x];
+                }
+                tb |= sbad[x];
+                for (int k = 0; k < 6; ++k) acc[k] += sv[x][k];
+            }
+            double *st = stats + 6 * (size_t)pair;
+            for (int k = 0; k < 6; ++k) st[k] = acc[k];
+            sbad_all = tb;
+            sthr = tb ? 0.0 : re_at(Xr, base + ti);
+        }
+        __syncthreads();
+        const int allbad = sbad_all;
+        const double thr = sthr;
+        int cnt = 0;
+        if (!allbad)
+            for (int i = tid; i < len; i += kLongStatsThreads) cnt += re_at(Xr, base + i) <= thr ? 1 : 0;
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (lane == 0) scnt[w] = cnt;
+        __syncthreads();
+        if (tid == 0) {
+            long long c = 0;
+#pragma unroll 1
+            for (int x = 0; x < NW; ++x) c += scnt[x];
+            f[pair] = allbad ? NAN : (float)((double)c / (double)len);
+        }
+        __syncthreads();   // the shared slots are reused by the next pair
+    }
+}
+
 // summary = {relative Frobenius error, correlation, mean f} from the pair sums,
 // reduced in pair order by one workgroup (each thread a contiguous range,
 // then the ranges in thread order)
@@ -188,15 +294,27 @@ hipError_t launch_top_targets(int n_img, int n_tgt, const float *score, int k, i
 
 hipError_t launch_landscape_metrics(long long n_pairs, int len, const void *X_est, const void *X_ref, int fp64,
                                     float *f, double *stats, double *summary, hipStream_t s) {
-    const int blocks = (int)std::min<long long>((n_pairs + 3) / 4, 1 << 20);
-    if (fp64)
-        hipLaunchKernelGGL(k_landscape_pair_stats<double>, dim3(blocks), dim3(256), 0, s,
-                           reinterpret_cast<const double *>(X_est), reinterpret_cast<const double *>(X_ref), n_pairs,
-                           len, f, stats);
-    else
-        hipLaunchKernelGGL(k_landscape_pair_stats<float>, dim3(blocks), dim3(256), 0, s,
-                           reinterpret_cast<const float *>(X_est), reinterpret_cast<const float *>(X_ref), n_pairs,
-                           len, f, stats);
+    if (len >= kLongLandscape) {
+        const int blocks = (int)std::min<long long>(n_pairs, 1 << 20);
+        if (fp64)
+            hipLaunchKernelGGL(k_landscape_pair_stats_long<double>, dim3(blocks), dim3(kLongStatsThreads), 0, s,
+                               reinterpret_cast<const double *>(X_est), reinterpret_cast<const double *>(X_ref),
+                               n_pairs, len, f, stats);
+        else
+            hipLaunchKernelGGL(k_landscape_pair_stats_long<float>, dim3(blocks), dim3(kLongStatsThreads), 0, s,
+                               reinterpret_cast<const float *>(X_est), reinterpret_cast<const float *>(X_ref),
+                               n_pairs, len, f, stats);
+    } else {
+        const int blocks = (int)std::min<long long>((n_pairs + 3) / 4, 1 << 20);
+        if (fp64)
+            hipLaunchKernelGGL(k_landscape_pair_stats<double>, dim3(blocks), dim3(256), 0, s,
+                               reinterpret_cast<const double *>(X_est), reinterpret_cast<const double *>(X_ref),
+                               n_pairs, len, f, stats);
+        else
+            hipLaunchKernelGGL(k_landscape_pair_stats<float>, dim3(blocks), dim3(256), 0, s,
+                               reinterpret_cast<const float *>(X_est), reinterpret_cast<const float *>(X_ref),
+                               n_pairs, len, f, stats);
+    }
     hipLaunchKernelGGL(k_landscape_summary, dim3(1), dim3(256), 0, s, stats, f, n_pairs, len, summary);
     return hipGetLastError();
 }

@@ -275,6 +275,13 @@ def test_volume_quality_measures():
     assert m["rel_fro"] > 0.0
     same = march.landscape_metrics(Xr, Xr)
     assert same["rel_fro"] == 0.0 and abs(same["corr"] - 1.0) < 1e-12 and same["mean_f"] == 1.0
+    # a non-finite value makes that pair's f NaN (landscapes this long take the
+    # workgroup-per-pair kernel)
+    Xn = Xe.clone()
+    Xn[3, 1, 5, 7, 2] = float("nan")
+    mn = march.landscape_metrics(Xn, Xr)
+    fn = mn["f"].cpu().numpy()
+    assert np.isnan(fn[3, 1]) and np.isfinite(np.delete(fn.ravel(), 3 * cfg.n_tgt + 1)).all()
 
 
 def test_volume_largest_shell_and_angle_counts():

@@ -297,3 +297,33 @@ def test_volume_largest_shell_and_angle_counts():
     Xo = ov.landscape_all(A, B, P.w, U, cfg.H_C, V, cfg.H_D, cfg.L, sv.beta_grid(256))
     _compare(_host(out["X"]), Xo, 1e-10, "K=128, 256 angles")
     _check_best(out["best_score"].cpu().numpy(), out["best_idx"].cpu().numpy(), Xo, 1e-10)
+
+
+def test_volume_align_graph_replays():
+    """vol_align launches kernels only (no allocation, no memset), so it can be
+    captured in a HIP graph: three replays, with eager work on the outputs in
+    between, each equal bitwise to the eager call."""
+    cfg = sv.vol_config("vsmall", n_vol=5, n_tgt=2)
+    P = sv.make_volume_problem(cfg, seed=2800)
+    plan, _, _ = _plan(P, "fp32", real=True)
+    ref = plan.align("best+full")
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    outs = {k: torch.empty_like(v) for k, v in ref.items()}
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.align("best+full", outputs=outs)   # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.align("best+full", outputs=outs)
+    for rep in range(3):
+        for v in outs.values():
+            v.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(outs[k], ref[k]), (rep, k)

@@ -66,7 +66,11 @@ def parse():
                     help="HBM bytes per dispatch of every kernel matching --kernel-regex in two rocprofv3 --pmc "
                          "runs (FETCH_SIZE, then WRITE_SIZE) made with --copy-probe, scaled by the copy kernel's "
                          "readings, and exit")
-    ap.add_argument("--kernel-regex", default=None, help="kernel-name pattern for --summarize-traffic")
+    ap.add_argument("--kernel-regex", default=None,
+                    help="kernel-name pattern for --summarize-traffic and --summarize-pmc")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="DIR",
+                    help="per-kernel averages of every counter in rocprofv3 --pmc runs, for the kernels matching "
+                         "--kernel-regex, and exit")
     ap.add_argument("--kernel-ms", type=float, default=None,
                     help="the pair kernel's duration (from a kernel-trace run), for the derived rates")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -243,6 +247,30 @@ def summarize_traffic(fetch_dir, write_dir, pattern):
         fb = sum(f) / len(f) * 1024.0 * scale["FETCH_SIZE"] if f else float("nan")
         wb = sum(w) / len(w) * 1024.0 * scale["WRITE_SIZE"] if w else float("nan")
         lines.append(f"{k[:56]:56s} {len(f):10d} {fb:12.4g} {wb:12.4g}")
+    return "\n".join(lines)
+
+
+def summarize_pmc(dirs, pattern):
+    """Average per dispatch of every counter of every library kernel whose name
+    matches the pattern, in the given rocprofv3 --pmc output folders."""
+    import collections
+    import re
+    rx = re.compile(pattern)
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in dirs:
+        for r in _counter_rows(d):
+            kn = r.get("Kernel_Name", "")
+            if not rx.search(kn):
+                continue
+            short = kn.replace("void ", "").replace("(anonymous namespace)::", "").replace("radsvd::", "")
+            short = short[:short.index("(")] if "(" in short else short
+            acc[short][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = []
+    for k in sorted(acc):
+        lines.append(k)
+        for c in sorted(acc[k]):
+            v = acc[k][c]
+            lines.append(f"  {c:28s} {sum(v) / len(v):.6g}  ({len(v)} dispatches)")
     return "\n".join(lines)
 
 
@@ -695,6 +723,11 @@ def main():
         return 0
     if a.summarize_kernel_stats:
         print(summarize_kernel_stats(a.summarize_kernel_stats))
+        return 0
+    if a.summarize_pmc:
+        if not a.kernel_regex:
+            raise SystemExit("--summarize-pmc needs --kernel-regex")
+        print(summarize_pmc(a.summarize_pmc, a.kernel_regex))
         return 0
     if a.summarize_traffic:
         if not a.kernel_regex:

@@ -392,8 +392,10 @@ typedef struct radsvd_vol_plan radsvd_vol_plan;   /* opaque host metadata */
 /* Workspace bytes for vol_prepare (0 on invalid arguments, see
  * radsvd_last_error).  It holds the kernels, U and V, the principal shells of
  * every volume and target, the principal-degree Wigner tables
- * [n_beta][H_D][M][M] and the per-pair intermediate of steps 1-1b for a
- * block of pairs (at most 1 GiB; vol_align walks the pairs block by block). */
+ * [n_beta][H_D][M][M] and the per-pair intermediates of steps 1, 1b and 2
+ * (sum_l (2l+1)^2 + H_D M^2 + n_beta M^2 complex values per pair) for a block
+ * of pairs (at most 1 GiB together, at least one pair; vol_align walks the
+ * pairs block by block). */
 size_t vol_prepare_workspace(const radsvd_vol_problem *prob, int n_vol, int n_tgt);
 
 /* Precompute (section 4.9, steps 1-7 of the operation count): C and D from

@@ -194,6 +194,13 @@ def test_volume_edges():
     # caller-supplied U, V: eigenvalues reported NaN
     _, lc, _, ld = plan2.UV()
     assert torch.isnan(lc).all() and torch.isnan(ld).all()
+    # only U supplied: V (and its eigenvalues) from the degree kernel, results as before
+    plan3, _, _ = _plan(P, "fp32", U=U[:, :cfg.H_C])
+    out3 = plan3.align("best")
+    _, lc3, V3, ld3 = plan3.UV()
+    assert torch.isnan(lc3).all() and torch.isfinite(ld3).all()
+    assert torch.equal(V3[:, :cfg.H_D], V[:, :cfg.H_D])
+    assert np.array_equal(out3["best_score"].cpu().numpy(), ref["best_score"].cpu().numpy())
 
 
 @pytest.mark.parametrize("L,precision,n_vol,real", [(64, "fp32", 130, False), (48, "fp64", 3, False),

@@ -212,9 +212,62 @@ __global__ __launch_bounds__(256) void k_rings(
 // chunk) rank values, splits them into the plane format and writes 16 (8)
 // bytes per plane and row; an FP32 slot half holds depth k = 8 hc + 4 j + g,
 // j = 0, 1, of one re or im half-chunk hc (8 bytes).
-__device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_tab, int n, int t, int T, int Q,
-                           int H, int Qc, float scale, cx<float> *__restrict__ G, void *__restrict__ F, int f_kind,
-                           int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
+// Row layout of the FP32 ring kernel's transform buffer: two padding values
+// after every 32, so that the FFT's strided radix passes and the emission's
+// reads of digit-reversed positions spread over the LDS banks (pairs j, j + 1
+// with j even stay adjacent and 16-byte aligned), and a row stride of 2 more
+// than a multiple of 32, so that rank rows a few apart fall on other banks.
+__host__ __device__ __forceinline__ int ring_pad(int i) { return i + 2 * (i >> 5); }
+__host__ __device__ __forceinline__ int ring_row_stride(int Q) {
+    const int base = ring_pad(Q - 1) + 1;
+    return base + ((2 - base % 32) + 32) % 32;
+}
+
+// one radix-RAD decimation-in-frequency butterfly of the padded row
+template <int RAD>
+__device__ __forceinline__ void fft_butterfly_pad(cx<float> *row, int base, int span, int k, int tstep,
+                                                  const cx<float> *tw) {
+    cx<float> v[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = row[ring_pad(base + r * span)];
+    dft_small(RAD, v);
+    row[ring_pad(base)] = v[0];
+#pragma unroll
+    for (int p = 1; p < RAD; ++p) row[ring_pad(base + p * span)] = cmul(v[p], tw[k * p * tstep]);   // k p tstep < n
+}
+
+// lds_fft_dif on rows in the padded layout (row stride rs): the same passes,
+// the same output order fft_pos
+__device__ void lds_fft_dif_pad(cx<float> *buf, int cnt, int rs, const FftPlan &pl, const cx<float> *tw) {
+    const int n = pl.n;
+    int L = n;
+    for (int s = 0; s < pl.nst; ++s) {
+        const int rad = pl.rad[s];
+        const int span = L / rad;
+        const int per_seq = n / rad;
+        const int nbf = cnt * per_seq;
+        const int tstep = n / L;
+        const unsigned ms = pl.mag_seq[s], mp = pl.mag_span[s];
+        for (int i = threadIdx.x; i < nbf; i += blockDim.x) {
+            const int sq = fft_div(i, ms);
+            const int bi = i - sq * per_seq;
+            const int blk = fft_div(bi, mp);
+            const int k = bi - blk * span;
+            cx<float> *row = buf + (size_t)sq * rs;
+            const int base = blk * L + k;
+            if (rad == 8) fft_butterfly_pad<8>(row, base, span, k, tstep, tw);
+            else if (rad == 4) fft_butterfly_pad<4>(row, base, span, k, tstep, tw);
+            else if (rad == 2) fft_butterfly_pad<2>(row, base, span, k, tstep, tw);
+            else fft_butterfly_pad<3>(row, base, span, k, tstep, tw);
+        }
+        __syncthreads();
+        L = span;
+    }
+}
+
+__device__ void emit_block(const cx<float> *yb, int rs, int h0, int nr, const int *pos_tab, int n, int t, int T,
+                           int Q, int H, int Qc, float scale, cx<float> *__restrict__ G, void *__restrict__ F,
+                           int f_kind, int f_tile, int f_ntiles, int H8, int nplanes, int is_img) {
     typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
     typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -222,7 +275,7 @@ __device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_t
         cx<float> *Gn = G + ((size_t)n * T + t) * H * Qc;   // [H][Qc]: q fastest
         for (int i = tid; i < Qc * nr; i += nt) {
             const int hh = i / Qc, q = i - hh * Qc;
-            const cx<float> v = yb[hh * Q + pos_tab[q]];
+            const cx<float> v = yb[hh * rs + ring_pad(pos_tab[q])];
             Gn[(size_t)(h0 + hh) * Qc + q] = cx<float>{v.re * scale, v.im * scale};
         }
     }
@@ -237,7 +290,7 @@ __device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_t
     auto val = [&](int h, int pos, int c) -> float {   // c: 0 re, 1 im; zero past the block's rows
         const int hh = h - h0;
         if (hh < 0 || hh >= nr) return 0.f;
-        const cx<float> v = yb[hh * Q + pos];
+        const cx<float> v = yb[hh * rs + ring_pad(pos)];
         return (c ? v.im : v.re) * scale;
     };
     if (f_kind == kFragBF16D || f_kind == kFragF32P) {
@@ -389,8 +442,9 @@ __device__ void emit_block(const cx<float> *yb, int h0, int nr, const int *pos_t
 // (weights Ueta come from global memory; lane r16 is rank row h).  Wave w
 // takes the angle groups w, w + 4, ...  Y is then transformed and written in
 // blocks of 16 rank rows, which keeps LDS small enough for two workgroups per
-// CU.  Workgroups loop over rings; each XCD runs one contiguous range of rings,
-// so the T translations of an item share its samples in one L2.
+// CU; the rows are held in the padded layout of ring_pad.  Workgroups loop
+// over rings; each XCD runs one contiguous range of rings, so the T
+// translations of an item share its samples in one L2.
 template <int NG, bool PHASE, bool TWO>
 __global__ __launch_bounds__(256, 2) void k_rings_mfma(
     const cx<float> *__restrict__ X, int n_real, int T, const cx<float> *__restrict__ phase,
@@ -401,7 +455,8 @@ __global__ __launch_bounds__(256, 2) void k_rings_mfma(
     __shared__ FftPlan spl;           // in LDS: the stage loops index it at run time
     __shared__ int pos_tab[kMaxQ];    // FFT output position of each frequency
     cx<float> *tw = reinterpret_cast<cx<float> *>(smem_raw);   // [Q]
-    cx<float> *ybuf = tw + Q;                                   // [16][Q]
+    cx<float> *ybuf = tw + Q;                                   // [16][RS], padded rows
+    const int RS = ring_row_stride(Q);
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     for (int i = tid; i < Q; i += blockDim.x) {
         double s, c;
@@ -495,7 +550,7 @@ __global__ __launch_bounds__(256, 2) void k_rings_mfma(
                     for (int v = 0; v < 4; ++v) {
                         const int row = 4 * rg + v;
                         if (row < nr)
-                            *reinterpret_cast<f32x4_t *>(ybuf + (size_t)row * Q + j) =
+                            *reinterpret_cast<f32x4_t *>(ybuf + (size_t)row * RS + ring_pad(j)) =
                                 f32x4_t{acc[gi][0][v], acc[gi][1][v], acc[gi][2][v], acc[gi][3][v]};
                     }
                 }
@@ -508,8 +563,8 @@ __global__ __launch_bounds__(256, 2) void k_rings_mfma(
             if (bi == 0) put(acc0, nr);
             else put(acc1, nr);
             __syncthreads();
-            lds_fft_dif(ybuf, nr, Q, pl, tw);
-            emit_block(ybuf, h0, nr, pos_tab, n, t, T, Q, H, Qc, scale, G, F, f_kind, f_tile, f_ntiles, H8, nplanes,
+            lds_fft_dif_pad(ybuf, nr, RS, pl, tw);
+            emit_block(ybuf, RS, h0, nr, pos_tab, n, t, T, Q, H, Qc, scale, G, F, f_kind, f_tile, f_ntiles, H8, nplanes,
                        is_img);
         }
     }
@@ -568,7 +623,7 @@ hipError_t launch_ueta(radsvd_plan *p, const double *U_src, int ld, hipStream_t 
 static hipError_t rings_side_mfma(radsvd_plan *p, const void *X, int n_real, int n_pad, int T, bool use_phase,
                                   void *G, void *F, int f_tile, int is_img, hipStream_t s) {
     const int Q = p->Q;
-    const size_t shmem = (size_t)17 * Q * sizeof(cx<float>);   // twiddles + 16 rows
+    const size_t shmem = (size_t)(Q + 16 * ring_row_stride(Q)) * sizeof(cx<float>);   // twiddles + 16 padded rows
     const int f_kind = is_img ? p->ffmt_a : p->ffmt_b;
     const int nplanes = is_img ? p->nplanes_a : p->nplanes_b;
     const int ng = ((Q + 31) / 32 + 3) / 4;                     // angle groups per wave

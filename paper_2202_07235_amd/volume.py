@@ -16,7 +16,7 @@ import torch
 from . import FP32, FP64, OUT_BEST, OUT_FULL, PRECISIONS, _check, _load, _ptr, _stream
 
 __all__ = ["VolPlan", "vol_prepare_workspace", "vol_prepare", "vol_align", "vol_get_UV", "vol_plan_destroy",
-           "make_vol_problem"]
+           "make_vol_problem", "euler_angles"]
 
 
 class _VolProblem(ctypes.Structure):
@@ -58,6 +58,22 @@ def vol_get_UV(plan, U=None, lamC=None, V=None, lamD=None, stream=None):
 
 def vol_plan_destroy(plan):
     _load().vol_plan_destroy(plan)
+
+
+def euler_angles(best_idx, beta, L: int):
+    """Euler angles (gamma, beta, alpha) of the rotations R_z(alpha) R_y(beta)
+    R_z(gamma) that vol_align's best_idx {ib, m1', m2'} name: alpha = 2 pi m1'/M,
+    gamma = 2 pi m2'/M, M = 2L + 1, beta = beta[ib].  Host arithmetic on the
+    indices only; entries of -1 (pairs without a best) give NaN."""
+    idx = np.asarray(best_idx.cpu() if isinstance(best_idx, torch.Tensor) else best_idx)
+    beta = np.asarray(beta, dtype=np.float64)
+    M = 2 * L + 1
+    ok = idx[..., 0] >= 0
+    ib = np.where(ok, idx[..., 0], 0)
+    alpha = np.where(ok, 2.0 * np.pi * idx[..., 1] / M, np.nan)
+    gamma = np.where(ok, 2.0 * np.pi * idx[..., 2] / M, np.nan)
+    bet = np.where(ok, beta[ib], np.nan)
+    return gamma, bet, alpha
 
 
 class VolPlan:

@@ -163,3 +163,14 @@ def test_volume_workspace_and_argument_errors():
     assert st == 3
     assert lib.vol_align(None, 1, fake, fake, None, None) == 1
     assert lib.vol_get_UV(None, None, None, None, None, None) == 1
+
+
+def test_volume_euler_angles():
+    """best_idx {ib, m1', m2'} -> (gamma, beta, alpha); -1 entries give NaN."""
+    from paper_2202_07235_amd import volume as rv
+    L, beta = 4, np.array([0.0, 0.5, 1.5])
+    M = 2 * L + 1
+    idx = np.array([[[2, 3, 7], [-1, -1, -1]]])
+    g, b, a = rv.euler_angles(idx, beta, L)
+    assert np.allclose([g[0, 0], b[0, 0], a[0, 0]], [2 * np.pi * 7 / M, 1.5, 2 * np.pi * 3 / M])
+    assert np.isnan(g[0, 1]) and np.isnan(b[0, 1]) and np.isnan(a[0, 1])

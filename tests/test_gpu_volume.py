@@ -250,9 +250,9 @@ def test_volume_paper_shaped_workload(real):
     M = 2 * cfg.L + 1
     step = 2 * math.pi / M
     worst = 0.0
+    gam, bet, alp = rv.euler_angles(out["best_idx"], P.beta, cfg.L)
     for a in range(cfg.n_vol):
-        ib, m1, m2 = bi[a, 0]
-        Rb = sv.rotation_matrix(2 * math.pi * m1 / M, P.beta[ib], 2 * math.pi * m2 / M)
+        Rb = sv.rotation_matrix(alp[a, 0], bet[a, 0], gam[a, 0])
         ang = _rot_angle(Rb @ P.truth["rot"][a].T)
         worst = max(worst, ang)
         assert ang <= 3 * step, (a, ang)

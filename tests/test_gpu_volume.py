@@ -334,3 +334,21 @@ def test_volume_align_graph_replays():
         torch.cuda.synchronize()
         for k in ref:
             assert torch.equal(outs[k], ref[k]), (rep, k)
+
+
+def test_volume_block_boundary_inside_a_row():
+    """Several targets per volume with a block-of-pairs boundary inside one
+    volume's row (L = 64, H_D = 65: 90 pairs per block; 14 x 7 pairs split at
+    pair 90 = volume 12, target 6)."""
+    cfg = sv.vol_config("vtiny", K=10, L=64, k_max=32.0, n_vol=14, n_tgt=7, n_blobs=6, H_C=5, H_D=65, n_beta=2)
+    P = sv.make_volume_problem(cfg, seed=2900)
+    betas = np.array([0.7, 2.2])
+    plan, A, B = _plan(P, "fp32", betas=betas, real=True)
+    out = plan.align("best+full")
+    U, _, V, _ = (t.cpu().numpy() for t in plan.UV())
+    pairs = [(12, 4), (12, 5), (12, 6), (13, 0), (0, 0), (13, 6)]
+    Xo = ov.landscape_all(A, B, P.w, U, cfg.H_C, V, cfg.H_D, cfg.L, betas, pairs=pairs)
+    Xg = np.stack([_host(out["X"][a, b]) for a, b in pairs])
+    _compare(Xg[:, None], Xo[:, None], 1e-5, "block boundary inside a row")
+    _check_best(np.array([out["best_score"][a, b].item() for a, b in pairs])[:, None],
+                np.stack([out["best_idx"][a, b].cpu().numpy() for a, b in pairs])[:, None], Xo[:, None], 1e-5)

@@ -43,12 +43,15 @@ struct BwdLayout {
         total;
 };
 
+// tiles of the per-frequency contractions (k_bwd_gBt, k_bwd_gAt)
+constexpr int kGbCB = 1, kGbAT = 16, kGaCB = 4, kGaAT = 8;
+
 // spans of columns of the g_at contraction: enough workgroups to fill the chip,
 // each span at least 256 columns (so the partials stay below Phat / 8)
 int gat_max_split(size_t NBT) { return (int)std::max<size_t>(1, std::min<size_t>(8, NBT / 256)); }
 
 int gat_span(int ca, int Qs, int NBT) {
-    const int nwg = ((ca + 63) / 64) * Qs;
+    const int nwg = ((ca + 64 * kGaCB - 1) / (64 * kGaCB)) * Qs;   // the g_at kernel's images per workgroup
     const int ns = std::max(1, std::min(gat_max_split(NBT), (4096 + nwg - 1) / nwg));
     return ((NBT + ns - 1) / ns + 15) / 16 * 16;
 }
@@ -410,52 +413,93 @@ __global__ __launch_bounds__(256) void k_bwd_kappa(const double *__restrict__ ps
     }
 }
 
-// g_bt[bt][q][h] (+)= sum_{a in chunk} at[a][q][h] Phat[a][q][bt]; one workgroup
-// per (64 columns bt, q); rank h <= 32 in 4 groups of 8 per thread.
-template <typename R>
+// Register blocking of the two per-frequency contractions: a thread keeps CB
+// columns (g_bt) or images (g_at) times HPT ranks h = wave + 4 i, so each rank
+// value it reads from LDS (the same address across the wave) serves CB
+// products and each Phat value HPT of them.  Tiles of AT images (g_bt) or
+// columns (g_at) are fetched into registers while the previous tile is used.
+// Every output is a sum over the chunk's images (g_bt) or the span's columns
+// (g_at) taken in index order.  g_bt runs with CB = 1: its workgroups each
+// reduce over the whole chunk, and with CB = 4 their count (NBT / 256 times
+// Qs) no longer filled the chip evenly (1.51 ms against 1.33 per call at the
+// differentiation workload); g_at with CB = 4 took 1.07 ms against 1.32.
+
+// g_bt[bt][q][h] (+)= sum_{a in chunk} at[a][q][h] kappa[a] Phat[a][q][bt]; one
+// workgroup per (TILE columns bt, q)
+template <typename R, int HPT, int CB, int AT>
 __global__ __launch_bounds__(256) void k_bwd_gBt(const cx<R> *__restrict__ Ag, const cx<double> *__restrict__ Phat,
                                                  const double *__restrict__ kappa, int a0, int na_chunk, int NBT,
                                                  int Qs, int H, int accumulate, cx<double> *__restrict__ gBt) {
-    __shared__ cx<double> sP[16][64];
-    __shared__ cx<double> sA[16][kMaxH];
-    const int q = blockIdx.y, bt0 = blockIdx.x * 64;
+    constexpr int TILE = 64 * CB;
+    __shared__ cx<double> sP[AT][TILE];
+    __shared__ cx<double> sA[AT][kMaxH];
+    const int q = blockIdx.y, bt0 = blockIdx.x * TILE;
     const int tid = threadIdx.x, bl = tid & 63, hg = tid >> 6;
-    cx<double> acc[8];
+    cx<double> acc[CB][HPT];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = cx<double>{0.0, 0.0};
-    for (int c0 = 0; c0 < na_chunk; c0 += 16) {
-        for (int e = tid; e < 16 * 64; e += 256) {
-            const int aa = e >> 6, bb = e & 63;
+    for (int k = 0; k < CB; ++k)
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) acc[k][i] = cx<double>{0.0, 0.0};
+    constexpr int NP = AT * TILE / 256;   // Phat values per thread and tile
+    constexpr int NA = (AT * kMaxH + 255) / 256;   // rank values per thread and tile
+    cx<double> rp[NP], ra[NA];
+    auto fetch = [&](int c0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int e = tid + 256 * j, aa = e / TILE, bb = e % TILE;
             cx<double> v = {0.0, 0.0};
             if (c0 + aa < na_chunk && bt0 + bb < NBT)
                 v = cscale(Phat[((size_t)(c0 + aa) * Qs + q) * NBT + bt0 + bb], kappa[c0 + aa]);
-            sP[aa][bb] = v;
+            rp[j] = v;
         }
-        for (int e = tid; e < 16 * H; e += 256) {
-            const int aa = e / H, h = e - aa * H;
-            cx<double> v = {0.0, 0.0};
-            if (c0 + aa < na_chunk) v = up(Ag[((size_t)(a0 + c0 + aa) * H + h) * Qs + q]);
-            sA[aa][h] = v;
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            const int e = tid + 256 * j, aa = e / H, h = e - aa * H;
+            ra[j] = cx<double>{0.0, 0.0};
+            if (e < AT * H && c0 + aa < na_chunk) ra[j] = up(Ag[((size_t)(a0 + c0 + aa) * H + h) * Qs + q]);
+        }
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < na_chunk; c0 += AT) {
+        __syncthreads();   // the previous tile is consumed
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const int e = tid + 256 * j;
+            sP[e / TILE][e % TILE] = rp[j];
+        }
+#pragma unroll
+        for (int j = 0; j < NA; ++j) {
+            const int e = tid + 256 * j;
+            if (e < AT * H) sA[e / H][e % H] = ra[j];
         }
         __syncthreads();
-        for (int aa = 0; aa < 16; ++aa) {
-            const cx<double> pv = sP[aa][bl];
+        if (c0 + AT < na_chunk) fetch(c0 + AT);
+#pragma unroll 2
+        for (int aa = 0; aa < AT; ++aa) {
+            cx<double> pv[CB];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int k = 0; k < CB; ++k) pv[k] = sP[aa][bl + 64 * k];
+#pragma unroll
+            for (int i = 0; i < HPT; ++i) {
                 const int h = hg + 4 * i;
-                if (h < H) acc[i] = cadd(acc[i], cmul(sA[aa][h], pv));
+                if (h < H) {
+                    const cx<double> av = sA[aa][h];
+#pragma unroll
+                    for (int k = 0; k < CB; ++k) acc[k][i] = cadd(acc[k][i], cmul(av, pv[k]));
+                }
             }
         }
-        __syncthreads();
     }
-    const int bt = bt0 + bl;
-    if (bt < NBT) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+    for (int k = 0; k < CB; ++k) {
+        const int bt = bt0 + bl + 64 * k;
+        if (bt >= NBT) continue;
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
             const int h = hg + 4 * i;
             if (h < H) {
                 cx<double> *o = gBt + ((size_t)bt * Qs + q) * H + h;
-                *o = accumulate ? cadd(*o, acc[i]) : acc[i];
+                *o = accumulate ? cadd(*o, acc[k][i]) : acc[k][i];
             }
         }
     }
@@ -463,73 +507,83 @@ __global__ __launch_bounds__(256) void k_bwd_gBt(const cx<R> *__restrict__ Ag, c
 
 // Partial g_at over one span of columns: part[sp][al][q][h] =
 // sum_{bt in span sp} conj(Phat[al][q][bt]) bt[bt][q][h]; one workgroup per
-// (64 images, q, span).  The next tile of 16 columns is fetched into registers
-// while the current one is used.
-template <typename R>
+// (TILE images, q, span)
+template <typename R, int HPT, int CB, int AT>
 __global__ __launch_bounds__(256) void k_bwd_gAt(const cx<R> *__restrict__ Bg, const cx<double> *__restrict__ Phat,
                                                  int na_chunk, int NBT, int Qs, int H, int span,
                                                  cx<double> *__restrict__ part) {
-    __shared__ cx<double> sP[64][17];
-    __shared__ cx<double> sB[16][kMaxH];
-    const int q = blockIdx.y, al0 = blockIdx.x * 64, sp = blockIdx.z;
+    constexpr int TILE = 64 * CB;
+    __shared__ cx<double> sP[TILE][AT + 1];
+    __shared__ cx<double> sB[AT][kMaxH];
+    const int q = blockIdx.y, al0 = blockIdx.x * TILE, sp = blockIdx.z;
     const int c_begin = sp * span, c_end = min(NBT, c_begin + span);
     const int tid = threadIdx.x, al = tid & 63, hg = tid >> 6;
-    cx<double> acc[8];
+    cx<double> acc[CB][HPT];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) acc[i] = cx<double>{0.0, 0.0};
-    cx<double> rp[4], rb[2];
+    for (int k = 0; k < CB; ++k)
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) acc[k][i] = cx<double>{0.0, 0.0};
+    constexpr int NP = AT * TILE / 256;
+    constexpr int NB = (AT * kMaxH + 255) / 256;   // rank values per thread and tile
+    cx<double> rp[NP], rb[NB];
     auto fetch = [&](int c0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = tid + 256 * k, aa = e >> 4, bb = e & 15;
+        for (int j = 0; j < NP; ++j) {
+            const int e = tid + 256 * j, aa = e / AT, bb = e % AT;
             double vr = 0.0, vi = 0.0;
             if (al0 + aa < na_chunk && c0 + bb < c_end) {
                 const cx<double> *src = Phat + ((size_t)(al0 + aa) * Qs + q) * NBT + c0 + bb;
                 vr = src->re;
                 vi = src->im;
             }
-            rp[k] = cx<double>{vr, vi};
+            rp[j] = cx<double>{vr, vi};
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int e = tid + 256 * k;
-            cx<double> v = {0.0, 0.0};
-            if (e < 16 * H) {
-                const int bb = e / H, h = e - bb * H;
-                if (c0 + bb < c_end) v = up(Bg[((size_t)(c0 + bb) * H + h) * Qs + q]);
-            }
-            rb[k] = v;
+        for (int j = 0; j < NB; ++j) {
+            const int e = tid + 256 * j, bb = e / H, h = e - bb * H;
+            rb[j] = cx<double>{0.0, 0.0};
+            if (e < AT * H && c0 + bb < c_end) rb[j] = up(Bg[((size_t)(c0 + bb) * H + h) * Qs + q]);
         }
     };
     fetch(c_begin);
-    for (int c0 = c_begin; c0 < c_end; c0 += 16) {
+    for (int c0 = c_begin; c0 < c_end; c0 += AT) {
         __syncthreads();   // the previous tile is consumed
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int e = tid + 256 * k;
-            sP[e >> 4][e & 15] = rp[k];
+        for (int j = 0; j < NP; ++j) {
+            const int e = tid + 256 * j;
+            sP[e / AT][e % AT] = rp[j];
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int e = tid + 256 * k;
-            if (e < 16 * H) sB[e / H][e % H] = rb[k];
+        for (int j = 0; j < NB; ++j) {
+            const int e = tid + 256 * j;
+            if (e < AT * H) sB[e / H][e % H] = rb[j];
         }
         __syncthreads();
-        if (c0 + 16 < c_end) fetch(c0 + 16);
-        for (int bb = 0; bb < 16; ++bb) {
-            const cx<double> pv = cconj(sP[al][bb]);
+        if (c0 + AT < c_end) fetch(c0 + AT);
+#pragma unroll 2
+        for (int bb = 0; bb < AT; ++bb) {
+            cx<double> pv[CB];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int k = 0; k < CB; ++k) pv[k] = cconj(sP[al + 64 * k][bb]);
+#pragma unroll
+            for (int i = 0; i < HPT; ++i) {
                 const int h = hg + 4 * i;
-                if (h < H) acc[i] = cadd(acc[i], cmul(pv, sB[bb][h]));
+                if (h < H) {
+                    const cx<double> bv = sB[bb][h];
+#pragma unroll
+                    for (int k = 0; k < CB; ++k) acc[k][i] = cadd(acc[k][i], cmul(pv[k], bv));
+                }
             }
         }
     }
-    if (al0 + al < na_chunk) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+    for (int k = 0; k < CB; ++k) {
+        const int a = al0 + al + 64 * k;
+        if (a >= na_chunk) continue;
+#pragma unroll
+        for (int i = 0; i < HPT; ++i) {
             const int h = hg + 4 * i;
-            if (h < H) part[(((size_t)sp * na_chunk + al0 + al) * Qs + q) * H + h] = acc[i];
+            if (h < H) part[(((size_t)sp * na_chunk + a) * Qs + q) * H + h] = acc[k][i];
         }
     }
 }
@@ -738,12 +792,22 @@ hipError_t run_backward(const radsvd_plan *p, float inv_s2, const float *lse_img
             n_cols = nb;
         }
         hipLaunchKernelGGL(k_bwd_kappa, dim3(ca), dim3(256), 0, s, psum, glse, a0, n_cols, (double)inv_s2, kappa);
-        hipLaunchKernelGGL(k_bwd_gBt<R>, dim3((NBT + 63) / 64, Qs), dim3(256), 0, s, Ag, Phat, kappa, a0, ca, NBT,
-                           Qs, H, a0 > 0 ? 1 : 0, gBt);
+        const dim3 gb((NBT + 64 * kGbCB - 1) / (64 * kGbCB), Qs);
+        if (H <= 16)
+            hipLaunchKernelGGL((k_bwd_gBt<R, 4, kGbCB, kGbAT>), gb, dim3(256), 0, s, Ag, Phat, kappa, a0, ca, NBT, Qs,
+                               H, a0 > 0 ? 1 : 0, gBt);
+        else
+            hipLaunchKernelGGL((k_bwd_gBt<R, 8, kGbCB, kGbAT>), gb, dim3(256), 0, s, Ag, Phat, kappa, a0, ca, NBT, Qs,
+                               H, a0 > 0 ? 1 : 0, gBt);
         if (want_U) {
             const int span = gat_span(ca, Qs, NBT), nsplit = (NBT + span - 1) / span;
-            hipLaunchKernelGGL(k_bwd_gAt<R>, dim3((ca + 63) / 64, Qs, nsplit), dim3(256), 0, s, Bg, Phat, ca, NBT, Qs,
-                               H, span, gApart);
+            const dim3 ga((ca + 64 * kGaCB - 1) / (64 * kGaCB), Qs, nsplit);
+            if (H <= 16)
+                hipLaunchKernelGGL((k_bwd_gAt<R, 4, kGaCB, kGaAT>), ga, dim3(256), 0, s, Bg, Phat, ca, NBT, Qs, H,
+                                   span, gApart);
+            else
+                hipLaunchKernelGGL((k_bwd_gAt<R, 8, kGaCB, kGaAT>), ga, dim3(256), 0, s, Bg, Phat, ca, NBT, Qs, H,
+                                   span, gApart);
             const size_t tot = (size_t)ca * Qs * H;
             const int nblk = (int)std::min<size_t>(4096, (tot + 255) / 256);
             hipLaunchKernelGGL(k_bwd_gAt_reduce, dim3(nblk), dim3(256), 0, s, gApart, kappa, a0, ca, Qs * H, nsplit,

@@ -66,6 +66,25 @@ def test_backward_matches_oracle_gradient(precision, hermitian):
     assert eB <= TOL and eU <= TOL
 
 
+@pytest.mark.parametrize("precision,H", [("fp32", 24), ("fp64", 32)])
+def test_backward_ranks_above_16_match_oracle_gradient(precision, H):
+    """Ranks above 16 take the contraction kernels' wider rank blocking (eight
+    ranks per thread, two rank values per thread and image tile); 5 targets x
+    9 translations leave a partial last tile of columns."""
+    cfg = synth.config("diff_fd", K=32, H=H, n_tgt=5)
+    P, A, B, A_h, B_h, U, s, g = _small(cfg, 90 + H, precision)
+    gB_or, gU_or = oracle.lse_grad(A_h, B_h, U, cfg.H, P.k, P.w, P.delta, s, g)
+    UH = torch.tensor(np.ascontiguousarray(U[:, :cfg.H]))
+    plan = rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision=precision, hermitian=True, U=UH)
+    o = plan.pairs("lse", inv_sigma2=s)
+    gB, gU = plan.backward(s, o["lse_img"], torch.tensor(g, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    eB = _rel(gB.cpu().to(torch.complex128).numpy(), gB_or)
+    eU = _rel(gU.cpu().numpy(), gU_or)
+    print(f"{precision} H={H}: dL/dB rel err {eB:.2e}, dL/dU rel err {eU:.2e}")
+    assert eB <= TOL and eU <= TOL
+
+
 def test_backward_outputs_are_optional_and_consistent():
     cfg = synth.config("diff_fd")
     P, A, B, A_h, B_h, U, s, g = _small(cfg, 5, "fp32")

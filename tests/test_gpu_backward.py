@@ -66,13 +66,14 @@ def test_backward_matches_oracle_gradient(precision, hermitian):
     assert eB <= TOL and eU <= TOL
 
 
-@pytest.mark.parametrize("precision,H", [("fp32", 24), ("fp64", 32)])
-def test_backward_ranks_above_16_match_oracle_gradient(precision, H):
+@pytest.mark.parametrize("precision,H,Q", [("fp32", 24, 64), ("fp64", 32, 64), ("fp32", 16, 128), ("fp64", 16, 256)])
+def test_backward_more_shapes_match_oracle_gradient(precision, H, Q):
     """Ranks above 16 take the contraction kernels' wider rank blocking (eight
-    ranks per thread, two rank values per thread and image tile); 5 targets x
-    9 translations leave a partial last tile of columns."""
-    cfg = synth.config("diff_fd", K=32, H=H, n_tgt=5)
-    P, A, B, A_h, B_h, U, s, g = _small(cfg, 90 + H, precision)
+    ranks per thread, two rank values per thread and image tile); Q = 128 and
+    256 give the P-hat step a last pass over frequencies holding only Q/2;
+    5 targets x 9 translations leave a partial last tile of columns."""
+    cfg = synth.config("diff_fd", K=32, H=H, n_tgt=5, Q=Q)
+    P, A, B, A_h, B_h, U, s, g = _small(cfg, 90 + H + Q, precision)
     gB_or, gU_or = oracle.lse_grad(A_h, B_h, U, cfg.H, P.k, P.w, P.delta, s, g)
     UH = torch.tensor(np.ascontiguousarray(U[:, :cfg.H]))
     plan = rs.Plan(A, B, P.k, P.w, P.delta, cfg.H, precision=precision, hermitian=True, U=UH)
@@ -81,7 +82,7 @@ def test_backward_ranks_above_16_match_oracle_gradient(precision, H):
     torch.cuda.synchronize()
     eB = _rel(gB.cpu().to(torch.complex128).numpy(), gB_or)
     eU = _rel(gU.cpu().numpy(), gU_or)
-    print(f"{precision} H={H}: dL/dB rel err {eB:.2e}, dL/dU rel err {eU:.2e}")
+    print(f"{precision} H={H} Q={Q}: dL/dB rel err {eB:.2e}, dL/dU rel err {eU:.2e}")
     assert eB <= TOL and eU <= TOL
 
 

@@ -388,24 +388,13 @@ __device__ __forceinline__ void land_twiddles(cx<R> *tw, int M, int tid, int nth
     }
 }
 
-// the best Re X of one angle (first maximum in m1' M + m2' order) and the FULL
-// write; rv, ri, rbad hold one entry per wave
+// the best of one angle from each thread's candidate (bv, bi; bad: a NaN seen):
+// first maximum in m1' M + m2' order, NaN if any value is NaN; rv, ri, rbad
+// hold one entry per wave
 template <typename R>
-__device__ void land_epilogue(const cx<R> *S, int MM, cx<R> *Xo, int tid, int nthr, R *rv, int *ri, int *rbad,
-                              double *pv, int32_t *pi) {
+__device__ void land_best_reduce(R bv, int bi, int bad, int tid, int nthr, R *rv, int *ri, int *rbad, double *pv,
+                                 int32_t *pi) {
     const int lane = tid & 63, wv = tid >> 6;
-    R bv = 0;
-    int bi = 0x7fffffff, bad = 0;
-    for (int i = tid; i < MM; i += nthr) {
-        const cx<R> x = S[i];
-        if (Xo) Xo[i] = x;
-        if (isnan(x.re)) {
-            bad = 1;
-        } else if (vol_before(x.re, i, bv, bi)) {
-            bv = x.re;
-            bi = i;
-        }
-    }
     for (int o = 32; o > 0; o >>= 1) {
         const R v2 = __shfl_xor(bv, o, 64);
         const int i2 = __shfl_xor(bi, o, 64);
@@ -432,6 +421,25 @@ __device__ void land_epilogue(const cx<R> *S, int MM, cx<R> *Xo, int tid, int nt
         *pv = (bad || bi == 0x7fffffff) ? __builtin_nan("") : (double)bv;
         *pi = bi;
     }
+}
+
+// the best Re X of one angle held in LDS and the FULL write
+template <typename R>
+__device__ void land_epilogue(const cx<R> *S, int MM, cx<R> *Xo, int tid, int nthr, R *rv, int *ri, int *rbad,
+                              double *pv, int32_t *pi) {
+    R bv = 0;
+    int bi = 0x7fffffff, bad = 0;
+    for (int i = tid; i < MM; i += nthr) {
+        const cx<R> x = S[i];
+        if (Xo) Xo[i] = x;
+        if (isnan(x.re)) {
+            bad = 1;
+        } else if (vol_before(x.re, i, bv, bi)) {
+            bv = x.re;
+            bi = i;
+        }
+    }
+    land_best_reduce<R>(bv, bi, bad, tid, nthr, rv, ri, rbad, pv, pi);
 }
 
 // the 16x16x4 matrix-core product of either precision.  Both take
@@ -555,6 +563,8 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<R> *__restri
 // write waits for a workgroup barrier, since every wave reads whole rows.
 // The second: wave w owns column block w (as in the complex kernel), two real
 // MFMA products per tile (re R x re F - im R x im F), over K = L + 1 orders.
+// The BEST reduction and the FULL write take X from the accumulators, so LDS
+// holds only the L + 1 rows of m1 >= 0 (about half of the complex kernel's).
 template <typename R, int NT>
 __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__restrict__ Xh, int n_beta, int M,
                                                                 long long p0, cx<R> *__restrict__ Xfull,
@@ -562,8 +572,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
                                                                 int32_t *__restrict__ part_idx) {
     extern __shared__ __align__(16) unsigned char vol_smem[];
     using V4 = typename Mfma<R>::v4;
-    cx<R> *S = reinterpret_cast<cx<R> *>(vol_smem);   // [M][M]
-    cx<R> *tw = S + M * M;
+    cx<R> *S = reinterpret_cast<cx<R> *>(vol_smem);   // [L + 1][M]: X-hat, then R, of the orders m1 >= 0
     __shared__ R rv[NT];
     __shared__ int ri[NT], rbad[NT];
     constexpr int NTHR = 64 * NT;
@@ -571,6 +580,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
     const int ib = blockIdx.x;
     const long long p = blockIdx.y;
     const int MM = M * M, L = M / 2, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    cx<R> *tw = S + (L + 1) * M;
     land_twiddles(tw, M, tid, NTHR);
     land_load(Xh + ((size_t)p * n_beta + ib) * (L + 1) * M, (L + 1) * M, S, tid, NTHR);
     __syncthreads();
@@ -655,21 +665,32 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
                 acc[t] = Mfma<R>::mma(xi, fi, acc[t]);
             }
         }
-        vol_wave_sync();
+        // the epilogue from the accumulators: lane values X(m1' = j, m2' = c)
+        cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
+        R bv = 0;
+        int bi = 0x7fffffff, bad = 0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int j = t * 16 + li;   // output row m1'
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int c = wv * 16 + Mfma<R>::drow(lk, q);
-                if (c < M && j < M) S[j * M + c] = cx<R>{acc[t][q], R(0)};
+                if (c < M && j < M) {
+                    const R x = acc[t][q];
+                    const int i = j * M + c;
+                    if (Xo) Xo[i] = cx<R>{x, R(0)};
+                    if (isnan(x)) {
+                        bad = 1;
+                    } else if (vol_before(x, i, bv, bi)) {
+                        bv = x;
+                        bi = i;
+                    }
+                }
             }
         }
-        __syncthreads();
+        land_best_reduce<R>(bv, bi, bad, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
+                            part_idx + (size_t)p * n_beta + ib);
     }
-    cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
-    land_epilogue<R>(S, MM, Xo, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
-                         part_idx + (size_t)p * n_beta + ib);
 }
 
 __global__ void k_vol_best(const double *__restrict__ part_val, const int32_t *__restrict__ part_idx, int n_pairs,
@@ -780,7 +801,8 @@ hipError_t launch_land(const radsvd_vol_plan *p, int np, long long p0, cx<R> *Xf
 template <typename R>
 hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32_t *best_idx, void *X_full,
                    hipStream_t s) {
-    const size_t shmem = (size_t)(p->M * p->M + p->M) * sizeof(cx<R>);
+    // X-hat of one (pair, angle) and the twiddles; real volumes keep only the orders m1 >= 0
+    const size_t shmem = (size_t)((p->real ? (p->L + 1) * p->M : p->M * p->M) + p->M) * sizeof(cx<R>);
     const long long n_pairs = (long long)p->n_vol * p->n_tgt;
     const int MM = p->M * p->M;
     cx<R> *Xf = (flags & RADSVD_OUT_FULL) ? reinterpret_cast<cx<R> *>(X_full) : nullptr;

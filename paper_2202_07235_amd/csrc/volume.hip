@@ -581,11 +581,43 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
     const long long p = blockIdx.y;
     const int MM = M * M, L = M / 2, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     cx<R> *tw = S + (L + 1) * M;
+    cx<R> *scr = tw + M;   // [2][M]: rows formed on the vector units
     land_twiddles(tw, M, tid, NTHR);
     land_load(Xh + ((size_t)p * n_beta + ib) * (L + 1) * M, (L + 1) * M, S, tid, NTHR);
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
     {   // first product: rows m1 = 0..L, column tile wv
+        // One or two rows past the last full block of 16 (L + 1 = 16 n + 1 or
+        // 16 n + 2, as at L = 48) would cost a whole block of matrix-core
+        // products; the vector units form them first, into the scratch rows:
+        // lane (kv, part) sums the orders e = part (mod 4) for column kv, then
+        // the four parts add up.
+        const int nrem = (L + 1) % 16;
+        const bool row_valu = nrem == 1 || nrem == 2;
+        const int nrb_run = row_valu ? (L + 1) / 16 : (L + 16) / 16;   // row blocks on the matrix cores
+        if (row_valu) {
+            const int kv = wv * 16 + (lane >> 2), part = lane & 3;
+            for (int i = 0; i < nrem; ++i) {
+                const int row = 16 * nrb_run + i;
+                R ar = 0, ai = 0;
+                if (kv < M) {
+                    int ix = (part * kv) % M;
+                    const int st = (4 * kv) % M;
+                    for (int e = part; e < M; e += 4) {
+                        const cx<R> x = S[row * M + e], f = tw[ix];
+                        ar += x.re * f.re - x.im * f.im;
+                        ai += x.re * f.im + x.im * f.re;
+                        ix += st;
+                        if (ix >= M) ix -= M;
+                    }
+                }
+                ar += __shfl_xor(ar, 1, 64);
+                ai += __shfl_xor(ai, 1, 64);
+                ar += __shfl_xor(ar, 2, 64);
+                ai += __shfl_xor(ai, 2, 64);
+                if (part == 0 && kv < M) scr[i * M + kv] = cx<R>{ar, ai};
+            }
+        }
         V4 k1[NRB], k2[NRB], k3[NRB];   // Gauss: re = k1 - k3, im = k1 + k2
 #pragma unroll
         for (int r = 0; r < NRB; ++r) {
@@ -608,6 +640,7 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
             if (tix >= M) tix -= M;
 #pragma unroll
             for (int r = 0; r < NRB; ++r) {
+                if (r >= nrb_run) break;   // uniform
                 const int row = r * 16 + li;
                 R xr = 0, xi = 0;
                 if (e < M && row <= L) {
@@ -622,12 +655,16 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
         }
         __syncthreads();   // every wave has read its rows
 #pragma unroll
-        for (int r = 0; r < NRB; ++r)
+        for (int r = 0; r < NRB; ++r) {
+            if (r >= nrb_run) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = r * 16 + Mfma<R>::drow(lk, q);
                 if (row <= L && j < M) S[row * M + j] = cx<R>{k1[r][q] - k3[r][q], k1[r][q] + k2[r][q]};
             }
+        }
+        if (row_valu)
+            for (int i = tid; i < nrem * M; i += NTHR) S[16 * nrb_run * M + i] = scr[i];
         __syncthreads();
     }
     {   // second product: column block wv, all rows m1' of the output
@@ -801,8 +838,9 @@ hipError_t launch_land(const radsvd_vol_plan *p, int np, long long p0, cx<R> *Xf
 template <typename R>
 hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32_t *best_idx, void *X_full,
                    hipStream_t s) {
-    // X-hat of one (pair, angle) and the twiddles; real volumes keep only the orders m1 >= 0
-    const size_t shmem = (size_t)((p->real ? (p->L + 1) * p->M : p->M * p->M) + p->M) * sizeof(cx<R>);
+    // X-hat of one (pair, angle) and the twiddles; real volumes keep only the orders m1 >= 0,
+    // and two scratch rows
+    const size_t shmem = (size_t)((p->real ? (p->L + 3) * p->M : p->M * p->M) + p->M) * sizeof(cx<R>);
     const long long n_pairs = (long long)p->n_vol * p->n_tgt;
     const int MM = p->M * p->M;
     cx<R> *Xf = (flags & RADSVD_OUT_FULL) ? reinterpret_cast<cx<R> *>(X_full) : nullptr;

@@ -227,6 +227,24 @@ def test_volume_largest_degree(L, precision, n_vol, real):
                 TOL[precision])
 
 
+@pytest.mark.parametrize("L,precision", [(15, "fp32"), (17, "fp32"), (20, "fp32"), (17, "fp64")])
+def test_volume_real_row_blocks(L, precision):
+    """Real volumes: the L + 1 rows of the first product in blocks of 16 on the
+    matrix cores, with one or two rows past the last full block on the vector
+    units: 16 rows (one block), 18 (one block and two rows), 21 (two blocks,
+    the second partly masked)."""
+    cfg = sv.vol_config("vtiny", K=6, L=L, k_max=L / 2, n_vol=4, n_tgt=2, n_blobs=6, H_C=6, H_D=8, n_beta=5)
+    P = sv.make_volume_problem(cfg, seed=2600 + L)
+    plan, A, B = _plan(P, precision, real=True)
+    out = plan.align("best+full")
+    U, _, V, _ = (t.cpu().numpy() for t in plan.UV())
+    Xo = ov.landscape_all(A, B, P.w, U, cfg.H_C, V, cfg.H_D, L, P.beta)
+    Xg = _host(out["X"])
+    assert np.all(Xg.imag == 0)
+    _compare(Xg, Xo, TOL[precision], f"real L={L} {precision}")
+    _check_best(out["best_score"].cpu().numpy(), out["best_idx"].cpu().numpy(), Xo, TOL[precision])
+
+
 def _rot_angle(R):
     return math.acos(max(-1.0, min(1.0, (np.trace(R) - 1) / 2)))
 

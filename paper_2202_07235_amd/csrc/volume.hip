@@ -340,12 +340,22 @@ __device__ __forceinline__ bool vol_before(R v, int i, R w, int j) {
 // (count = M^2, or (L+1) M for real volumes: the orders m1 >= 0).  Each thread
 // keeps PB pairs x BB angles of one entry in registers, so every Y value is
 // read by ceil(n_beta / BB) threads and every table value by ceil(np / PB).
+// Workgroups go to the eight XCDs in turn, in launch order: workgroup g serves
+// XCD g % 8, which owns the entries [x span, (x + 1) span) and walks them in
+// sub-blocks of kStep2Sub entries with every (pair block, angle block) of a
+// sub-block launched together, so that its L2 keeps that sub-block's Y and
+// table values (2.4 MB at the volume workload) while they are read again.
+constexpr int kStep2Sub = 128, kXcds = 8;
 template <typename R, int PB, int BB>
-__global__ __launch_bounds__(256) void k_vol_step2(const cx<R> *__restrict__ Y, const R *__restrict__ Vd, int np,
-                                                   int n_beta, int HD, int MM, int count, cx<R> *__restrict__ Xh) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= count) return;
-    const int pa = blockIdx.y * PB, ba = blockIdx.z * BB;
+__global__ __launch_bounds__(kStep2Sub) void k_vol_step2(const cx<R> *__restrict__ Y, const R *__restrict__ Vd,
+                                                         int np, int n_beta, int HD, int MM, int count, int span,
+                                                         int npb, int nbb, cx<R> *__restrict__ Xh) {
+    const int g = blockIdx.x, xcd = g % kXcds, slot = g / kXcds;
+    const int per = npb * nbb, sub = slot / per, rem = slot - sub * per;
+    const int pbk = rem / nbb, bbk = rem - pbk * nbb;
+    const int off = sub * kStep2Sub + threadIdx.x, i = xcd * span + off;
+    if (off >= span || i >= count) return;
+    const int pa = pbk * PB, ba = bbk * BB;
     cx<R> acc[PB][BB];
 #pragma unroll
     for (int a = 0; a < PB; ++a)
@@ -857,10 +867,13 @@ hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32
         // step 2: 8 pairs x 8 angles per thread in FP32, 4 x 4 in FP64 (registers)
         constexpr int PB = sizeof(R) == 4 ? 8 : 4;
         const int count = nrow * p->M;
-        hipLaunchKernelGGL((k_vol_step2<R, PB, PB>), dim3((count + 255) / 256, (np + PB - 1) / PB,
-                                                         (p->n_beta + PB - 1) / PB),
-                           dim3(256), 0, s, reinterpret_cast<const cx<R> *>(p->Y), reinterpret_cast<const R *>(p->Vd),
-                           np, p->n_beta, p->HD, MM, count, reinterpret_cast<cx<R> *>(p->Xh));
+        const int span = (count + kXcds - 1) / kXcds, nsub = (span + kStep2Sub - 1) / kStep2Sub;
+        const int npb = (np + PB - 1) / PB, nbb = (p->n_beta + PB - 1) / PB;
+        const size_t nwg = (size_t)kXcds * nsub * npb * nbb;   // below 2^26 under the 1 GiB block bound
+        if (nwg > 0x7fffffffu) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL((k_vol_step2<R, PB, PB>), dim3((unsigned)nwg), dim3(kStep2Sub), 0, s,
+                           reinterpret_cast<const cx<R> *>(p->Y), reinterpret_cast<const R *>(p->Vd), np, p->n_beta,
+                           p->HD, MM, count, span, npb, nbb, reinterpret_cast<cx<R> *>(p->Xh));
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = launch_land<R>(p, np, p0, Xf, shmem, s);
         if (e == hipSuccess && (flags & RADSVD_OUT_BEST))

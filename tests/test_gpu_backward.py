@@ -66,12 +66,14 @@ def test_backward_matches_oracle_gradient(precision, hermitian):
     assert eB <= TOL and eU <= TOL
 
 
-@pytest.mark.parametrize("precision,H,Q", [("fp32", 24, 64), ("fp64", 32, 64), ("fp32", 16, 128), ("fp64", 16, 256)])
+@pytest.mark.parametrize("precision,H,Q", [("fp32", 24, 64), ("fp64", 32, 64), ("fp32", 16, 128), ("fp64", 16, 256),
+                                           ("fp32", 16, 512)])
 def test_backward_more_shapes_match_oracle_gradient(precision, H, Q):
     """Ranks above 16 take the contraction kernels' wider rank blocking (eight
     ranks per thread, two rank values per thread and image tile); Q = 128 and
-    256 give the P-hat step a last pass over frequencies holding only Q/2;
-    5 targets x 9 translations leave a partial last tile of columns."""
+    256 give the P-hat step a last pass over frequencies holding only Q/2, and
+    Q = 512 is the largest angle count of its wave-per-row kernel; 5 targets x
+    9 translations leave a partial last tile of columns."""
     cfg = synth.config("diff_fd", K=32, H=H, n_tgt=5, Q=Q)
     P, A, B, A_h, B_h, U, s, g = _small(cfg, 90 + H + Q, precision)
     gB_or, gU_or = oracle.lse_grad(A_h, B_h, U, cfg.H, P.k, P.w, P.delta, s, g)

@@ -575,8 +575,14 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<R> *__restri
 // MFMA products per tile (re R x re F - im R x im F), over K = L + 1 orders.
 // The BEST reduction and the FULL write take X from the accumulators, so LDS
 // holds only the L + 1 rows of m1 >= 0 (about half of the complex kernel's).
+// waves per SIMD the real-mode kernel is compiled for at 7 tiles (M = 97 .. 111):
+// LDS holds four FP32 workgroups (28 waves per CU) or two FP64 ones (14), which
+// 72 and 128 VGPRs respectively let run together
 template <typename R, int NT>
-__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__restrict__ Xh, int n_beta, int M,
+constexpr int land_real_waves() { return NT == 7 ? (sizeof(R) == 4 ? 7 : 4) : 1; }
+
+template <typename R, int NT>
+__global__ __launch_bounds__(64 * NT, (land_real_waves<R, NT>())) void k_vol_land_mfma_real(const cx<R> *__restrict__ Xh, int n_beta, int M,
                                                                 long long p0, cx<R> *__restrict__ Xfull,
                                                                 double *__restrict__ part_val,
                                                                 int32_t *__restrict__ part_idx) {
@@ -635,34 +641,36 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
             k2[r] = V4{0, 0, 0, 0};
             k3[r] = V4{0, 0, 0, 0};
         }
+        // Output columns j >= M and rows past L (in a partial last block, whose
+        // reads are clamped to row L) only feed outputs that are never written,
+        // so the loop masks nothing but the orders e >= M of its last step
+        // (their twiddles are zero; the clamped reads stay inside S).
         const int j = wv * 16 + li;
         int tix = (lk * j) % M;
         const int tst = (4 * j) % M;
-        for (int e0 = 0; e0 < M; e0 += 4) {
+        int rowo[NRB];
+#pragma unroll
+        for (int r = 0; r < NRB; ++r) rowo[r] = min(r * 16 + li, L) * M;
+        auto step1 = [&](int e0, bool tail) {
             const int e = e0 + lk;
-            R fr = 0, fi = 0;
-            if (e < M && j < M) {
-                const cx<R> f = tw[tix];
-                fr = f.re;
-                fi = f.im;
-            }
+            cx<R> f = tw[tix];
+            if (tail && e >= M) f = cx<R>{0, 0};
             tix += tst;
             if (tix >= M) tix -= M;
+            const R fr = f.re, fi = f.im, fd = fi - fr, fs = fr + fi;
+            const int ec = tail ? min(e, M - 1) : e;
 #pragma unroll
             for (int r = 0; r < NRB; ++r) {
                 if (r >= nrb_run) break;   // uniform
-                const int row = r * 16 + li;
-                R xr = 0, xi = 0;
-                if (e < M && row <= L) {
-                    const cx<R> x = S[row * M + e];
-                    xr = x.re;
-                    xi = x.im;
-                }
-                k1[r] = Mfma<R>::mma(xr + xi, fr, k1[r]);
-                k2[r] = Mfma<R>::mma(xr, fi - fr, k2[r]);
-                k3[r] = Mfma<R>::mma(xi, fr + fi, k3[r]);
+                const cx<R> x = S[rowo[r] + ec];
+                k1[r] = Mfma<R>::mma(x.re + x.im, fr, k1[r]);
+                k2[r] = Mfma<R>::mma(x.re, fd, k2[r]);
+                k3[r] = Mfma<R>::mma(x.im, fs, k3[r]);
             }
-        }
+        };
+        const int e_main = M & ~3;
+        for (int e0 = 0; e0 < e_main; e0 += 4) step1(e0, false);
+        if (e_main < M) step1(e_main, true);
         __syncthreads();   // every wave has read its rows
 #pragma unroll
         for (int r = 0; r < NRB; ++r) {
@@ -687,31 +695,31 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma_real(const cx<R> *__r
             tix[t] = (lk * j) % M;
             tst[t] = (4 * j) % M;
         }
-        const int ia = wv * 16 + li;   // column c of R
-        for (int e0 = 0; e0 <= L; e0 += 4) {
+        // columns c >= M of R (read clamped to column M - 1) and output rows
+        // m1' >= M are never written; only the orders e > L of the last step
+        // are masked
+        const int iac = min(wv * 16 + li, M - 1);   // column c of R
+        auto step2 = [&](int e0, bool tail) {
             const int e = e0 + lk;     // order m1 >= 0
             R xr = 0, xi = 0;
-            if (e <= L && ia < M) {
-                const cx<R> x = S[e * M + ia];
+            if (!tail || e <= L) {
+                const cx<R> x = S[e * M + iac];
                 const R c = e == 0 ? R(1) : R(2);
                 xr = c * x.re;
                 xi = -c * x.im;
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const int j = t * 16 + li;
-                R fr = 0, fi = 0;
-                if (e <= L && j < M) {
-                    const cx<R> f = tw[tix[t]];
-                    fr = f.re;
-                    fi = f.im;
-                }
+                const cx<R> f = tw[tix[t]];
                 tix[t] += tst[t];
                 if (tix[t] >= M) tix[t] -= M;
-                acc[t] = Mfma<R>::mma(xr, fr, acc[t]);
-                acc[t] = Mfma<R>::mma(xi, fi, acc[t]);
+                acc[t] = Mfma<R>::mma(xr, f.re, acc[t]);
+                acc[t] = Mfma<R>::mma(xi, f.im, acc[t]);
             }
-        }
+        };
+        const int e_main2 = (L + 1) & ~3;
+        for (int e0 = 0; e0 < e_main2; e0 += 4) step2(e0, false);
+        if (e_main2 < L + 1) step2(e_main2, true);
         // the epilogue from the accumulators: lane values X(m1' = j, m2' = c)
         cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
         R bv = 0;

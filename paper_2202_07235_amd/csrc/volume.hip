@@ -477,35 +477,57 @@ struct Mfma<double> {
 // Step 3 as two complex matrix products on the matrix cores,
 // Xrow = S F, then X = F Xrow (F[a][b] = e^{-2 pi i ab / M}, symmetric), each
 // as three real MFMA 16x16x4 products (Gauss: k1 = (Sr + Si) Fr, k2 = Sr (Fi - Fr),
-// k3 = Si (Fr + Fi); re = k1 - k3, im = k1 + k2)
-// over 16 x 16 output tiles, the order grid padded to NT tiles of 16 by
-// zero operands.  Wave w owns row block w in the first product (column block
-// w in the second): it reads only that block and overwrites it after its
-// last read, so a wave-level fence suffices between read and write.
+// k3 = Si (Fr + Fi); re = k1 - k3, im = k1 + k2) over 16 x 16 output tiles of
+// the order grid padded to NT tiles of 16; the twiddle table holds Fr, Fi - Fr
+// and Fr + Fi.  Wave w owns row block w in the first product: it reads only
+// that block and overwrites it after its last read, so a wave-level fence
+// suffices between read and write.  In the second it owns column block w, and
+// the BEST reduction and FULL write take X from its accumulators.
 // FP32 plans use the FP32 products, FP64 plans the FP64 ones (Mfma<R>).
+
+// waves per SIMD the complex-mode kernel is compiled for at 7 tiles: LDS holds
+// two FP32 workgroups (14 waves per CU) or one FP64 one (7)
 template <typename R, int NT>
-__global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<R> *__restrict__ Xh, int n_beta, int M,
-                                                           long long p0, cx<R> *__restrict__ Xfull,
-                                                           double *__restrict__ part_val,
-                                                           int32_t *__restrict__ part_idx) {
+constexpr int land_cx_waves() { return NT == 7 ? (sizeof(R) == 4 ? 4 : 2) : 1; }
+
+// byte offset of the complex kernel's twiddle table: after the M x M landscape,
+// 16-byte aligned
+__host__ __device__ inline size_t land_cx_tw_off(int M, size_t cxb) { return ((size_t)M * M * cxb + 15) & ~(size_t)15; }
+
+template <typename R, int NT>
+__global__ __launch_bounds__(64 * NT, (land_cx_waves<R, NT>())) void k_vol_land_mfma(
+    const cx<R> *__restrict__ Xh, int n_beta, int M, long long p0, cx<R> *__restrict__ Xfull,
+    double *__restrict__ part_val, int32_t *__restrict__ part_idx) {
     extern __shared__ __align__(16) unsigned char vol_smem[];
     using V4 = typename Mfma<R>::v4;
+    struct T3 {   // twiddle entry: the Gauss operands fr, fi - fr, fr + fi
+        R a, b, c;
+    };
     cx<R> *S = reinterpret_cast<cx<R> *>(vol_smem);   // [M][M]
-    cx<R> *tw = S + M * M;
+    T3 *tw = reinterpret_cast<T3 *>(vol_smem + land_cx_tw_off(M, sizeof(cx<R>)));
     __shared__ R rv[NT];
     __shared__ int ri[NT], rbad[NT];
     constexpr int NTHR = 64 * NT;
     const int ib = blockIdx.x;
     const long long p = blockIdx.y;
     const int MM = M * M, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    land_twiddles(tw, M, tid, NTHR);
+    for (int k = tid; k < M; k += NTHR) {
+        double sn, cs;
+        sincospi(-2.0 * (double)k / (double)M, &sn, &cs);
+        const R fr = (R)cs, fi = (R)sn;
+        tw[k] = T3{fr, fi - fr, fr + fi};
+    }
     land_load(Xh + ((size_t)p * n_beta + ib) * MM, MM, S, tid, NTHR);
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
-    const int ia = wv * 16 + li;   // A row: m1 (first product) or c (second)
-    for (int pass = 0; pass < 2; ++pass) {
-        V4 k1[NT], k2[NT], k3[NT];   // Gauss: re = k1 - k3, im = k1 + k2
-        int tix[NT], tst[NT];
+    // A rows m1 (first product) or c (second) past M, read clamped to M - 1, and
+    // B columns past M only feed outputs that are never written: the loops mask
+    // nothing but the orders e >= M of their last step (zero twiddles there)
+    const int iac = min(wv * 16 + li, M - 1);
+    const int e_main = M & ~3;
+    V4 k1[NT], k2[NT], k3[NT];   // Gauss: re = k1 - k3, im = k1 + k2
+    int tix[NT], tst[NT];
+    auto product = [&](bool rows) {   // rows: S F with A = rows of S; else F (S F) with A = columns
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             k1[t] = V4{0, 0, 0, 0};
@@ -515,52 +537,64 @@ __global__ __launch_bounds__(64 * NT) void k_vol_land_mfma(const cx<R> *__restri
             tix[t] = (lk * j) % M;       // (e j) mod M for e = lk
             tst[t] = (4 * j) % M;
         }
-        for (int e0 = 0; e0 < M; e0 += 4) {
+        auto step = [&](int e0, bool tail) {
             const int e = e0 + lk;
-            R xr = 0, xi = 0;
-            if (e < M && ia < M) {
-                const cx<R> x = pass == 0 ? S[ia * M + e] : S[e * M + ia];
-                xr = x.re;
-                xi = x.im;
-            }
+            const int ec = tail ? min(e, M - 1) : e;
+            const cx<R> x = rows ? S[iac * M + ec] : S[ec * M + iac];
+            const R xs = x.re + x.im;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const int j = t * 16 + li;
-                R fr = 0, fi = 0;
-                if (e < M && j < M) {
-                    const cx<R> f = tw[tix[t]];
-                    fr = f.re;
-                    fi = f.im;
-                }
+                T3 f = tw[tix[t]];
+                if (tail && e >= M) f = T3{0, 0, 0};
                 tix[t] += tst[t];
                 if (tix[t] >= M) tix[t] -= M;
                 // (xr + i xi)(fr + i fi) with three products
-                k1[t] = Mfma<R>::mma(xr + xi, fr, k1[t]);
-                k2[t] = Mfma<R>::mma(xr, fi - fr, k2[t]);
-                k3[t] = Mfma<R>::mma(xi, fr + fi, k3[t]);
+                k1[t] = Mfma<R>::mma(xs, f.a, k1[t]);
+                k2[t] = Mfma<R>::mma(x.re, f.b, k2[t]);
+                k3[t] = Mfma<R>::mma(x.im, f.c, k3[t]);
             }
+        };
+        for (int e0 = 0; e0 < e_main; e0 += 4) step(e0, false);
+        if (e_main < M) step(e_main, true);
+    };
+    product(true);
+    vol_wave_sync();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int j = t * 16 + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = wv * 16 + Mfma<R>::drow(lk, r);
+            if (i < M && j < M) S[i * M + j] = cx<R>{k1[t][r] - k3[t][r], k1[t][r] + k2[t][r]};
         }
-        vol_wave_sync();
+    }
+    __syncthreads();
+    product(false);
+    // the epilogue from the accumulators: lane values X(m1' = j, m2' = c)
+    cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
+    R bv = 0;
+    int bi = 0x7fffffff, bad = 0;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int j = t * 16 + li;
+    for (int t = 0; t < NT; ++t) {
+        const int j = t * 16 + li;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = wv * 16 + Mfma<R>::drow(lk, r);
-                if (i < M && j < M) {
-                    const cx<R> v{k1[t][r] - k3[t][r], k1[t][r] + k2[t][r]};
-                    if (pass == 0)
-                        S[i * M + j] = v;
-                    else
-                        S[j * M + i] = v;
+        for (int r = 0; r < 4; ++r) {
+            const int c = wv * 16 + Mfma<R>::drow(lk, r);
+            if (c < M && j < M) {
+                const R xre = k1[t][r] - k3[t][r];
+                const int i = j * M + c;
+                if (Xo) Xo[i] = cx<R>{xre, k1[t][r] + k2[t][r]};
+                if (isnan(xre)) {
+                    bad = 1;
+                } else if (vol_before(xre, i, bv, bi)) {
+                    bv = xre;
+                    bi = i;
                 }
             }
         }
-        __syncthreads();
     }
-    cx<R> *Xo = Xfull ? Xfull + ((size_t)(p0 + p) * n_beta + ib) * MM : nullptr;
-    land_epilogue<R>(S, MM, Xo, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
-                         part_idx + (size_t)p * n_beta + ib);
+    land_best_reduce<R>(bv, bi, bad, tid, NTHR, rv, ri, rbad, part_val + (size_t)p * n_beta + ib,
+                        part_idx + (size_t)p * n_beta + ib);
 }
 
 
@@ -857,8 +891,9 @@ template <typename R>
 hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32_t *best_idx, void *X_full,
                    hipStream_t s) {
     // X-hat of one (pair, angle) and the twiddles; real volumes keep only the orders m1 >= 0,
-    // and two scratch rows
-    const size_t shmem = (size_t)((p->real ? (p->L + 3) * p->M : p->M * p->M) + p->M) * sizeof(cx<R>);
+    // and two scratch rows; the complex kernel's twiddle entries hold three values
+    const size_t shmem = p->real ? (size_t)((p->L + 3) * p->M + p->M) * sizeof(cx<R>)
+                                 : land_cx_tw_off(p->M, sizeof(cx<R>)) + (size_t)p->M * 3 * sizeof(R);
     const long long n_pairs = (long long)p->n_vol * p->n_tgt;
     const int MM = p->M * p->M;
     cx<R> *Xf = (flags & RADSVD_OUT_FULL) ? reinterpret_cast<cx<R> *>(X_full) : nullptr;

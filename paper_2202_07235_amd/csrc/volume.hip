@@ -310,6 +310,8 @@ __global__ __launch_bounds__(256) void k_vol_step1b(const cx<R> *__restrict__ Xt
         R are[kStep1JB], aim[kStep1JB];
 #pragma unroll
         for (int jj = 0; jj < kStep1JB; ++jj) are[jj] = aim[jj] = 0;
+        // four degrees' loads in flight at a time (the loop is latency-bound otherwise)
+#pragma unroll 4
         for (int l = l0; l <= L; ++l) {
             const int n = 2 * l + 1;
             const cx<R> x = Xp[xt_off(l) + (long long)(m1 + l) * n + (m2 + l)];

@@ -235,20 +235,22 @@ constexpr int kXtOut = 8;   // outputs per thread per pass
 
 // step 1, one workgroup per (degree l, pair): Xt_l = As_l^H Bs_l, a
 // (2l+1) x (2l+1) product over the H_C principal shells, with the shells'
-// degree-l blocks staged through LDS kXtH ranks at a time
+// degree-l blocks staged through LDS kXtH ranks at a time; real volumes need
+// only the rows m1 >= 0 (step 1b reads no others), the rest is left unwritten
 template <typename R>
 __global__ __launch_bounds__(256) void k_vol_xt(const cx<R> *__restrict__ As, const cx<R> *__restrict__ Bs,
-                                                int n_tgt, long long p0, int NC, int HC, long long NXT,
+                                                int n_tgt, long long p0, int NC, int HC, long long NXT, int real,
                                                 cx<R> *__restrict__ Xt) {
     __shared__ cx<R> sa[kXtH][2 * kVolMaxL32 + 1], sb[kXtH][2 * kVolMaxL32 + 1];
     const int l = blockIdx.x;
     const long long p = blockIdx.y;
     const long long pg = p0 + p;
     const long long a = pg / n_tgt, b = pg - a * n_tgt;
-    const int n = 2 * l + 1, nn = n * n, base = l * l;
+    const int n = 2 * l + 1, base = l * l;
+    const int r0 = real ? l : 0, nn = (n - r0) * n;   // outputs: rows m1 + l >= r0
     const cx<R> *Aa = As + (size_t)a * HC * NC + base;
     const cx<R> *Bb = Bs + (size_t)b * HC * NC + base;
-    cx<R> *out = Xt + (size_t)p * NXT + xt_off(l);
+    cx<R> *out = Xt + (size_t)p * NXT + xt_off(l) + (size_t)r0 * n;
     for (int o0 = 0; o0 < nn; o0 += 256 * kXtOut) {
         R re[kXtOut], im[kXtOut];
 #pragma unroll
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(256) void k_vol_xt(const cx<R> *__restrict__ As, co
             for (int c = 0; c < kXtOut; ++c) {
                 const int o = o0 + c * 256 + threadIdx.x;
                 if (o < nn) {
-                    const int m1 = o / n, m2 = o - m1 * n;
+                    const int m1 = r0 + o / n, m2 = o % n;
                     for (int h = 0; h < hn; ++h) {
                         const cx<R> u = sa[h][m1], v = sb[h][m2];
                         re[c] += u.re * v.re + u.im * v.im;   // conj(u) v
@@ -903,7 +905,7 @@ hipError_t align_t(const radsvd_vol_plan *p, int flags, float *best_score, int32
         const int np = (int)std::min<long long>(p->chunk, n_pairs - p0);
         const long long NXT = xt_off(p->L + 1);
         hipLaunchKernelGGL(k_vol_xt<R>, dim3(p->L + 1, np), dim3(256), 0, s, reinterpret_cast<const cx<R> *>(p->As),
-                           reinterpret_cast<const cx<R> *>(p->Bs), p->n_tgt, p0, p->NC, p->HC, NXT,
+                           reinterpret_cast<const cx<R> *>(p->Bs), p->n_tgt, p0, p->NC, p->HC, NXT, p->real,
                            reinterpret_cast<cx<R> *>(p->Xt));
         const int nrow = p->real ? p->L + 1 : p->M;
         hipLaunchKernelGGL(k_vol_step1b<R>, dim3((nrow * p->M + 255) / 256, np), dim3(256), 0, s,

@@ -171,11 +171,20 @@ __device__ double wigner_seed(int l, int a, int b, double c, double s) {
 constexpr int kWigJB = 16;   // degree ranks accumulated per recurrence
 
 // thread per (beta, m1, m2) and block of up to kWigJB ranks: one recurrence
-// in l, accumulated into each rank's table
+// in l, accumulated into each rank's table.  The workgroup stages the first
+// HD columns of V in LDS (dynamic, (L + 1) HD doubles); the root
+// sqrt((l^2 - a^2)(l^2 - b^2)) of one step is carried into the next.
 template <typename R>
 __global__ __launch_bounds__(256) void k_vol_wigner(const double *__restrict__ beta, int n_beta, int L, int M,
                                                     const double *__restrict__ V, int HD, int real,
                                                     R *__restrict__ Vd) {
+    extern __shared__ double sVw[];   // [L + 1][HD]
+    const int L1 = L + 1;
+    for (int k = threadIdx.x; k < L1 * HD; k += 256) {
+        const int l = k / HD, j = k - l * HD;
+        sVw[k] = V[(size_t)l * L1 + j];
+    }
+    __syncthreads();
     const long long MM = (long long)M * M;
     const int njb = (HD + kWigJB - 1) / kWigJB;
     const long long total = (long long)n_beta * njb * MM;
@@ -192,12 +201,11 @@ __global__ __launch_bounds__(256) void k_vol_wigner(const double *__restrict__ b
     double sb, cb;
     sincos(0.5 * beta[ib], &sb, &cb);
     const double x = cos(beta[ib]);
-    const int L1 = L + 1;
     double acc[kWigJB];
 #pragma unroll
     for (int jj = 0; jj < kWigJB; ++jj) acc[jj] = 0.0;
     auto add = [&](int l, double d) {
-        const double *v = V + (size_t)l * L1 + jb;
+        const double *v = sVw + l * HD + jb;
 #pragma unroll
         for (int jj = 0; jj < kWigJB; ++jj)
             if (jb + jj < HD) acc[jj] += v[jj] * d;
@@ -212,13 +220,19 @@ __global__ __launch_bounds__(256) void k_vol_wigner(const double *__restrict__ b
         add(1, d);
     }
     const double ab = (double)a * b, a2 = (double)a * a, b2 = (double)b * b;
+    double rt = 0.0;   // sqrt((l^2 - a^2)(l^2 - b^2)) at the current l
+    if (l < L) {
+        const double fl = l;
+        rt = sqrt((fl * fl - a2) * (fl * fl - b2));
+    }
     for (; l < L; ++l) {
         const double fl = l, fl1 = l + 1;
-        const double num = (2.0 * fl + 1.0) * (fl * fl1 * x - ab) * d -
-                           fl1 * sqrt((fl * fl - a2) * (fl * fl - b2)) * dprev;
-        const double den = fl * sqrt((fl1 * fl1 - a2) * (fl1 * fl1 - b2));
+        const double rt1 = sqrt((fl1 * fl1 - a2) * (fl1 * fl1 - b2));
+        const double num = (2.0 * fl + 1.0) * (fl * fl1 * x - ab) * d - fl1 * rt * dprev;
+        const double den = fl * rt1;
         dprev = d;
         d = num / den;
+        rt = rt1;
         add(l + 1, d);
     }
     R *out = Vd + ((size_t)ib * HD + jb) * MM + el;
@@ -853,7 +867,8 @@ hipError_t prepare_t(radsvd_vol_plan *p, const VolGrid &g, const void *A, const 
     hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_tgt * nbx), p->HC), dim3(256), 0, s, Bc,
                        p->n_tgt, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->Bs));
     const long long nvd = (long long)p->n_beta * ((p->HD + kWigJB - 1) / kWigJB) * p->M * p->M;
-    hipLaunchKernelGGL(k_vol_wigner<R>, dim3((unsigned)((nvd + 255) / 256)), dim3(256), 0, s, p->beta,
+    hipLaunchKernelGGL(k_vol_wigner<R>, dim3((unsigned)((nvd + 255) / 256)), dim3(256),
+                       (size_t)(p->L + 1) * p->HD * sizeof(double), s, p->beta,
                        p->n_beta, p->L, p->M, p->V, p->HD, p->real, reinterpret_cast<R *>(p->Vd));
     return hipGetLastError();
 }

@@ -116,23 +116,41 @@ __global__ void k_vol_user_mat(const double *__restrict__ Uin, int n, int H, dou
         lam[i] = __builtin_nan("");
 }
 
+// principal shells, thread per (volume, coefficient) and block of up to
+// kShellHB ranks: each volume value is read once per rank block; the weights
+// U[r][h] sqrt(w_r) are staged in LDS (dynamic, K kShellHB doubles)
+constexpr int kShellHB = 16;
 template <typename R>
 __global__ __launch_bounds__(256) void k_vol_shells(const cx<R> *__restrict__ X, int n, int K, int NC,
                                                     const double *__restrict__ U, int H,
                                                     const double *__restrict__ w, cx<R> *__restrict__ out) {
+    extern __shared__ double sUw[];   // [K][kShellHB]
+    const int h0 = blockIdx.y * kShellHB;
+    for (int k = threadIdx.x; k < K * kShellHB; k += 256) {
+        const int r = k / kShellHB, hh = k - r * kShellHB;
+        sUw[k] = h0 + hh < H ? U[(size_t)r * K + h0 + hh] * sqrt(w[r]) : 0.0;
+    }
+    __syncthreads();
     const int nbx = (NC + 255) / 256;
     const long long v = blockIdx.x / nbx;
     const int i = (int)(blockIdx.x - v * nbx) * 256 + threadIdx.x;
-    const int h = blockIdx.y;
     if (i >= NC) return;
-    double re = 0.0, im = 0.0;
+    double re[kShellHB], im[kShellHB];
+#pragma unroll
+    for (int hh = 0; hh < kShellHB; ++hh) re[hh] = im[hh] = 0.0;
     for (int r = 0; r < K; ++r) {
-        const double u = U[(size_t)r * K + h] * sqrt(w[r]);
         const cx<R> x = X[((size_t)v * K + r) * NC + i];
-        re += u * (double)x.re;
-        im += u * (double)x.im;
+        const double xr = (double)x.re, xi = (double)x.im;
+#pragma unroll
+        for (int hh = 0; hh < kShellHB; ++hh) {
+            const double u = sUw[r * kShellHB + hh];
+            re[hh] += u * xr;
+            im[hh] += u * xi;
+        }
     }
-    out[((size_t)v * H + h) * NC + i] = cx<R>{(R)re, (R)im};
+#pragma unroll
+    for (int hh = 0; hh < kShellHB; ++hh)
+        if (h0 + hh < H) out[((size_t)v * H + h0 + hh) * NC + i] = cx<R>{(R)re[hh], (R)im[hh]};
 }
 
 // d^l_{ab}(beta) at l = max(|a|, |b|), from c = cos(beta/2), s = sin(beta/2):
@@ -862,10 +880,12 @@ hipError_t prepare_t(radsvd_vol_plan *p, const VolGrid &g, const void *A, const 
         if (e != hipSuccess) return e;
     }
     const int nbx = (p->NC + 255) / 256;
-    hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_vol * nbx), p->HC), dim3(256), 0, s, Ac,
-                       p->n_vol, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->As));
-    hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_tgt * nbx), p->HC), dim3(256), 0, s, Bc,
-                       p->n_tgt, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->Bs));
+    const int nhb = (p->HC + kShellHB - 1) / kShellHB;
+    const size_t sh_shells = (size_t)p->K * kShellHB * sizeof(double);
+    hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_vol * nbx), nhb), dim3(256), sh_shells, s,
+                       Ac, p->n_vol, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->As));
+    hipLaunchKernelGGL(k_vol_shells<R>, dim3((unsigned)((long long)p->n_tgt * nbx), nhb), dim3(256), sh_shells, s,
+                       Bc, p->n_tgt, p->K, p->NC, p->U, p->HC, p->w, reinterpret_cast<cx<R> *>(p->Bs));
     const long long nvd = (long long)p->n_beta * ((p->HD + kWigJB - 1) / kWigJB) * p->M * p->M;
     hipLaunchKernelGGL(k_vol_wigner<R>, dim3((unsigned)((nvd + 255) / 256)), dim3(256),
                        (size_t)(p->L + 1) * p->HD * sizeof(double), s, p->beta,

@@ -44,7 +44,7 @@ struct BwdLayout {
 };
 
 // tiles of the per-frequency contractions (k_bwd_gBt, k_bwd_gAt)
-constexpr int kGbCB = 1, kGbAT = 16, kGaCB = 4, kGaAT = 8;
+constexpr int kGbCB = 2, kGbAT = 8, kGaCB = 4, kGaAT = 8;
 
 // spans of columns of the g_at contraction: enough workgroups to fill the chip,
 // each span at least 256 columns (so the partials stay below Phat / 8)
@@ -419,10 +419,11 @@ __global__ __launch_bounds__(256) void k_bwd_kappa(const double *__restrict__ ps
 // products and each Phat value HPT of them.  Tiles of AT images (g_bt) or
 // columns (g_at) are fetched into registers while the previous tile is used.
 // Every output is a sum over the chunk's images (g_bt) or the span's columns
-// (g_at) taken in index order.  g_bt runs with CB = 1: its workgroups each
+// (g_at) taken in index order.  g_bt runs with CB = 2: its workgroups each
 // reduce over the whole chunk, and with CB = 4 their count (NBT / 256 times
 // Qs) no longer filled the chip evenly (1.51 ms against 1.33 per call at the
-// differentiation workload); g_at with CB = 4 took 1.07 ms against 1.32.
+// differentiation workload; CB = 2 with tiles of 8 images took the backward
+// from 22.6 to 22.3 ms); g_at with CB = 4 took 1.07 ms against 1.32.
 
 // g_bt[bt][q][h] (+)= sum_{a in chunk} at[a][q][h] kappa[a] Phat[a][q][bt]; one
 // workgroup per (TILE columns bt, q)
